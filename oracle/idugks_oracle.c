@@ -47,6 +47,16 @@
 enum { F_INTERIOR = 0, F_SELF = 1, F_WALL = 2, F_FAR = 3 };
 enum { BC_WALL = 0, BC_FAR = 1, BC_PERIODIC = 2 };
 
+/* Normal particle speed xi.n at a face.  The upwind side is undefined for velocities
+   tangent to the face; a velocity whose normal speed is below 1e-12 of its speed counts as
+   tangent (normal speed exactly 0), so that the tie rules below do not depend on the
+   rounding of face normals. */
+static double normal_speed(double x, double y, double nx, double ny)
+{
+    double un = x * nx + y * ny;
+    return fabs(un) <= 1e-12 * (fabs(x) + fabs(y)) ? 0.0 : un;
+}
+
 static _Thread_local char g_err[512];
 
 static int fail(int code, const char *msg)
@@ -748,7 +758,7 @@ int orc_create(const orc_config *cfg, orc_problem **out)
         const double *g = p->gw + (size_t)p->fside[k] * nv;
         double den = 0.0;
         for (int v = 0; v < nv; ++v) {
-            double un = p->xi[v] * p->fnx[k] + p->eta[v] * p->fny[k];
+            double un = normal_speed(p->xi[v], p->eta[v], p->fnx[k], p->fny[k]);
             if (un < 0) den += p->w[v] * un * g[v];
         }
         p->wden[k] = den;
@@ -922,7 +932,7 @@ static void face_fluxes(orc_problem *p)
             double *bG = fb, *bH = fb + nv;
             double num = 0.0;
             for (int v = 0; v < nv; ++v) {
-                double x = p->xi[v], y = p->eta[v], un = x * nx + y * ny;
+                double x = p->xi[v], y = p->eta[v], un = normal_speed(x, y, nx, ny);
                 int u;
                 double dx, dy;
                 if (un > 0 || type != F_INTERIOR) {
@@ -946,7 +956,7 @@ static void face_fluxes(orc_problem *p)
                 const double *g = p->gw + (size_t)side * nv;
                 rho_w = -num / p->wden[k];
                 for (int v = 0; v < nv; ++v) {
-                    double un = p->xi[v] * nx + p->eta[v] * ny;
+                    double un = normal_speed(p->xi[v], p->eta[v], nx, ny);
                     if (un <= 0) {
                         bG[v] = rho_w * g[v];
                         bH[v] = rho_w * K * p->wall_RT[side] * g[v];
@@ -954,7 +964,7 @@ static void face_fluxes(orc_problem *p)
                 }
             } else if (type == F_FAR) {
                 for (int v = 0; v < nv; ++v) {
-                    double un = p->xi[v] * nx + p->eta[v] * ny;
+                    double un = normal_speed(p->xi[v], p->eta[v], nx, ny);
                     if (un < 0) {
                         bG[v] = p->ginf[v];
                         bH[v] = p->hinf[v];
@@ -972,7 +982,7 @@ static void face_fluxes(orc_problem *p)
             }
             equilibrium(p, Wk, qk, fe, fe + nv);
             for (int v = 0; v < nv; ++v) {
-                double un = p->xi[v] * nx + p->eta[v] * ny;
+                double un = normal_speed(p->xi[v], p->eta[v], nx, ny);
                 double pg = (t2 * bG[v] + h * fe[v]) / (t2 + h);
                 double ph = (t2 * bH[v] + h * fe[nv + v]) / (t2 + h);
                 FG[v] = p->fS[k] * un * pg;
@@ -1253,7 +1263,7 @@ static double micro_diag(const orc_problem *p, int c, int v)
     for (int side = 0; side < 4; ++side) {
         int m = 4 * c + side, k = p->cf[m];
         if (p->ftype[k] == F_SELF) continue;
-        double un = x * p->onx[m] + y * p->ony[m];
+        double un = normal_speed(x, y, p->onx[m], p->ony[m]);
         if (un > 0) D += un * p->sS[m];
     }
     return D + 2.0 * p->area[c] / (2.0 * p->taust[c] + p->dt);
@@ -1265,7 +1275,7 @@ static double micro_coupling(const orc_problem *p, int c, int side, int v)
 {
     int m = 4 * c + side, k = p->cf[m];
     if (p->ftype[k] == F_SELF || p->nb[m] < 0) return 0.0;
-    double un = p->xi[v] * p->onx[m] + p->eta[v] * p->ony[m];
+    double un = normal_speed(p->xi[v], p->eta[v], p->onx[m], p->ony[m]);
     return un < 0 ? -un * p->sS[m] : 0.0;
 }
 
@@ -1300,7 +1310,7 @@ static void sweep_upper(const orc_problem *p, int v, double *d, int stride, cons
             for (int side = 0; side < 4; ++side) {
                 int m = 4 * c + side, k = p->cf[m];
                 if (p->ftype[k] != F_WALL) continue;
-                double un = p->xi[v] * p->onx[m] + p->eta[v] * p->ony[m];
+                double un = normal_speed(p->xi[v], p->eta[v], p->onx[m], p->ony[m]);
                 if (un < 0) {
                     int ws = p->fside[k];
                     double in = -un * p->sS[m] * drho[k] * p->gw[(size_t)ws * p->nv + v];
@@ -1321,7 +1331,7 @@ static void wall_ghost(orc_problem *p)
         int c = p->fL[k];
         double num = 0.0;
         for (int v = 0; v < nv; ++v) {
-            double un = p->xi[v] * p->fnx[k] + p->eta[v] * p->fny[k];
+            double un = normal_speed(p->xi[v], p->eta[v], p->fnx[k], p->fny[k]);
             if (un > 0) num += p->w[v] * un * p->delta[(size_t)c * nv + v];
         }
         p->drho_g[k] = -num / p->wden[k];
