@@ -1,0 +1,985 @@
+// C ABI of the MI355X implicit DUGKS solver: configuration checks, mesh geometry,
+// discrete velocity set, boundary distributions, workspace carving and the kernel
+// sequence of one explicit or implicit step.  Method: arXiv:1709.01819, Section 2.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/idugks.h"
+#include "idugks_internal.hpp"
+#include "idugks_kernels.hpp"
+
+using namespace idugks;
+
+namespace {
+
+thread_local std::string g_err;
+
+idugks_status fail(idugks_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(IDUGKS_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------------------
+// velocity quadrature (Section 2.2, last paragraph)
+// ---------------------------------------------------------------------------------------
+
+// Number of eigenvalues below x of the Jacobi matrix of the Hermite weight exp(-x^2)
+// (zero diagonal, off-diagonal sqrt(k/2)) by the Sturm count of its LDL^T pivots.
+int sturm_count(int n, double x) {
+    int cnt = 0;
+    double d = -x;
+    if (d < 0) ++cnt;
+    for (int k = 1; k < n; ++k) {
+        const double b2 = 0.5 * k;
+        if (d == 0.0) d = 1e-300;
+        d = -x - b2 / d;
+        if (d < 0) ++cnt;
+    }
+    return cnt;
+}
+
+// Orthonormal Hermite functions psi_n(x) and psi_{n-1}(x).
+void hermite_pair(int n, double x, double &pn, double &pn1) {
+    double a = 0.0, b = pow(M_PI, -0.25) * exp(-0.5 * x * x);
+    for (int k = 0; k < n; ++k) {
+        const double c = sqrt(2.0 / (k + 1)) * x * b - sqrt((double)k / (k + 1)) * a;
+        a = b;
+        b = c;
+    }
+    pn = b;
+    pn1 = a;
+}
+
+// Gauss-Hermite nodes (eigenvalues of the Jacobi matrix by Sturm bisection, then Newton
+// on psi_n) and total weights W_i = w_i exp(x_i^2) = 1 / (n psi_{n-1}(x_i)^2).
+bool gauss_hermite(int n, std::vector<double> &x, std::vector<double> &W) {
+    x.assign(n, 0.0);
+    W.assign(n, 0.0);
+    const double R = sqrt(2.0 * n + 1.0) + 1.0;
+    for (int k = 0; k < n; ++k) {
+        double lo = -R, hi = R;
+        for (int it = 0; it < 200 && hi - lo > 1e-15 * (1.0 + fabs(lo)); ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (sturm_count(n, mid) > k) hi = mid; else lo = mid;
+        }
+        double r = 0.5 * (lo + hi);
+        for (int it = 0; it < 3; ++it) {
+            double pn, pn1;
+            hermite_pair(n, r, pn, pn1);
+            const double dp = sqrt(2.0 * n) * pn1 - r * pn;
+            if (dp == 0.0) break;
+            const double step = pn / dp;
+            if (!(fabs(step) < 1e-3)) break;
+            r -= step;
+        }
+        x[k] = r;
+    }
+    for (int k = 0; k < n / 2; ++k) {
+        const double a = 0.5 * (x[n - 1 - k] - x[k]);
+        x[k] = -a;
+        x[n - 1 - k] = a;
+    }
+    if (n & 1) x[n / 2] = 0.0;
+    for (int k = 0; k < n; ++k) {
+        double pn, pn1;
+        hermite_pair(n, x[k], pn, pn1);
+        W[k] = 1.0 / (n * pn1 * pn1);
+        if (!std::isfinite(W[k]) || !(W[k] > 0)) return false;
+    }
+    return true;
+}
+
+// Composite Newton-Cotes on [-vmax, vmax] with m = n-1 intervals: Boole if 4 | m,
+// Simpson 3/8 if 3 | m, Simpson if 2 | m, else trapezoid.
+bool newton_cotes(int n, double vmax, std::vector<double> &x, std::vector<double> &W) {
+    const int m = n - 1;
+    const double h = 2.0 * vmax / m;
+    x.resize(n);
+    W.assign(n, 0.0);
+    for (int k = 0; k < n; ++k) x[k] = -vmax + h * k;
+    int panel;
+    std::vector<double> c;
+    if (m % 4 == 0) { panel = 4; c = {14.0 / 45, 64.0 / 45, 24.0 / 45, 64.0 / 45, 14.0 / 45}; }
+    else if (m % 3 == 0) { panel = 3; c = {3.0 / 8, 9.0 / 8, 9.0 / 8, 3.0 / 8}; }
+    else if (m % 2 == 0) { panel = 2; c = {1.0 / 3, 4.0 / 3, 1.0 / 3}; }
+    else { panel = 1; c = {0.5, 0.5}; }
+    for (int s = 0; s < m; s += panel)
+        for (int k = 0; k <= panel; ++k) W[s + k] += c[k] * h;
+    return true;
+}
+
+// ---------------------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------------------
+struct Layout {
+    size_t off[64];
+    size_t bytes = 0;
+    int n = 0;
+    size_t add(size_t b) {
+        bytes = (bytes + 255) & ~size_t(255);
+        off[n] = bytes;
+        bytes += b;
+        return n++;
+    }
+};
+
+enum KernelId {
+    KID_RECORDS, KID_PARTIALS, KID_FACE_RECORDS, KID_FLUX, KID_MACRO, KID_RECORDS_PRED,
+    KID_LOWER, KID_WALL_GHOST, KID_UPPER, KID_EXPLICIT, KID_RAW, KID_FINALIZE, KID_COUNT
+};
+const char *kKernelNames[KID_COUNT] = {
+    "records", "face_partials", "face_records", "flux", "macro_lusgs", "records_pred",
+    "sweep_lower", "wall_ghost", "sweep_upper", "explicit_update", "raw_moments", "finalize"};
+
+}  // namespace
+
+struct idugks_ctx {
+    idugks_config cfg;
+    Params p;
+    bool fp32;
+    int vb;
+    hipStream_t st;
+    std::vector<double> area_h, xi_h, eta_h, w_h;
+    double *stage;  // [nc][nvp] FP64 staging of one canonical species
+    int64_t iters;
+    // profiling: one event pair per launch, read after the stream drains
+    bool prof;
+    hipEvent_t ev0, ev1;
+    std::vector<hipEvent_t> evs;
+    std::vector<int> ev_kid;
+    size_t ev_used;
+    double ms[KID_COUNT];
+    int64_t cnt[KID_COUNT];
+};
+
+namespace {
+
+idugks_status validate(const idugks_config *c) {
+    if (!c) return fail(IDUGKS_E_INVALID, "null config");
+    if (c->struct_size != sizeof(idugks_config)) return fail(IDUGKS_E_INVALID, "struct_size mismatch");
+    if (c->ni < 1 || c->nj < 1) return fail(IDUGKS_E_INVALID, "mesh needs ni, nj >= 1");
+    if (c->ni > 2048) return fail(IDUGKS_E_INVALID, "ni > 2048 is not supported");
+    if (!c->xn || !c->yn) return fail(IDUGKS_E_INVALID, "missing node coordinates");
+    if (c->nvx < 2 || c->nvy < 2) return fail(IDUGKS_E_INVALID, "need nv >= 2 per direction");
+    if (c->nvx > 4096 || c->nvy > 4096) return fail(IDUGKS_E_INVALID, "velocity grid too large");
+    if (!(c->Kn > 0)) return fail(IDUGKS_E_INVALID, "Kn must be positive");
+    if (!(c->Pr > 0)) return fail(IDUGKS_E_INVALID, "Pr must be positive");
+    if (c->K < 0) return fail(IDUGKS_E_INVALID, "K must be >= 0");
+    if (c->model != IDUGKS_BGK && c->model != IDUGKS_SHAKHOV) return fail(IDUGKS_E_INVALID, "unknown model");
+    if (c->model == IDUGKS_SHAKHOV && c->K != 1)
+        return fail(IDUGKS_E_INVALID, "the Shakhov model is implemented for K = 1");
+    if (c->quad != IDUGKS_GAUSS_HERMITE && c->quad != IDUGKS_NEWTON_COTES)
+        return fail(IDUGKS_E_INVALID, "unknown quadrature");
+    if (c->quad == IDUGKS_NEWTON_COTES && !(c->vmax > 0))
+        return fail(IDUGKS_E_INVALID, "Newton-Cotes needs vmax > 0");
+    if (!(c->cfl_phys > 0) || !(c->cfl_imp > 0)) return fail(IDUGKS_E_INVALID, "CFL numbers must be positive");
+    if (c->limiter != 0 && c->limiter != 1) return fail(IDUGKS_E_INVALID, "unknown limiter");
+    if (c->precision != IDUGKS_FP64 && c->precision != IDUGKS_FP32_MIXED)
+        return fail(IDUGKS_E_INVALID, "unknown precision");
+    for (int s = 0; s < 4; ++s)
+        if (c->bc[s] < 0 || c->bc[s] > 2) return fail(IDUGKS_E_INVALID, "unknown boundary type");
+    if ((c->bc[0] == IDUGKS_BC_PERIODIC) != (c->bc[1] == IDUGKS_BC_PERIODIC) ||
+        (c->bc[2] == IDUGKS_BC_PERIODIC) != (c->bc[3] == IDUGKS_BC_PERIODIC))
+        return fail(IDUGKS_E_INVALID, "periodic sides must come in pairs");
+    if (c->bc[0] == IDUGKS_BC_PERIODIC && c->ni == 2) return fail(IDUGKS_E_INVALID, "periodic ni must be 1 or >= 3");
+    if (c->bc[2] == IDUGKS_BC_PERIODIC && c->nj == 2) return fail(IDUGKS_E_INVALID, "periodic nj must be 1 or >= 3");
+    for (int s = 0; s < 4; ++s) {
+        if (c->bc[s] == IDUGKS_BC_WALL && !(c->wall_T[s] > 0)) return fail(IDUGKS_E_INVALID, "wall T must be positive");
+        if (c->bc[s] == IDUGKS_BC_FARFIELD && (!(c->far_rho > 0) || !(c->far_T > 0)))
+            return fail(IDUGKS_E_INVALID, "far-field state must be positive");
+    }
+    if (!(c->init_rho > 0) || !(c->init_T > 0)) return fail(IDUGKS_E_INVALID, "initial state must be positive");
+    if (!(c->omega >= 0) || !std::isfinite(c->omega)) return fail(IDUGKS_E_INVALID, "bad omega");
+    return IDUGKS_OK;
+}
+
+// Host-side problem description built from the configuration.
+struct Built {
+    int ni, nj, nc, nf, nv, nvp, nvx, nvy, nwall, closed;
+    double dt;
+    std::vector<double> x1, wx1, y1, wy1, xi, eta, w;
+    std::vector<int16_t> vix, viy;
+    std::vector<double> area, xc, yc;
+    std::vector<CellSide> cs;
+    std::vector<Face> faces;
+    std::vector<int> wall_faces;
+    std::vector<double> gw, wKRT, ginf, hinf, wden, bhalf, eq0;
+};
+
+// Equilibrium pair with exact discrete conserved moments for a state at rest in its
+// own frame (no heat flux): G = G_M (1 + beta.psi(c)), H = K RT G (Eq. 2, Eq. 5).
+void host_equilibrium(const Built &b, int K, double rho, double U, double V, double T,
+                      double *G, double *H) {
+    const double RT = 0.5 * T, lam = 0.5 / RT, A0 = rho * lam / M_PI;
+    double A[4][4] = {{0}}, r[4] = {rho, 0.0, 0.0, rho * RT};
+    std::vector<double> gm(b.nv);
+    for (int v = 0; v < b.nv; ++v) {
+        const double cx = b.xi[v] - U, cy = b.eta[v] - V, c2 = cx * cx + cy * cy;
+        gm[v] = A0 * exp(-lam * c2);
+        const double ps[4] = {1.0, cx, cy, 0.5 * c2};
+        for (int a = 0; a < 4; ++a) {
+            r[a] -= b.w[v] * ps[a] * gm[v];
+            for (int c = 0; c < 4; ++c) A[a][c] += b.w[v] * ps[a] * ps[c] * gm[v];
+        }
+    }
+    // Gaussian elimination with partial pivoting
+    for (int k = 0; k < 4; ++k) {
+        int pv = k;
+        for (int i = k + 1; i < 4; ++i)
+            if (fabs(A[i][k]) > fabs(A[pv][k])) pv = i;
+        std::swap(A[k], A[pv]);
+        std::swap(r[k], r[pv]);
+        for (int i = k + 1; i < 4; ++i) {
+            const double m = A[i][k] / A[k][k];
+            for (int c = k; c < 4; ++c) A[i][c] -= m * A[k][c];
+            r[i] -= m * r[k];
+        }
+    }
+    for (int k = 3; k >= 0; --k) {
+        double s = r[k];
+        for (int c = k + 1; c < 4; ++c) s -= A[k][c] * r[c];
+        r[k] = s / A[k][k];
+    }
+    for (int v = 0; v < b.nv; ++v) {
+        const double cx = b.xi[v] - U, cy = b.eta[v] - V;
+        const double g = gm[v] * (1.0 + r[0] + r[1] * cx + r[2] * cy + 0.5 * r[3] * (cx * cx + cy * cy));
+        G[v] = g;
+        H[v] = K * RT * g;
+    }
+}
+
+// Normal speed with velocities tangent to the face (within 1e-12 of their speed) snapped
+// to exactly 0; the device kernels classify with the same rule.
+double normal_speed(double x, double y, double nx, double ny) {
+    const double un = x * nx + y * ny;
+    return fabs(un) <= 1e-12 * (fabs(x) + fabs(y)) ? 0.0 : un;
+}
+
+// 12 raw moments (the set accumulated on the device) of a pair over a subset of v.
+void raw12(const Built &b, const double *G, const double *H, const std::vector<char> &use,
+           double *m) {
+    for (int a = 0; a < 12; ++a) m[a] = 0.0;
+    for (int v = 0; v < b.nv; ++v) {
+        if (!use[v]) continue;
+        const double x = b.xi[v], y = b.eta[v], q2 = x * x + y * y;
+        const double wG = b.w[v] * G[v], wH = b.w[v] * H[v];
+        m[0] += wG; m[1] += wG * x; m[2] += wG * y; m[3] += 0.5 * (wG * q2 + wH);
+        m[4] += wG * x * x; m[5] += wG * x * y; m[6] += wG * y * y;
+        m[7] += wG * x * q2; m[8] += wG * y * q2;
+        m[9] += wH; m[10] += wH * x; m[11] += wH * y;
+    }
+}
+
+idugks_status build(const idugks_config *c, Built &b) {
+    const int ni = c->ni, nj = c->nj;
+    b.ni = ni;
+    b.nj = nj;
+    b.nc = ni * nj;
+    b.nvx = c->nvx;
+    b.nvy = c->nvy;
+    b.nv = c->nvx * c->nvy;
+    b.nvp = (b.nv + VPAD - 1) / VPAD * VPAD;
+    // velocity set
+    bool ok = c->quad == IDUGKS_GAUSS_HERMITE
+                  ? gauss_hermite(c->nvx, b.x1, b.wx1) && gauss_hermite(c->nvy, b.y1, b.wy1)
+                  : newton_cotes(c->nvx, c->vmax, b.x1, b.wx1) && newton_cotes(c->nvy, c->vmax, b.y1, b.wy1);
+    if (!ok) return fail(IDUGKS_E_INVALID, "quadrature construction failed");
+    b.xi.assign(b.nvp, 0.0);
+    b.eta.assign(b.nvp, 0.0);
+    b.w.assign(b.nvp, 0.0);
+    b.vix.assign(b.nvp, 0);
+    b.viy.assign(b.nvp, 0);
+    for (int ix = 0; ix < b.nvx; ++ix)
+        for (int iy = 0; iy < b.nvy; ++iy) {
+            const int v = ix * b.nvy + iy;
+            b.xi[v] = b.x1[ix];
+            b.eta[v] = b.y1[iy];
+            b.w[v] = b.wx1[ix] * b.wy1[iy];
+            b.vix[v] = (int16_t)ix;
+            b.viy[v] = (int16_t)iy;
+        }
+    // cells: shoelace area and centroid
+    auto X = [&](int i, int j) { return c->xn[i + j * (ni + 1)]; };
+    auto Y = [&](int i, int j) { return c->yn[i + j * (ni + 1)]; };
+    b.area.resize(b.nc);
+    b.xc.resize(b.nc);
+    b.yc.resize(b.nc);
+    for (int j = 0; j < nj; ++j)
+        for (int i = 0; i < ni; ++i) {
+            const double px[4] = {X(i, j), X(i + 1, j), X(i + 1, j + 1), X(i, j + 1)};
+            const double py[4] = {Y(i, j), Y(i + 1, j), Y(i + 1, j + 1), Y(i, j + 1)};
+            double a = 0, sx = 0, sy = 0;
+            for (int k = 0; k < 4; ++k) {
+                const int l = (k + 1) & 3;
+                const double cr = px[k] * py[l] - px[l] * py[k];
+                a += cr;
+                sx += (px[k] + px[l]) * cr;
+                sy += (py[k] + py[l]) * cr;
+            }
+            a *= 0.5;
+            if (!(a > 0)) return fail(IDUGKS_E_INVALID, "non-positive cell area (check node order)");
+            const int cidx = i + j * ni;
+            b.area[cidx] = a;
+            b.xc[cidx] = sx / (6.0 * a);
+            b.yc[cidx] = sy / (6.0 * a);
+        }
+    // faces: i-faces (i, j) at index j*(ni+1)+i, then j-faces (i, j) at nfi + j*ni + i
+    const bool pi = c->bc[0] == IDUGKS_BC_PERIODIC, pj = c->bc[2] == IDUGKS_BC_PERIODIC;
+    const int nfi = (ni + 1) * nj, nfj = ni * (nj + 1);
+    b.nf = nfi + nfj;
+    b.faces.assign(b.nf, Face{});
+    for (auto &F : b.faces) { F.type = FT_SELF; F.L = F.R = -1; }
+    auto set_face = [&](int k, int L, int sL, int R, int sR, int type, int side, double ax, double ay,
+                        double bx, double by, bool plus_i) {
+        Face &F = b.faces[k];
+        const double tx = bx - ax, ty = by - ay, S = sqrt(tx * tx + ty * ty);
+        double nx = plus_i ? ty / S : -ty / S, ny = plus_i ? -tx / S : tx / S;
+        if (R < 0 && (side == 0 || side == 2)) { nx = -nx; ny = -ny; }  // outward at i- / j-
+        F.L = L; F.sL = sL; F.R = R; F.sR = sR; F.type = type; F.wside = side;
+        F.nx = nx; F.ny = ny; F.S = S;
+    };
+    for (int j = 0; j < nj; ++j)
+        for (int i = 0; i <= ni; ++i) {
+            const int k = j * (ni + 1) + i;
+            const double ax = X(i, j), ay = Y(i, j), bx = X(i, j + 1), by = Y(i, j + 1);
+            if (i > 0 && i < ni) set_face(k, i - 1 + j * ni, 1, i + j * ni, 0, FT_INTERIOR, -1, ax, ay, bx, by, true);
+            else if (pi) {
+                if (i == ni) set_face(k, ni - 1 + j * ni, 1, j * ni, 0, ni == 1 ? FT_SELF : FT_INTERIOR, -1, ax, ay, bx, by, true);
+            } else {
+                const int side = i == 0 ? 0 : 1, cell = i == 0 ? j * ni : ni - 1 + j * ni;
+                set_face(k, cell, side, -1, -1, c->bc[side] == IDUGKS_BC_WALL ? FT_WALL : FT_FAR, side, ax, ay, bx, by, true);
+            }
+        }
+    for (int j = 0; j <= nj; ++j)
+        for (int i = 0; i < ni; ++i) {
+            const int k = nfi + j * ni + i;
+            const double ax = X(i, j), ay = Y(i, j), bx = X(i + 1, j), by = Y(i + 1, j);
+            if (j > 0 && j < nj) set_face(k, i + (j - 1) * ni, 3, i + j * ni, 2, FT_INTERIOR, -1, ax, ay, bx, by, false);
+            else if (pj) {
+                if (j == nj) set_face(k, i + (nj - 1) * ni, 3, i, 2, nj == 1 ? FT_SELF : FT_INTERIOR, -1, ax, ay, bx, by, false);
+            } else {
+                const int side = j == 0 ? 2 : 3, cell = j == 0 ? i : i + (nj - 1) * ni;
+                set_face(k, cell, side, -1, -1, c->bc[side] == IDUGKS_BC_WALL ? FT_WALL : FT_FAR, side, ax, ay, bx, by, false);
+            }
+        }
+    // cell sides
+    b.cs.assign((size_t)4 * b.nc, CellSide{});
+    b.closed = 1;
+    for (int s = 0; s < 4; ++s)
+        if (c->bc[s] == IDUGKS_BC_FARFIELD) b.closed = 0;
+    for (int j = 0; j < nj; ++j)
+        for (int i = 0; i < ni; ++i) {
+            const int cidx = i + j * ni;
+            for (int s = 0; s < 4; ++s) {
+                CellSide &q = b.cs[(size_t)4 * cidx + s];
+                // own edge, counter-clockwise orientation of the cell
+                double ax, ay, bx, by;
+                if (s == 0) { ax = X(i, j + 1); ay = Y(i, j + 1); bx = X(i, j); by = Y(i, j); }
+                else if (s == 1) { ax = X(i + 1, j); ay = Y(i + 1, j); bx = X(i + 1, j + 1); by = Y(i + 1, j + 1); }
+                else if (s == 2) { ax = X(i, j); ay = Y(i, j); bx = X(i + 1, j); by = Y(i + 1, j); }
+                else { ax = X(i + 1, j + 1); ay = Y(i + 1, j + 1); bx = X(i, j + 1); by = Y(i, j + 1); }
+                const double tx = bx - ax, ty = by - ay, S = sqrt(tx * tx + ty * ty);
+                q.nx = ty / S;  // outward normal of a counter-clockwise edge
+                q.ny = -tx / S;
+                q.S = S;
+                q.dx = 0.5 * (ax + bx) - b.xc[cidx];
+                q.dy = 0.5 * (ay + by) - b.yc[cidx];
+                // face and neighbour
+                int fi, fj, ni2 = i, nj2 = j;
+                double shx = 0.0, shy = 0.0;
+                bool has = true;
+                if (s == 0) {
+                    fi = j * (ni + 1) + i;
+                    if (i > 0) ni2 = i - 1;
+                    else if (pi) { ni2 = ni - 1; fi = j * (ni + 1) + ni; shx = -(X(ni, j) - X(0, j)); shy = -(Y(ni, j) - Y(0, j)); }
+                    else has = false;
+                } else if (s == 1) {
+                    fi = j * (ni + 1) + i + 1;
+                    if (i < ni - 1) ni2 = i + 1;
+                    else if (pi) { ni2 = 0; shx = X(ni, j) - X(0, j); shy = Y(ni, j) - Y(0, j); }
+                    else has = false;
+                } else if (s == 2) {
+                    fi = nfi + j * ni + i;
+                    if (j > 0) nj2 = j - 1;
+                    else if (pj) { nj2 = nj - 1; fi = nfi + nj * ni + i; shx = -(X(i, nj) - X(i, 0)); shy = -(Y(i, nj) - Y(i, 0)); }
+                    else has = false;
+                } else {
+                    fi = nfi + (j + 1) * ni + i;
+                    if (j < nj - 1) nj2 = j + 1;
+                    else if (pj) { nj2 = 0; shx = X(i, nj) - X(i, 0); shy = Y(i, nj) - Y(i, 0); }
+                    else has = false;
+                }
+                (void)fj;
+                q.face = fi;
+                const Face &F = b.faces[fi];
+                q.type = F.type;
+                q.wside = s;
+                if (has) {
+                    q.nb = ni2 + nj2 * ni;
+                    q.ndx = b.xc[q.nb] + shx - b.xc[cidx];
+                    q.ndy = b.yc[q.nb] + shy - b.yc[cidx];
+                    q.tie = (F.type == FT_INTERIOR && F.R == cidx && F.sR == s) ? 1 : 0;
+                    q.hp_adj = abs((ni2 + nj2) - (i + j)) == 1 ? 1 : 0;
+                } else {
+                    q.nb = -1;
+                    q.tie = F.type == FT_FAR ? 1 : 0;
+                    q.hp_adj = 0;
+                }
+            }
+            // least-squares weights (Eq. 15) over the neighbours (periodic images included)
+            double a11 = 0, a12 = 0, a22 = 0;
+            for (int s = 0; s < 4; ++s) {
+                const CellSide &q = b.cs[(size_t)4 * cidx + s];
+                if (q.nb < 0) continue;
+                a11 += q.ndx * q.ndx; a12 += q.ndx * q.ndy; a22 += q.ndy * q.ndy;
+            }
+            const double det = a11 * a22 - a12 * a12;
+            if (!(det > 0)) return fail(IDUGKS_E_INVALID, "degenerate least-squares stencil");
+            for (int s = 0; s < 4; ++s) {
+                CellSide &q = b.cs[(size_t)4 * cidx + s];
+                if (q.nb < 0) continue;
+                q.ax = (a22 * q.ndx - a12 * q.ndy) / det;
+                q.ay = (a11 * q.ndy - a12 * q.ndx) / det;
+            }
+        }
+    // physical time step
+    double hmin = 1e300, smax = 0.0;
+    for (int cidx = 0; cidx < b.nc; ++cidx) {
+        double d = 1e300;
+        for (int s = 0; s < 4; ++s) {
+            const CellSide &q = b.cs[(size_t)4 * cidx + s];
+            d = std::min(d, fabs(q.dx * q.nx + q.dy * q.ny));
+        }
+        hmin = std::min(hmin, 2.0 * d);
+    }
+    for (int v = 0; v < b.nv; ++v) smax = std::max(smax, sqrt(b.xi[v] * b.xi[v] + b.eta[v] * b.eta[v]));
+    b.dt = c->cfl_phys * hmin / smax;
+    // boundary distributions
+    b.gw.assign((size_t)4 * b.nvp, 0.0);
+    b.wKRT.assign(4, 0.0);
+    std::vector<double> tmpH(b.nvp, 0.0);
+    for (int s = 0; s < 4; ++s) {
+        if (c->bc[s] != IDUGKS_BC_WALL) continue;
+        host_equilibrium(b, c->K, 1.0, c->wall_u[s], c->wall_v[s], c->wall_T[s], &b.gw[(size_t)s * b.nvp], tmpH.data());
+        b.wKRT[s] = c->K * 0.5 * c->wall_T[s];
+    }
+    b.ginf.assign(b.nvp, 0.0);
+    b.hinf.assign(b.nvp, 0.0);
+    host_equilibrium(b, c->K, c->far_rho, c->far_u, c->far_v, c->far_T, b.ginf.data(), b.hinf.data());
+    b.eq0.assign((size_t)2 * b.nvp, 0.0);
+    host_equilibrium(b, c->K, c->init_rho, c->init_u, c->init_v, c->init_T, b.eq0.data(), b.eq0.data() + b.nvp);
+    b.wden.assign(b.nf, 0.0);
+    b.bhalf.assign((size_t)b.nf * NM_MAX, 0.0);
+    b.nwall = 0;
+    std::vector<char> use(b.nv);
+    std::vector<double> gH(b.nv);
+    for (int k = 0; k < b.nf; ++k) {
+        const Face &F = b.faces[k];
+        if (F.type != FT_WALL && F.type != FT_FAR) continue;
+        for (int v = 0; v < b.nv; ++v) {
+            const double un = normal_speed(b.xi[v], b.eta[v], F.nx, F.ny);
+            use[v] = F.type == FT_WALL ? (un <= 0.0) : (un < 0.0);
+        }
+        if (F.type == FT_WALL) {
+            b.wall_faces.push_back(k);
+            ++b.nwall;
+            const double *g = &b.gw[(size_t)F.wside * b.nvp];
+            double den = 0.0;
+            for (int v = 0; v < b.nv; ++v) {
+                const double un = normal_speed(b.xi[v], b.eta[v], F.nx, F.ny);
+                if (un < 0.0) den += b.w[v] * un * g[v];
+                gH[v] = b.wKRT[F.wside] * g[v];
+            }
+            b.wden[k] = den;
+            raw12(b, g, gH.data(), use, &b.bhalf[(size_t)k * NM_MAX]);
+        } else {
+            raw12(b, b.ginf.data(), b.hinf.data(), use, &b.bhalf[(size_t)k * NM_MAX]);
+        }
+    }
+    return IDUGKS_OK;
+}
+
+// Workspace regions.
+enum Region {
+    R_CS, R_FACES, R_WALLF, R_AREA, R_XI, R_ETA, R_W, R_X1, R_WX1, R_Y1, R_WY1, R_VIX, R_VIY,
+    R_GW, R_WKRT, R_GINF, R_HINF, R_WDEN, R_BHALF, R_F, R_D1, R_TAB, R_TABS, R_TABF, R_REC,
+    R_RECS, R_RECF, R_PART, R_RAW, R_WC, R_MW, R_DW, R_DWD, R_DTIMP, R_RHOOLD, R_DRHO, R_SCAL,
+    R_STAGE, R_COUNT
+};
+
+Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy, int nwall) {
+    Layout L;
+    const size_t S = c->precision == IDUGKS_FP32_MIXED ? 4 : 8, TW = (size_t)nvx + nvy;
+    const size_t sizes[R_COUNT] = {
+        sizeof(CellSide) * 4 * (size_t)nc, sizeof(Face) * (size_t)nf, sizeof(int) * (size_t)std::max(nwall, 1),
+        8 * (size_t)nc, 8 * (size_t)nvp, 8 * (size_t)nvp, 8 * (size_t)nvp, 8 * (size_t)nvx, 8 * (size_t)nvx,
+        8 * (size_t)nvy, 8 * (size_t)nvy, 2 * (size_t)nvp, 2 * (size_t)nvp,
+        8 * 4 * (size_t)nvp, 8 * 4, 8 * (size_t)nvp, 8 * (size_t)nvp, 8 * (size_t)nf, 8 * (size_t)nf * NM_MAX,
+        S * 2 * (size_t)nc * nvp, S * 2 * (size_t)nc * nvp, S * (size_t)nc * TW, S * (size_t)nc * TW,
+        S * (size_t)nf * TW, sizeof(Rec) * (size_t)nc, sizeof(Rec) * (size_t)nc, sizeof(Rec) * (size_t)nf,
+        8 * (size_t)nc * 4 * NM_MAX, 8 * (size_t)nc * NM_MAX, 8 * 4 * (size_t)nc, 8 * 4 * (size_t)nc,
+        8 * 4 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nf, 8 * SC_NUM,
+        8 * (size_t)std::max(nc, 2) * nvp};
+    for (int r = 0; r < R_COUNT; ++r) L.add(sizes[r]);
+    L.bytes = (L.bytes + 255) & ~size_t(255);
+    return L;
+}
+
+// ---------------------------------------------------------------------------------------
+// kernel sequence
+// ---------------------------------------------------------------------------------------
+template <class F>
+idugks_status timed(idugks_ctx *x, int kid, F &&launch) {
+    size_t slot = 0;
+    if (x->prof) {
+        slot = x->ev_used++;
+        while (x->evs.size() < 2 * x->ev_used) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            x->evs.push_back(e);
+        }
+        if (x->ev_kid.size() < x->ev_used) x->ev_kid.resize(x->ev_used);
+        x->ev_kid[slot] = kid;
+        HIPCHK(hipEventRecord(x->evs[2 * slot], x->st));
+    }
+    hipError_t e = launch();
+    if (e != hipSuccess)
+        return fail(IDUGKS_E_DEVICE, std::string("kernel ") + kKernelNames[kid] + ": " + hipGetErrorString(e));
+    if (x->prof) HIPCHK(hipEventRecord(x->evs[2 * slot + 1], x->st));
+    return IDUGKS_OK;
+}
+
+#define RUN(kid, call)                                            \
+    do {                                                          \
+        idugks_status s_ = timed(x, kid, [&] { return (call); }); \
+        if (s_ != IDUGKS_OK) return s_;                           \
+    } while (0)
+
+idugks_status flux_pipeline(idugks_ctx *x) {
+    const Params &p = x->p;
+    RUN(KID_RECORDS, launch_records(p, x->fp32, 0, x->st));
+    RUN(KID_PARTIALS, launch_partials(p, x->fp32, x->st));
+    RUN(KID_FACE_RECORDS, launch_face_records(p, x->fp32, x->st));
+    RUN(KID_FLUX, launch_flux(p, x->fp32, x->st));
+    return IDUGKS_OK;
+}
+
+idugks_status finalize_state(idugks_ctx *x, int mode) {
+    const Params &p = x->p;
+    RUN(KID_RAW, launch_raw(p, x->fp32, p.nm, x->st));
+    RUN(KID_FINALIZE, launch_finalize(p, mode, x->st));
+    return IDUGKS_OK;
+}
+
+idugks_status one_step(idugks_ctx *x, int mode) {
+    const Params &p = x->p;
+    idugks_status s = flux_pipeline(x);
+    if (s != IDUGKS_OK) return s;
+    if (mode == IDUGKS_IMPLICIT) {
+        RUN(KID_MACRO, launch_macro(p, x->st));
+        RUN(KID_RECORDS_PRED, launch_records(p, x->fp32, 1, x->st));
+        RUN(KID_LOWER, launch_sweep(p, x->fp32, false, x->vb, x->st));
+        RUN(KID_WALL_GHOST, launch_wall_ghost(p, x->fp32, x->st));
+        RUN(KID_UPPER, launch_sweep(p, x->fp32, true, x->vb, x->st));
+    } else {
+        RUN(KID_EXPLICIT, launch_explicit(p, x->fp32, x->st));
+    }
+    return finalize_state(x, mode == IDUGKS_IMPLICIT ? 1 : 2);
+}
+
+idugks_status read_scalars(idugks_ctx *x, double *sc) {
+    HIPCHK(hipMemcpyAsync(sc, x->p.scal, sizeof(double) * SC_NUM, hipMemcpyDeviceToHost, x->st));
+    HIPCHK(hipStreamSynchronize(x->st));
+    return IDUGKS_OK;
+}
+
+// Velocities per sweep block: enough slices to occupy the chip, at least 8 velocities per
+// slice, and the two LDS fronts (2 x ni x vb values) within 128 KiB.
+int choose_vb(int nv, int ni, size_t s_bytes) {
+    int vb = nv >= 64 * 256 ? 64 : nv >= 32 * 256 ? 32 : nv >= 16 * 128 ? 16 : 8;
+    while (vb > 8 && (size_t)2 * ni * vb * s_bytes > 128 * 1024) vb /= 2;
+    return vb;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------------------
+extern "C" {
+
+const char *idugks_last_error(void) { return g_err.c_str(); }
+
+idugks_status idugks_workspace_size(const idugks_config *cfg, size_t *bytes) {
+    if (!bytes) return fail(IDUGKS_E_INVALID, "null output");
+    idugks_status s = validate(cfg);
+    if (s != IDUGKS_OK) return s;
+    const int nc = cfg->ni * cfg->nj, nf = (cfg->ni + 1) * cfg->nj + cfg->ni * (cfg->nj + 1);
+    const int nv = cfg->nvx * cfg->nvy, nvp = (nv + VPAD - 1) / VPAD * VPAD;
+    *bytes = layout(cfg, nc, nf, nvp, cfg->nvx, cfg->nvy, 2 * (cfg->ni + cfg->nj)).bytes;
+    return IDUGKS_OK;
+}
+
+idugks_status idugks_describe(const idugks_config *cfg, double *xi, double *eta, double *w, double *dt,
+                              double *area, int32_t *nb, double *nx, double *ny, double *S, double *ax,
+                              double *ay) {
+    idugks_status s = validate(cfg);
+    if (s != IDUGKS_OK) return s;
+    Built b;
+    s = build(cfg, b);
+    if (s != IDUGKS_OK) return s;
+    for (int v = 0; v < b.nv; ++v) {
+        if (xi) xi[v] = b.xi[v];
+        if (eta) eta[v] = b.eta[v];
+        if (w) w[v] = b.w[v];
+    }
+    if (dt) *dt = b.dt;
+    for (int c = 0; c < b.nc; ++c) {
+        if (area) area[c] = b.area[c];
+        for (int k = 0; k < 4; ++k) {
+            const CellSide &q = b.cs[(size_t)4 * c + k];
+            const int m = 4 * c + k;
+            if (nb) nb[m] = q.nb;
+            if (nx) nx[m] = q.nx;
+            if (ny) ny[m] = q.ny;
+            if (S) S[m] = q.S;
+            if (ax) ax[m] = q.ax;
+            if (ay) ay[m] = q.ay;
+        }
+    }
+    return IDUGKS_OK;
+}
+
+idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t bytes, void *hip_stream,
+                          idugks_ctx **out) {
+    if (!out) return fail(IDUGKS_E_INVALID, "null output");
+    *out = nullptr;
+    idugks_status s = validate(cfg);
+    if (s != IDUGKS_OK) return s;
+    if (!d_workspace) return fail(IDUGKS_E_INVALID, "null workspace");
+    size_t need = 0;
+    idugks_workspace_size(cfg, &need);
+    if (bytes < need) return fail(IDUGKS_E_INVALID, "workspace too small");
+    Built b;
+    s = build(cfg, b);
+    if (s != IDUGKS_OK) return s;
+    Layout L = layout(cfg, b.nc, b.nf, b.nvp, b.nvx, b.nvy, 2 * (cfg->ni + cfg->nj));
+    char *base = (char *)d_workspace;
+    auto R = [&](int r) { return (void *)(base + L.off[r]); };
+
+    idugks_ctx *x = new idugks_ctx();
+    x->cfg = *cfg;
+    x->cfg.xn = x->cfg.yn = nullptr;
+    x->fp32 = cfg->precision == IDUGKS_FP32_MIXED;
+    x->st = (hipStream_t)hip_stream;
+    x->vb = choose_vb(b.nv, b.ni, x->fp32 ? 4 : 8);
+    x->iters = 0;
+    x->prof = false;
+    x->ev_used = 0;
+    x->area_h = b.area;
+    x->xi_h.assign(b.xi.begin(), b.xi.begin() + b.nv);
+    x->eta_h.assign(b.eta.begin(), b.eta.begin() + b.nv);
+    x->w_h.assign(b.w.begin(), b.w.begin() + b.nv);
+    Params &p = x->p;
+    memset(&p, 0, sizeof p);
+    p.ni = b.ni; p.nj = b.nj; p.nc = b.nc; p.nf = b.nf; p.nv = b.nv; p.nvp = b.nvp;
+    p.nvx = b.nvx; p.nvy = b.nvy; p.K = cfg->K; p.model = cfg->model; p.limiter = cfg->limiter;
+    p.closed = b.closed; p.nm = cfg->model == IDUGKS_SHAKHOV ? NM_SHAKHOV : NM_BGK; p.nwall = b.nwall;
+    p.dt = b.dt; p.h = 0.5 * b.dt; p.Pr = cfg->Pr; p.mu_ref = cfg->Kn / sqrt(M_PI);
+    p.omega = cfg->omega; p.cfl_imp = cfg->cfl_imp; p.gam = (cfg->K + 4.0) / (cfg->K + 2.0);
+    p.cs = (const CellSide *)R(R_CS); p.faces = (const Face *)R(R_FACES);
+    p.wall_faces = (const int *)R(R_WALLF); p.area = (const double *)R(R_AREA);
+    p.xi = (const double *)R(R_XI); p.eta = (const double *)R(R_ETA); p.w = (const double *)R(R_W);
+    p.x1 = (const double *)R(R_X1); p.wx1 = (const double *)R(R_WX1);
+    p.y1 = (const double *)R(R_Y1); p.wy1 = (const double *)R(R_WY1);
+    p.vix = (const int16_t *)R(R_VIX); p.viy = (const int16_t *)R(R_VIY);
+    p.gw = (const double *)R(R_GW); p.wKRT = (const double *)R(R_WKRT);
+    p.ginf = (const double *)R(R_GINF); p.hinf = (const double *)R(R_HINF);
+    p.wden = (const double *)R(R_WDEN); p.bhalf = (const double *)R(R_BHALF);
+    p.f = R(R_F); p.d1 = R(R_D1); p.tab = R(R_TAB); p.tabs = R(R_TABS); p.tabf = R(R_TABF);
+    p.rec = (Rec *)R(R_REC); p.recs = (Rec *)R(R_RECS); p.recf = (Rec *)R(R_RECF);
+    p.part = (double *)R(R_PART); p.raw = (double *)R(R_RAW); p.Wc = (double *)R(R_WC);
+    p.MW = (double *)R(R_MW); p.dW = (double *)R(R_DW); p.DWd = (double *)R(R_DWD);
+    p.dtimp = (double *)R(R_DTIMP); p.rho_old = (double *)R(R_RHOOLD); p.drho = (double *)R(R_DRHO);
+    p.scal = (double *)R(R_SCAL);
+    x->stage = (double *)R(R_STAGE);
+
+    auto up = [&](void *dst, const void *src, size_t n) {
+        return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, x->st);
+    };
+    hipError_t e = hipSuccess;
+#define UP(r, vec) if (e == hipSuccess && !(vec).empty()) e = up(R(r), (vec).data(), (vec).size() * sizeof((vec)[0]))
+    UP(R_CS, b.cs); UP(R_FACES, b.faces); UP(R_WALLF, b.wall_faces); UP(R_AREA, b.area);
+    UP(R_XI, b.xi); UP(R_ETA, b.eta); UP(R_W, b.w); UP(R_X1, b.x1); UP(R_WX1, b.wx1);
+    UP(R_Y1, b.y1); UP(R_WY1, b.wy1); UP(R_VIX, b.vix); UP(R_VIY, b.viy); UP(R_GW, b.gw);
+    UP(R_WKRT, b.wKRT); UP(R_GINF, b.ginf); UP(R_HINF, b.hinf); UP(R_WDEN, b.wden); UP(R_BHALF, b.bhalf);
+    UP(R_STAGE, b.eq0);
+#undef UP
+    if (e == hipSuccess) e = hipMemsetAsync(p.drho, 0, sizeof(double) * b.nf, x->st);
+    if (e == hipSuccess) e = hipMemsetAsync(p.rho_old, 0, sizeof(double) * b.nc, x->st);
+    if (e == hipSuccess) e = hipMemsetAsync(p.scal, 0, sizeof(double) * SC_NUM, x->st);
+    if (e == hipSuccess) e = hipMemsetAsync(p.dW, 0, sizeof(double) * 4 * b.nc, x->st);
+    if (e == hipSuccess) e = launch_fill_uniform(p, x->fp32, x->stage, x->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(x->st);  // host vectors die with b
+    if (e != hipSuccess) {
+        delete x;
+        return fail(IDUGKS_E_DEVICE, std::string("init upload: ") + hipGetErrorString(e));
+    }
+    if (hipEventCreate(&x->ev0) != hipSuccess || hipEventCreate(&x->ev1) != hipSuccess) {
+        delete x;
+        return fail(IDUGKS_E_DEVICE, "hipEventCreate failed");
+    }
+    s = finalize_state(x, 0);
+    double sc[SC_NUM];
+    if (s == IDUGKS_OK) s = read_scalars(x, sc);
+    if (s != IDUGKS_OK) {
+        idugks_destroy(x);
+        return s;
+    }
+    p.M0 = sc[SC_MASS];
+    *out = x;
+    return IDUGKS_OK;
+}
+
+void idugks_destroy(idugks_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipEventDestroy(ctx->ev0);
+    (void)hipEventDestroy(ctx->ev1);
+    for (hipEvent_t e : ctx->evs) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+idugks_status idugks_get_info(idugks_ctx *x, idugks_info *out) {
+    if (!x || !out) return fail(IDUGKS_E_INVALID, "null argument");
+    out->nc = x->p.nc; out->nv = x->p.nv; out->nvp = x->p.nvp; out->nf = x->p.nf;
+    out->nwall = x->p.nwall; out->nvx = x->p.nvx; out->nvy = x->p.nvy;
+    out->precision = x->cfg.precision; out->dt = x->p.dt; out->M0 = x->p.M0;
+    out->iterations = x->iters;
+    return IDUGKS_OK;
+}
+
+idugks_status idugks_velocities(idugks_ctx *x, double *xi, double *eta, double *w) {
+    if (!x || !xi || !eta || !w) return fail(IDUGKS_E_INVALID, "null argument");
+    memcpy(xi, x->xi_h.data(), sizeof(double) * x->p.nv);
+    memcpy(eta, x->eta_h.data(), sizeof(double) * x->p.nv);
+    memcpy(w, x->w_h.data(), sizeof(double) * x->p.nv);
+    return IDUGKS_OK;
+}
+
+idugks_status idugks_step(idugks_ctx *x, int32_t mode, int32_t nsteps, double *res_out) {
+    if (!x) return fail(IDUGKS_E_INVALID, "null context");
+    if (mode != IDUGKS_EXPLICIT && mode != IDUGKS_IMPLICIT) return fail(IDUGKS_E_INVALID, "unknown mode");
+    if (nsteps < 0) return fail(IDUGKS_E_INVALID, "negative step count");
+    for (int n = 0; n < nsteps; ++n) {
+        idugks_status s = one_step(x, mode);
+        if (s != IDUGKS_OK) return s;
+        ++x->iters;
+    }
+    double sc[SC_NUM];
+    idugks_status s = read_scalars(x, sc);
+    if (s != IDUGKS_OK) return s;
+    if (res_out) *res_out = sc[SC_RES];
+    if (sc[SC_FLAG] != 0.0 || !std::isfinite(sc[SC_RES]))
+        return fail(IDUGKS_E_DIVERGED, "non-physical state (rho <= 0, E <= 0 or NaN)");
+    return IDUGKS_OK;
+}
+
+idugks_status idugks_solve(idugks_ctx *x, double tol, int32_t max_iter, int32_t *iters, double *res_out) {
+    if (!x) return fail(IDUGKS_E_INVALID, "null context");
+    if (!(tol > 0) || max_iter < 0) return fail(IDUGKS_E_INVALID, "bad tolerance or iteration limit");
+    double r = INFINITY;
+    int n = 0;
+    idugks_status s = IDUGKS_OK;
+    while (n < max_iter) {
+        s = idugks_step(x, IDUGKS_IMPLICIT, 1, &r);
+        ++n;
+        if (s != IDUGKS_OK || r < tol) break;
+    }
+    if (iters) *iters = n;
+    if (res_out) *res_out = r;
+    if (s != IDUGKS_OK) return s;
+    return r < tol ? IDUGKS_OK : fail(IDUGKS_E_NOT_CONVERGED, "iteration limit reached");
+}
+
+static idugks_status copy_out(idugks_ctx *x, void *dst, const void *src, size_t n, int on_host) {
+    HIPCHK(hipMemcpyAsync(dst, src, n, on_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, x->st));
+    HIPCHK(hipStreamSynchronize(x->st));
+    return IDUGKS_OK;
+}
+
+idugks_status idugks_flux(idugks_ctx *x, double *M, int32_t on_host) {
+    if (!x || !M) return fail(IDUGKS_E_INVALID, "null argument");
+    idugks_status s = flux_pipeline(x);
+    if (s != IDUGKS_OK) return s;
+    const size_t n = (size_t)x->p.nc * x->p.nv;
+    for (int sp = 0; sp < 2; ++sp) {
+        double *dst = on_host ? x->stage : M + sp * n;
+        HIPCHK(launch_pack(x->p, x->fp32, x->p.d1, dst, sp, 1, 0, x->st));
+        if (on_host) {
+            s = copy_out(x, M + sp * n, x->stage, n * sizeof(double), 1);
+            if (s != IDUGKS_OK) return s;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(x->st));
+    return IDUGKS_OK;
+}
+
+idugks_status idugks_face_moments(idugks_ctx *x, double *Wf, double *rho_w, int32_t on_host) {
+    if (!x) return fail(IDUGKS_E_INVALID, "null context");
+    idugks_status s = flux_pipeline(x);
+    if (s != IDUGKS_OK) return s;
+    const int nf = x->p.nf;
+    std::vector<Rec> r(nf);
+    std::vector<Face> F(nf);
+    HIPCHK(hipMemcpyAsync(r.data(), x->p.recf, sizeof(Rec) * nf, hipMemcpyDeviceToHost, x->st));
+    HIPCHK(hipMemcpyAsync(F.data(), x->p.faces, sizeof(Face) * nf, hipMemcpyDeviceToHost, x->st));
+    HIPCHK(hipStreamSynchronize(x->st));
+    std::vector<double> W(4 * (size_t)nf, 0.0), rw(nf, 0.0);
+    for (int k = 0; k < nf; ++k) {
+        if (F[k].type == FT_SELF) continue;
+        const Rec &q = r[k];
+        W[4 * k] = q.rho;
+        W[4 * k + 1] = q.rho * q.U;
+        W[4 * k + 2] = q.rho * q.V;
+        W[4 * k + 3] = 0.5 * q.rho * (q.U * q.U + q.V * q.V + (x->p.K + 2) * q.RT);
+        rw[k] = q.rw;
+    }
+    const hipMemcpyKind kind = on_host ? hipMemcpyHostToHost : hipMemcpyHostToDevice;
+    if (Wf) HIPCHK(hipMemcpyAsync(Wf, W.data(), sizeof(double) * 4 * nf, kind, x->st));
+    if (rho_w) HIPCHK(hipMemcpyAsync(rho_w, rw.data(), sizeof(double) * nf, kind, x->st));
+    HIPCHK(hipStreamSynchronize(x->st));
+    return IDUGKS_OK;
+}
+
+idugks_status idugks_macro_residual(idugks_ctx *x, double *MW, int32_t on_host) {
+    if (!x || !MW) return fail(IDUGKS_E_INVALID, "null argument");
+    idugks_status s = flux_pipeline(x);
+    if (s != IDUGKS_OK) return s;
+    return copy_out(x, MW, x->p.MW, sizeof(double) * 4 * x->p.nc, on_host);
+}
+
+idugks_status idugks_predict(idugks_ctx *x, double *Wstar, double *dt_imp, int32_t on_host) {
+    if (!x) return fail(IDUGKS_E_INVALID, "null context");
+    idugks_status s = flux_pipeline(x);
+    if (s != IDUGKS_OK) return s;
+    RUN(KID_MACRO, launch_macro(x->p, x->st));
+    const int nc = x->p.nc;
+    std::vector<double> W(4 * nc), dW(4 * nc);
+    HIPCHK(hipMemcpyAsync(W.data(), x->p.Wc, sizeof(double) * 4 * nc, hipMemcpyDeviceToHost, x->st));
+    HIPCHK(hipMemcpyAsync(dW.data(), x->p.dW, sizeof(double) * 4 * nc, hipMemcpyDeviceToHost, x->st));
+    HIPCHK(hipStreamSynchronize(x->st));
+    for (int i = 0; i < 4 * nc; ++i) W[i] += dW[i];
+    if (Wstar) {
+        HIPCHK(hipMemcpyAsync(Wstar, W.data(), sizeof(double) * 4 * nc,
+                              on_host ? hipMemcpyHostToHost : hipMemcpyHostToDevice, x->st));
+    }
+    if (dt_imp) {
+        HIPCHK(hipMemcpyAsync(dt_imp, x->p.dtimp, sizeof(double) * nc,
+                              on_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, x->st));
+    }
+    HIPCHK(hipStreamSynchronize(x->st));
+    return IDUGKS_OK;
+}
+
+idugks_status idugks_residual(idugks_ctx *x, double out_l2[4]) {
+    if (!x || !out_l2) return fail(IDUGKS_E_INVALID, "null argument");
+    const int nc = x->p.nc;
+    std::vector<double> MW(4 * nc);
+    idugks_status s = idugks_macro_residual(x, MW.data(), 1);
+    if (s != IDUGKS_OK) return s;
+    for (int a = 0; a < 4; ++a) {
+        double acc = 0.0;
+        for (int c = 0; c < nc; ++c) {
+            const double r = MW[4 * c + a] / x->area_h[c];
+            acc += r * r;
+        }
+        out_l2[a] = sqrt(acc / nc);
+    }
+    return IDUGKS_OK;
+}
+
+idugks_status idugks_moments(idugks_ctx *x, double *out, int32_t out_on_host) {
+    if (!x || !out) return fail(IDUGKS_E_INVALID, "null argument");
+    HIPCHK(launch_raw(x->p, x->fp32, NM_MAX, x->st));
+    HIPCHK(launch_fields(x->p, x->p.part, x->st));
+    return copy_out(x, out, x->p.part, sizeof(double) * 8 * x->p.nc, out_on_host);
+}
+
+idugks_status idugks_get_state(idugks_ctx *x, double *f, int32_t on_host) {
+    if (!x || !f) return fail(IDUGKS_E_INVALID, "null argument");
+    const size_t n = (size_t)x->p.nc * x->p.nv;
+    for (int sp = 0; sp < 2; ++sp) {
+        double *dst = on_host ? x->stage : f + sp * n;
+        HIPCHK(launch_pack(x->p, x->fp32, x->p.f, dst, sp, 1, 1, x->st));
+        if (on_host) {
+            idugks_status s = copy_out(x, f + sp * n, x->stage, n * sizeof(double), 1);
+            if (s != IDUGKS_OK) return s;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(x->st));
+    return IDUGKS_OK;
+}
+
+idugks_status idugks_set_state(idugks_ctx *x, const double *f, int32_t on_host) {
+    if (!x || !f) return fail(IDUGKS_E_INVALID, "null argument");
+    const size_t n = (size_t)x->p.nc * x->p.nv;
+    for (int sp = 0; sp < 2; ++sp) {
+        const double *src = f + sp * n;
+        if (on_host) {
+            HIPCHK(hipMemcpyAsync(x->stage, src, n * sizeof(double), hipMemcpyHostToDevice, x->st));
+            src = x->stage;
+        }
+        HIPCHK(launch_unpack(x->p, x->fp32, src, sp, 1, x->st));
+        HIPCHK(hipStreamSynchronize(x->st));
+    }
+    HIPCHK(hipMemsetAsync(x->p.rho_old, 0, sizeof(double) * x->p.nc, x->st));
+    HIPCHK(hipMemsetAsync(x->p.drho, 0, sizeof(double) * x->p.nf, x->st));
+    idugks_status s = finalize_state(x, 0);
+    double sc[SC_NUM];
+    if (s == IDUGKS_OK) s = read_scalars(x, sc);
+    if (s != IDUGKS_OK) return s;
+    x->p.M0 = sc[SC_MASS];
+    x->iters = 0;
+    return IDUGKS_OK;
+}
+
+int32_t idugks_num_kernels(void) { return KID_COUNT; }
+
+const char *idugks_kernel_name(int32_t k) { return (k >= 0 && k < KID_COUNT) ? kKernelNames[k] : ""; }
+
+idugks_status idugks_profile(idugks_ctx *x, int32_t mode, int32_t nsteps, double *ms, int64_t *counts) {
+    if (!x || !ms) return fail(IDUGKS_E_INVALID, "null argument");
+    for (int k = 0; k < KID_COUNT; ++k) { x->ms[k] = 0.0; x->cnt[k] = 0; }
+    x->prof = true;
+    x->ev_used = 0;
+    idugks_status s = idugks_step(x, mode, nsteps, nullptr);
+    x->prof = false;
+    HIPCHK(hipStreamSynchronize(x->st));
+    for (size_t i = 0; i < x->ev_used; ++i) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, x->evs[2 * i], x->evs[2 * i + 1]));
+        x->ms[x->ev_kid[i]] += ms;
+        x->cnt[x->ev_kid[i]] += 1;
+    }
+    for (int k = 0; k < KID_COUNT; ++k) {
+        ms[k] = x->ms[k];
+        if (counts) counts[k] = x->cnt[k];
+    }
+    return s;
+}
+
+}  // extern "C"

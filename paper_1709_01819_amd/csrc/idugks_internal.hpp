@@ -1,0 +1,92 @@
+// Internal data layout shared by the host orchestration and the HIP kernels.
+//
+// HBM layout (all arrays carved from the caller's workspace, 256-byte aligned):
+//   f    [nc][2][nvp]  S   transformed distributions G~, H~, velocity innermost
+//   d1   [nc][2][nvp]  S   flux sum M -> forward-sweep increment -> final increment
+//   tab  [nc][nvx+nvy] S   factored Maxwellian of the cell records:
+//                          E(ix,iy) = tab[ix] * tab[nvx+iy]
+//   tabs [nc][nvx+nvy] S   same for the predicted records
+//   tabf [nf][nvx+nvy] S   same for the face records
+//   rec, recs [nc], recf [nf]   FP64 equilibrium records
+//   part [nc][4][NM]   FP64 partial face moments, one slot per cell side
+//   raw  [nc][NM]      FP64 raw moments of the stored state
+// S is double (FP64 form) or float (FP32-mixed form).  nvp = nv rounded up to 64.
+#pragma once
+
+#include <stdint.h>
+
+namespace idugks {
+
+enum FaceType : int { FT_INTERIOR = 0, FT_SELF = 1, FT_WALL = 2, FT_FAR = 3 };
+
+constexpr int NM_BGK = 4;      // raw moments: 1, xi, eta, (|xi|^2 G + H)/2
+constexpr int NM_SHAKHOV = 12; // + xi^2, xi eta, eta^2, xi|xi|^2, eta|xi|^2 (G); 1, xi, eta (H)
+constexpr int NM_MAX = 12;
+constexpr int VPAD = 64;
+
+// One side (i-, i+, j-, j+) of one cell.
+struct CellSide {
+    int nb;        // neighbour cell, -1 at a boundary (may be the cell itself: self-periodic)
+    int face;      // face index
+    int type;      // FaceType
+    int tie;       // 1 if this cell is upwind for xi.n_out == 0 (R end of interior, far field)
+    int wside;     // boundary side (0..3) of wall / far-field faces
+    int hp_adj;    // 1 if nb is on the adjacent i+j hyperplane (not a periodic wrap)
+    int pad0, pad1;
+    double nx, ny; // outward unit normal
+    double S;      // face length
+    double dx, dy; // face midpoint (own frame) minus own centroid
+    double ndx, ndy; // neighbour image centroid minus own centroid
+    double ax, ay; // least-squares gradient weights of the neighbour (Eq. 15)
+};
+
+struct Face {
+    int L, R;      // cells (R = -1 at a boundary; L = R for self-periodic faces)
+    int sL, sR;    // side index of the face in L and in R
+    int type, wside, pad0, pad1;
+    double nx, ny, S; // unit normal from L to R (outward of L at a boundary)
+};
+
+// Equilibrium record.  With cx = xi - U, cy = eta - V, c2 = cx^2 + cy^2,
+// P = kqx cx + kqy cy and E = tab[ix] * tab[nvx + iy]:
+//   G_eq = E (c0 + c1 cx + c2c cy + c3 c2 + P (c2 iRT - 4))
+//   H_eq = KRT E (c0 + c1 cx + c2c cy + c3 c2 + P (c2 iRT - 2))
+struct Rec {
+    double rho, U, V, RT, tau;
+    double qx, qy;           // Shakhov heat flux entering the equilibrium
+    double c0, c1, c2c, c3;  // discrete-conservation correction (central basis)
+    double kqx, kqy;         // (1 - Pr)/(5 p RT) * q
+    double iRT, KRT;
+    double ab, bb;           // cells: phi-bar-plus = ab phi~ + bb phi_eq (Eq. 10, 12)
+    double alpha;            // faces: 2 tau / (2 tau + h) (Eq. 18)
+    double rw;               // wall faces: density of the reflected Maxwellian
+};
+
+// Scalars kept on the device (FP64).
+enum Scalar : int { SC_SCALE = 0, SC_RES = 1, SC_MASS = 2, SC_FLAG = 3, SC_NUM = 8 };
+
+struct Params {
+    int ni, nj, nc, nf, nv, nvp, nvx, nvy, K, model, limiter, closed, nm, nwall;
+    double dt, h, Pr, mu_ref, omega, cfl_imp, M0, gam;
+    // velocity set
+    const double *xi, *eta, *w;
+    const double *x1, *wx1, *y1, *wy1;  // 1D nodes and weights
+    const int16_t *vix, *viy;
+    // geometry
+    const double *area;
+    const CellSide *cs;      // [nc][4]
+    const Face *faces;       // [nf]
+    const int *wall_faces;   // [nwall]
+    // boundary distributions
+    const double *gw;        // [4][nvp] G of the wall Maxwellian at unit density
+    const double *wKRT;      // [4] K RT of each wall side
+    const double *ginf, *hinf; // [nvp] free-stream equilibrium
+    const double *wden;      // [nf] sum over incoming v of w (xi.n) gw
+    const double *bhalf;     // [nf][NM] moments of the incoming half of the ghost distribution
+    // state and work (S-typed arrays as void*)
+    void *f, *d1, *tab, *tabs, *tabf;
+    Rec *rec, *recs, *recf;
+    double *part, *raw, *Wc, *MW, *dW, *DWd, *dtimp, *rho_old, *drho, *scal;
+};
+
+}  // namespace idugks

@@ -1,0 +1,1033 @@
+// HIP kernels (gfx950) of the implicit DUGKS hot path.
+//
+// Paper: Pan, Zhong & Zhuo, arXiv:1709.01819.  One implicit iteration is
+//   records    cell equilibrium records from the conserved moments (Eq. 2, 4, 20)
+//   partials   phi-bar-plus (Eq. 10, 12), least-squares gradient and limiter (Eq. 14-17),
+//              upwind reconstruction at the faces (Eq. 11, 13) reduced to partial moments
+//   face rec   face moments, wall density, face equilibrium (moments of phi-bar, Eq. 18)
+//   flux       interface distribution (Eq. 18), flux (Eq. 19), M_i(v) (Eq. 23), M_W (Eq. 27)
+//   macro      predicted macroscopic LU-SGS (Eq. 28-31) on i+j hyperplanes
+//   records*   predicted equilibrium
+//   lower      forward micro sweep of Eq. 26 over hyperplanes, all velocities in parallel
+//   ghost      wall ghost density increment from the forward sweep (Eq. 34-35)
+//   upper      backward sweep and update (Eq. 32)
+//   raw        raw moments of the new state
+//   finalize   closed-domain mass scale, density-change residual, divergence flag
+// Nothing here is a dense contraction: every kernel streams [cell][species][v] rows and
+// reduces over v with wave shuffles and an LDS tree in fixed order (no atomics).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "idugks_internal.hpp"
+#include "idugks_kernels.hpp"
+
+namespace idugks {
+
+#define DEV __device__ __forceinline__
+
+// ---------------------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------------------
+
+// Block b of n is dispatched to XCD b % 8; give each XCD a contiguous range of cells so
+// that neighbouring cells share an L2.
+DEV int xcd_remap(int b, int n) {
+    const int x = b & 7, local = b >> 3, per = n >> 3, rem = n & 7;
+    return x * per + (x < rem ? x : rem) + local;
+}
+
+template <int N>
+DEV void wave_sum(double (&a)[N]) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        double x = a[m];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        a[m] = __shfl(x, 0, 64);  // every lane takes lane 0's (deterministic) sum
+    }
+}
+
+// Sum over the whole block; sh must hold (blockDim/64)*N doubles.  Fixed order.
+template <int N>
+DEV void block_sum(double (&a)[N], double *sh) {
+    wave_sum<N>(a);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int m = 0; m < N; ++m) sh[wid * N + m] = a[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += sh[w * N + m];
+        a[m] = s;
+    }
+    __syncthreads();
+}
+
+template <class T>
+struct RecT {
+    T U, V, c0, c1, c2c, c3, kqx, kqy, iRT, KRT, ab, bb;
+};
+
+template <class T>
+DEV RecT<T> load_rec(const Rec &r) {
+    RecT<T> o;
+    o.U = (T)r.U; o.V = (T)r.V; o.c0 = (T)r.c0; o.c1 = (T)r.c1; o.c2c = (T)r.c2c;
+    o.c3 = (T)r.c3; o.kqx = (T)r.kqx; o.kqy = (T)r.kqy; o.iRT = (T)r.iRT; o.KRT = (T)r.KRT;
+    o.ab = (T)r.ab; o.bb = (T)r.bb;
+    return o;
+}
+
+// Equilibrium pair at velocity (x, y) from a record and the factored Maxwellian E.
+template <class T, bool SHAK>
+DEV void eq_eval(const RecT<T> &r, T x, T y, T E, T &G, T &H) {
+    const T cx = x - r.U, cy = y - r.V, c2 = cx * cx + cy * cy;
+    const T base = r.c0 + r.c1 * cx + r.c2c * cy + r.c3 * c2;
+    if (SHAK) {
+        const T P = r.kqx * cx + r.kqy * cy;
+        G = E * (base + P * (c2 * r.iRT - T(4)));
+        H = r.KRT * E * (base + P * (c2 * r.iRT - T(2)));
+    } else {
+        G = E * base;
+        H = r.KRT * G;
+    }
+}
+
+template <class S>
+DEV const S *rowp(const Params &p, const void *a, int c, int s) {
+    return (const S *)a + ((size_t)c * 2 + s) * p.nvp;
+}
+
+// Raw moments of a pair at one velocity, accumulated in double.
+template <int NM>
+DEV void acc_moments(double (&a)[NM], double w, double x, double y, double G, double H) {
+    const double wG = w * G, wH = w * H, q2 = x * x + y * y;
+    a[0] += wG;
+    a[1] += wG * x;
+    a[2] += wG * y;
+    a[3] += 0.5 * (wG * q2 + wH);
+    if (NM > 4) {
+        a[4] += wG * x * x;
+        a[5] += wG * x * y;
+        a[6] += wG * y * y;
+        a[7] += wG * x * q2;
+        a[8 % NM] += wG * y * q2;
+        a[9 % NM] += wH;
+        a[10 % NM] += wH * x;
+        a[11 % NM] += wH * y;
+    }
+}
+
+// Heat flux about (U, V) from raw moments (q = sum w c (|c|^2 G + H)/2).
+DEV void heat_from_raw(const double *m, double U, double V, double &qx, double &qy) {
+    const double UU = U * U + V * V;
+    const double sx = m[7] - 2.0 * (U * m[4] + V * m[5]) + UU * m[1] - U * (m[4] + m[6]) +
+                      2.0 * U * (U * m[1] + V * m[2]) - U * UU * m[0];
+    const double sy = m[8] - 2.0 * (U * m[5] + V * m[6]) + UU * m[2] - V * (m[4] + m[6]) +
+                      2.0 * V * (U * m[1] + V * m[2]) - V * UU * m[0];
+    qx = 0.5 * (sx + m[10] - U * m[9]);
+    qy = 0.5 * (sy + m[11] - V * m[9]);
+}
+
+// Normal particle speed at a face; velocities tangent to the face within 1e-12 of their
+// speed have normal speed exactly 0, so the upwind/tie classification does not depend on
+// the rounding (or FMA contraction) of xi.n.  Always evaluated in FP64.
+DEV double normal_speed(double x, double y, double nx, double ny) {
+    const double un = x * nx + y * ny;
+    return fabs(un) <= 1e-12 * (fabs(x) + fabs(y)) ? 0.0 : un;
+}
+
+DEV double tau_of(const Params &p, double rho, double RT) {
+    return p.mu_ref * pow(2.0 * RT, p.omega) / (rho * RT);
+}
+
+DEV void solve4(double A[4][4], double b[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int piv = k;
+        for (int r = k + 1; r < 4; ++r)
+            if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
+        if (piv != k) {
+            for (int c = 0; c < 4; ++c) {
+                double t = A[k][c]; A[k][c] = A[piv][c]; A[piv][c] = t;
+            }
+            double t = b[k]; b[k] = b[piv]; b[piv] = t;
+        }
+        for (int r = k + 1; r < 4; ++r) {
+            double m = A[r][k] / A[k][k];
+            for (int c = k; c < 4; ++c) A[r][c] -= m * A[k][c];
+            b[r] -= m * b[k];
+        }
+    }
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+        double s = b[k];
+        for (int c = k + 1; c < 4; ++c) s -= A[k][c] * b[c];
+        b[k] = s / A[k][k];
+    }
+}
+
+// Equilibrium record with exact discrete conserved moments, built by one wave.
+// G_M = A0 ex(cx) ey(cy) with A0 = rho lambda/pi; the correction lives in the span of
+// psi = (1, cx, cy, |c|^2/2) (the same span as the conserved-moment weights) and solves
+// A beta = (rho, 0, 0, rho RT) - sum w psi G_M, with A assembled from 1D central moments
+// X_p = sum_ix w_ix cx^p ex, Y_p likewise.  Shakhov (monatomic reduced form of Eq. 20):
+// dG = k P (|c|^2/RT - 4) G_M, dH = k P K (|c|^2/RT - 2) RT G_M, k = (1-Pr)/(5 p RT),
+// P = c.q, projected out of the conserved moments with the same A.
+template <class S, bool SHAK>
+DEV void build_eq(const Params &p, double rho, double U, double V, double RT, double tau,
+                  double qx, double qy, Rec *out, S *tab, int lane) {
+    constexpr int NP = SHAK ? 6 : 5;
+    const double lam = 0.5 / RT, A0 = rho * lam / M_PI;
+    double X[NP], Y[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) X[k] = Y[k] = 0.0;
+    for (int ix = lane; ix < p.nvx; ix += 64) {
+        const double cx = p.x1[ix] - U, e = exp(-lam * cx * cx);
+        tab[ix] = (S)(A0 * e);
+        double t = p.wx1[ix] * e;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) { X[k] += t; t *= cx; }
+    }
+    for (int iy = lane; iy < p.nvy; iy += 64) {
+        const double cy = p.y1[iy] - V, e = exp(-lam * cy * cy);
+        tab[p.nvx + iy] = (S)e;
+        double t = p.wy1[iy] * e;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) { Y[k] += t; t *= cy; }
+    }
+    wave_sum<NP>(X);
+    wave_sum<NP>(Y);
+    auto m = [&](int a, int b) { return A0 * X[a] * Y[b]; };
+    double A[4][4], Ac[4][4], r[4];
+    A[0][0] = m(0, 0); A[0][1] = m(1, 0); A[0][2] = m(0, 1); A[0][3] = 0.5 * (m(2, 0) + m(0, 2));
+    A[1][1] = m(2, 0); A[1][2] = m(1, 1); A[1][3] = 0.5 * (m(3, 0) + m(1, 2));
+    A[2][2] = m(0, 2); A[2][3] = 0.5 * (m(2, 1) + m(0, 3));
+    A[3][3] = 0.25 * (m(4, 0) + 2.0 * m(2, 2) + m(0, 4));
+    for (int a = 1; a < 4; ++a)
+        for (int b = 0; b < a; ++b) A[a][b] = A[b][a];
+    r[0] = rho - A[0][0];
+    r[1] = -A[0][1];
+    r[2] = -A[0][2];
+    r[3] = rho * RT - A[0][3];
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) Ac[a][b] = A[a][b];
+    solve4(Ac, r);
+    double kap = 0.0;
+    if (SHAK && (qx != 0.0 || qy != 0.0)) {
+        kap = (1.0 - p.Pr) / (5.0 * rho * RT * RT);
+        const double iRT = 1.0 / RT, e0 = 0.5 * p.K * RT;
+        // sum w g P (|c|^2/RT - a) G_M for g = 1, cx, cy, |c|^2/2
+        const double g1x = (m(3, 0) + m(1, 2)) * iRT, g1y = (m(2, 1) + m(0, 3)) * iRT;
+        double d[4];
+        d[0] = qx * (g1x - 4.0 * m(1, 0)) + qy * (g1y - 4.0 * m(0, 1));
+        d[1] = qx * ((m(4, 0) + m(2, 2)) * iRT - 4.0 * m(2, 0)) +
+               qy * ((m(3, 1) + m(1, 3)) * iRT - 4.0 * m(1, 1));
+        d[2] = qx * ((m(3, 1) + m(1, 3)) * iRT - 4.0 * m(1, 1)) +
+               qy * ((m(2, 2) + m(0, 4)) * iRT - 4.0 * m(0, 2));
+        const double eG = 0.5 * (qx * ((m(5, 0) + 2.0 * m(3, 2) + m(1, 4)) * iRT -
+                                       4.0 * (m(3, 0) + m(1, 2))) +
+                                 qy * ((m(4, 1) + 2.0 * m(2, 3) + m(0, 5)) * iRT -
+                                       4.0 * (m(2, 1) + m(0, 3))));
+        const double eH = 0.5 * p.K * RT *
+                          (qx * (g1x - 2.0 * m(1, 0)) + qy * (g1y - 2.0 * m(0, 1)));
+        d[3] = eG + eH - e0 * d[0];
+        for (int a = 0; a < 4; ++a) {
+            d[a] *= kap;
+            for (int b = 0; b < 4; ++b) Ac[a][b] = A[a][b];
+        }
+        solve4(Ac, d);
+        for (int a = 0; a < 4; ++a) r[a] -= d[a];
+    }
+    if (lane == 0) {
+        Rec o;
+        o.rho = rho; o.U = U; o.V = V; o.RT = RT; o.tau = tau; o.qx = qx; o.qy = qy;
+        o.c0 = 1.0 + r[0]; o.c1 = r[1]; o.c2c = r[2]; o.c3 = 0.5 * r[3];
+        o.kqx = kap * qx; o.kqy = kap * qy; o.iRT = 1.0 / RT; o.KRT = p.K * RT;
+        o.ab = (2.0 * tau - p.h) / (2.0 * tau + p.dt);
+        o.bb = 3.0 * p.h / (2.0 * tau + p.dt);
+        o.alpha = 2.0 * tau / (2.0 * tau + p.h);
+        o.rw = 0.0;
+        *out = o;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// raw moments of the stored state, one block per cell
+// ---------------------------------------------------------------------------------------
+template <class S, int NM>
+__global__ __launch_bounds__(256) void k_raw(Params p) {
+    __shared__ double sh[4 * NM];
+    const int c = xcd_remap(blockIdx.x, p.nc);
+    const S *G = rowp<S>(p, p.f, c, 0), *H = rowp<S>(p, p.f, c, 1);
+    double a[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) a[m] = 0.0;
+    for (int v = threadIdx.x; v < p.nv; v += blockDim.x)
+        acc_moments<NM>(a, p.w[v], p.xi[v], p.eta[v], (double)G[v], (double)H[v]);
+    block_sum<NM>(a, sh);
+    if (threadIdx.x < NM) p.raw[(size_t)c * NM_MAX + threadIdx.x] = a[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------------------
+// finalize: closed-domain mass scale, residual, divergence flag (one block)
+// mode 0: after init/set_state (scale 1, no residual); 1: implicit; 2: explicit
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_finalize(Params p, int mode) {
+    __shared__ double sh[16 * 3];
+    const int NM = NM_MAX;
+    double a[1] = {0.0};
+    for (int c = threadIdx.x; c < p.nc; c += blockDim.x) a[0] += p.area[c] * p.raw[(size_t)c * NM];
+    block_sum<1>(a, sh);
+    const double mass = a[0];
+    const double s = (mode == 1 && p.closed) ? p.M0 / mass : 1.0;
+    double b[3] = {0.0, 0.0, 0.0};
+    for (int c = threadIdx.x; c < p.nc; c += blockDim.x) {
+        const double r = s * p.raw[(size_t)c * NM], d = r - p.rho_old[c];
+        b[0] += d * d;
+        b[1] += r * r;
+        const double e = s * p.raw[(size_t)c * NM + 3];
+        if (!(r > 0.0) || !(e > 0.0) || !isfinite(r) || !isfinite(e)) b[2] += 1.0;
+        p.rho_old[c] = r;
+    }
+    block_sum<3>(b, sh);
+    if (threadIdx.x == 0) {
+        p.scal[SC_SCALE] = s;
+        p.scal[SC_MASS] = s * mass;
+        p.scal[SC_RES] = mode == 0 ? 0.0 : sqrt(b[0] / b[1]);
+        p.scal[SC_FLAG] = b[2];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// equilibrium records.  which 0: cell records from the scaled raw moments (W^n, q^n);
+// which 1: predicted records from W* = W^n + dW with the heat flux of step n.
+// One wave per cell, four cells per block.
+// ---------------------------------------------------------------------------------------
+template <class S, bool SHAK>
+__global__ __launch_bounds__(256) void k_records(Params p, int which) {
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= p.nc) return;
+    const int NM = NM_MAX;
+    const int TW = p.nvx + p.nvy;
+    double W[4], qx = 0.0, qy = 0.0;
+    if (which == 0) {
+        const double s = p.scal[SC_SCALE];
+        const double *m = p.raw + (size_t)c * NM;
+        for (int a = 0; a < 4; ++a) W[a] = s * m[a];
+        for (int a = 0; a < 4; ++a) p.Wc[(size_t)c * 4 + a] = W[a];
+    } else {
+        for (int a = 0; a < 4; ++a) W[a] = p.Wc[(size_t)c * 4 + a] + p.dW[(size_t)c * 4 + a];
+    }
+    const double rho = W[0], U = W[1] / rho, V = W[2] / rho;
+    const double RT = (2.0 * W[3] / rho - U * U - V * V) / (p.K + 2);
+    const double tau = tau_of(p, rho, RT);
+    if (SHAK) {
+        if (which == 0) {
+            double mm[12];
+            const double s = p.scal[SC_SCALE];
+            for (int a = 0; a < 12; ++a) mm[a] = s * p.raw[(size_t)c * NM + a];
+            double qtx, qty;
+            heat_from_raw(mm, U, V, qtx, qty);
+            const double t2 = 2.0 * tau;
+            qx = t2 * qtx / (t2 + p.dt * p.Pr);
+            qy = t2 * qty / (t2 + p.dt * p.Pr);
+        } else {
+            qx = p.rec[c].qx;
+            qy = p.rec[c].qy;
+        }
+    }
+    Rec *out = which == 0 ? p.rec + c : p.recs + c;
+    S *tab = (S *)(which == 0 ? p.tab : p.tabs) + (size_t)c * TW;
+    build_eq<S, SHAK>(p, rho, U, V, RT, tau, qx, qy, out, tab, lane);
+}
+
+// ---------------------------------------------------------------------------------------
+// phi-bar-plus (Eq. 10 and Eq. 12 combined) and the limited least-squares gradient
+// ---------------------------------------------------------------------------------------
+template <class S, class T, bool SHAK>
+DEV void barplus(const Params &p, int j, int v, int ix, int iy, T x, T y, T sc, T &bG, T &bH) {
+    const RecT<T> r = load_rec<T>(p.rec[j]);
+    const S *tb = (const S *)p.tab + (size_t)j * (p.nvx + p.nvy);
+    const T E = (T)tb[ix] * (T)tb[p.nvx + iy];
+    T eG, eH;
+    eq_eval<T, SHAK>(r, x, y, E, eG, eH);
+    const T XG = sc * (T)rowp<S>(p, p.f, j, 0)[v], XH = sc * (T)rowp<S>(p, p.f, j, 1)[v];
+    bG = r.ab * XG + r.bb * eG;
+    bH = r.ab * XH + r.bb * eH;
+}
+
+template <class T>
+DEV T venkat(T x) { return (x * x + T(2) * x) / (x * x + x + T(2)); }
+
+template <class T>
+DEV T limiter_phi(const CellSide *cs, T b0, T bmax, T bmin, T gx, T gy) {
+    T phi = T(1);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const T d = gx * (T)cs[s].dx + gy * (T)cs[s].dy;
+        T th = T(1);
+        if (d > T(0)) th = venkat<T>((bmax - b0) / d);
+        else if (d < T(0)) th = venkat<T>((bmin - b0) / d);
+        phi = th < phi ? th : phi;
+    }
+    return phi;
+}
+
+template <class S, class T, bool SHAK, bool LIM>
+DEV void recon_cell(const Params &p, int j, int v, int ix, int iy, T x, T y, T sc, T &bG, T &bH,
+                    T &gxG, T &gyG, T &gxH, T &gyH) {
+    const CellSide *cs = p.cs + 4 * j;
+    barplus<S, T, SHAK>(p, j, v, ix, iy, x, y, sc, bG, bH);
+    gxG = gyG = gxH = gyH = T(0);
+    T mxG = bG, mnG = bG, mxH = bH, mnH = bH;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int n = cs[s].nb;
+        if (n < 0) continue;
+        T nG, nH;
+        barplus<S, T, SHAK>(p, n, v, ix, iy, x, y, sc, nG, nH);
+        const T ax = (T)cs[s].ax, ay = (T)cs[s].ay, dG = nG - bG, dH = nH - bH;
+        gxG += ax * dG; gyG += ay * dG; gxH += ax * dH; gyH += ay * dH;
+        if (LIM) {
+            mxG = nG > mxG ? nG : mxG; mnG = nG < mnG ? nG : mnG;
+            mxH = nH > mxH ? nH : mxH; mnH = nH < mnH ? nH : mnH;
+        }
+    }
+    if (LIM) {
+        const T pG = limiter_phi<T>(cs, bG, mxG, mnG, gxG, gyG);
+        const T pH = limiter_phi<T>(cs, bH, mxH, mnH, gxH, gyH);
+        gxG *= pG; gyG *= pG; gxH *= pH; gyH *= pH;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// partial face moments: each cell reduces, for each of its faces, the moments of the
+// reconstructed phi-bar over the velocities for which it is the upwind cell
+// ---------------------------------------------------------------------------------------
+template <class S, bool SHAK, bool LIM>
+__global__ __launch_bounds__(256) void k_partials(Params p) {
+    using T = S;
+    constexpr int NM = SHAK ? NM_SHAKHOV : NM_BGK;
+    __shared__ double sh[4 * 4 * NM];
+    const int c = xcd_remap(blockIdx.x, p.nc);
+    const CellSide *cs = p.cs + 4 * c;
+    const T sc = (T)p.scal[SC_SCALE], h = (T)p.h;
+    double acc[4 * NM];
+#pragma unroll
+    for (int m = 0; m < 4 * NM; ++m) acc[m] = 0.0;
+    for (int v = threadIdx.x; v < p.nv; v += blockDim.x) {
+        const int ix = p.vix[v], iy = p.viy[v];
+        const T x = (T)p.xi[v], y = (T)p.eta[v];
+        T bG, bH, gxG, gyG, gxH, gyH;
+        recon_cell<S, T, SHAK, LIM>(p, c, v, ix, iy, x, y, sc, bG, bH, gxG, gyG, gxH, gyH);
+        const double wv = p.w[v];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (cs[s].type == FT_SELF) continue;
+            const double un = normal_speed(p.xi[v], p.eta[v], cs[s].nx, cs[s].ny);
+            if (!(un > 0.0 || (un == 0.0 && cs[s].tie))) continue;
+            const T rx = (T)cs[s].dx - h * x, ry = (T)cs[s].dy - h * y;
+            const T G = bG + gxG * rx + gyG * ry, H = bH + gxH * rx + gyH * ry;
+            double a[NM];
+#pragma unroll
+            for (int m = 0; m < NM; ++m) a[m] = 0.0;
+            acc_moments<NM>(a, wv, (double)x, (double)y, (double)G, (double)H);
+#pragma unroll
+            for (int m = 0; m < NM; ++m) acc[s * NM + m] += a[m];
+        }
+    }
+    block_sum<4 * NM>(acc, sh);
+    if (threadIdx.x < 4 * NM) p.part[(size_t)c * 4 * NM + threadIdx.x] = acc[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------------------
+// face records: moments of phi-bar at every face, wall density (zero normal mass flux),
+// face equilibrium (heat flux 2 tau qbar / (2 tau + h Pr)).  One wave per face.
+// ---------------------------------------------------------------------------------------
+template <class S, bool SHAK>
+__global__ __launch_bounds__(256) void k_face_records(Params p) {
+    constexpr int NM = SHAK ? NM_SHAKHOV : NM_BGK;
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= p.nf) return;
+    const Face F = p.faces[k];
+    if (F.type == FT_SELF) return;
+    double m[NM];
+    const double *a = p.part + ((size_t)F.L * 4 + F.sL) * NM;
+    for (int i = 0; i < NM; ++i) m[i] = a[i];
+    double rw = 0.0;
+    if (F.type == FT_INTERIOR) {
+        const double *b = p.part + ((size_t)F.R * 4 + F.sR) * NM;
+        for (int i = 0; i < NM; ++i) m[i] += b[i];
+    } else {
+        const double *b = p.bhalf + (size_t)k * NM_MAX;
+        if (F.type == FT_WALL) rw = -(F.nx * m[1] + F.ny * m[2]) / p.wden[k];
+        const double sc = F.type == FT_WALL ? rw : 1.0;
+        for (int i = 0; i < NM; ++i) m[i] += sc * b[i];
+    }
+    const double rho = m[0], U = m[1] / rho, V = m[2] / rho;
+    const double RT = (2.0 * m[3] / rho - U * U - V * V) / (p.K + 2);
+    const double tau = tau_of(p, rho, RT);
+    double qx = 0.0, qy = 0.0;
+    if (SHAK) {
+        double qbx, qby;
+        heat_from_raw(m, U, V, qbx, qby);
+        const double t2 = 2.0 * tau;
+        qx = t2 * qbx / (t2 + p.h * p.Pr);
+        qy = t2 * qby / (t2 + p.h * p.Pr);
+    }
+    S *tab = (S *)p.tabf + (size_t)k * (p.nvx + p.nvy);
+    build_eq<S, SHAK>(p, rho, U, V, RT, tau, qx, qy, p.recf + k, tab, lane);
+    if (lane == 0) p.recf[k].rw = rw;
+}
+
+// ---------------------------------------------------------------------------------------
+// flux: M_i(v) = -sum_k S (xi.n_out) phi_k (Eq. 18, 19, 23) and M_W = sum w psi M (Eq. 27)
+// ---------------------------------------------------------------------------------------
+template <class S, bool SHAK, bool LIM>
+__global__ __launch_bounds__(256) void k_flux(Params p) {
+    using T = S;
+    __shared__ double sh[4 * 4];
+    const int c = xcd_remap(blockIdx.x, p.nc);
+    const CellSide *cs = p.cs + 4 * c;
+    const T sc = (T)p.scal[SC_SCALE], h = (T)p.h;
+    const int TW = p.nvx + p.nvy;
+    S *MG = (S *)p.d1 + ((size_t)c * 2) * p.nvp, *MH = MG + p.nvp;
+    double mw[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int v = threadIdx.x; v < p.nv; v += blockDim.x) {
+        const int ix = p.vix[v], iy = p.viy[v];
+        const T x = (T)p.xi[v], y = (T)p.eta[v];
+        T bG, bH, gxG, gyG, gxH, gyH;
+        recon_cell<S, T, SHAK, LIM>(p, c, v, ix, iy, x, y, sc, bG, bH, gxG, gyG, gxH, gyH);
+        T accG = T(0), accH = T(0);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int type = cs[s].type;
+            if (type == FT_SELF) continue;
+            const int k = cs[s].face;
+            const double und = normal_speed(p.xi[v], p.eta[v], cs[s].nx, cs[s].ny);
+            const bool mine = und > 0.0 || (und == 0.0 && cs[s].tie);
+            const T un = (T)und;
+            T fG, fH;
+            if (mine) {
+                const T rx = (T)cs[s].dx - h * x, ry = (T)cs[s].dy - h * y;
+                fG = bG + gxG * rx + gyG * ry;
+                fH = bH + gxH * rx + gyH * ry;
+            } else if (type == FT_INTERIOR) {
+                T nG, nH, ngxG, ngyG, ngxH, ngyH;
+                recon_cell<S, T, SHAK, LIM>(p, cs[s].nb, v, ix, iy, x, y, sc, nG, nH, ngxG, ngyG,
+                                            ngxH, ngyH);
+                const T rx = (T)(cs[s].dx - cs[s].ndx) - h * x;
+                const T ry = (T)(cs[s].dy - cs[s].ndy) - h * y;
+                fG = nG + ngxG * rx + ngyG * ry;
+                fH = nH + ngxH * rx + ngyH * ry;
+            } else if (type == FT_WALL) {
+                const T rw = (T)p.recf[k].rw;
+                const T g = (T)p.gw[(size_t)cs[s].wside * p.nvp + v];
+                fG = rw * g;
+                fH = rw * (T)p.wKRT[cs[s].wside] * g;
+            } else {
+                fG = (T)p.ginf[v];
+                fH = (T)p.hinf[v];
+            }
+            const RecT<T> rf = load_rec<T>(p.recf[k]);
+            const S *tf = (const S *)p.tabf + (size_t)k * TW;
+            T eG, eH;
+            eq_eval<T, SHAK>(rf, x, y, (T)tf[ix] * (T)tf[p.nvx + iy], eG, eH);
+            const T al = (T)p.recf[k].alpha;
+            const T pG = al * fG + (T(1) - al) * eG, pH = al * fH + (T(1) - al) * eH;
+            const T fl = (T)cs[s].S * un;
+            accG -= fl * pG;
+            accH -= fl * pH;
+        }
+        MG[v] = (S)accG;
+        MH[v] = (S)accH;
+        const double wv = p.w[v], dx = (double)x, dy = (double)y, dG = (double)accG;
+        mw[0] += wv * dG;
+        mw[1] += wv * dx * dG;
+        mw[2] += wv * dy * dG;
+        mw[3] += 0.5 * wv * ((dx * dx + dy * dy) * dG + (double)accH);
+    }
+    block_sum<4>(mw, sh);
+    if (threadIdx.x < 4) p.MW[(size_t)c * 4 + threadIdx.x] = mw[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------------------
+// predicted macroscopic step: LU-SGS of Eq. 29-31 (Rusanov split, matrix-free flux
+// differences, mirrored wall ghost) over i+j hyperplanes in one block
+// ---------------------------------------------------------------------------------------
+DEV void euler_flux(const double W[4], double nx, double ny, int K, double F[4]) {
+    const double rho = W[0], U = W[1] / rho, V = W[2] / rho;
+    const double pr = (2.0 * W[3] - rho * (U * U + V * V)) / (K + 2);
+    const double un = U * nx + V * ny;
+    F[0] = rho * un;
+    F[1] = W[1] * un + pr * nx;
+    F[2] = W[2] * un + pr * ny;
+    F[3] = (W[3] + pr) * un;
+}
+
+DEV double sound(const Params &p, int c) { return sqrt(p.gam * p.rec[c].RT); }
+
+// contribution 1/2 S (F_n(W_j + dW_j) - F_n(W_j) - lambda_j dW_j) of neighbour j
+DEV void macro_term(const Params &p, int j, const CellSide &cs, const double dWj[4], double out[4]) {
+    const double *Wj = p.Wc + (size_t)j * 4;
+    const double lam = fabs((Wj[1] * cs.nx + Wj[2] * cs.ny) / Wj[0]) + sound(p, j);
+    double Wn[4], F1[4], F0[4];
+    for (int a = 0; a < 4; ++a) Wn[a] = Wj[a] + dWj[a];
+    euler_flux(Wn, cs.nx, cs.ny, p.K, F1);
+    euler_flux(Wj, cs.nx, cs.ny, p.K, F0);
+    for (int a = 0; a < 4; ++a) out[a] = 0.5 * cs.S * (F1[a] - F0[a] - lam * dWj[a]);
+}
+
+__global__ __launch_bounds__(1024) void k_macro(Params p) {
+    extern __shared__ double front[];  // [2][ni][4]
+    const int ni = p.ni, nj = p.nj, nh = ni + nj - 1;
+    // diagonal and implicit time step
+    for (int c = threadIdx.x; c < p.nc; c += blockDim.x) {
+        const CellSide *cs = p.cs + 4 * c;
+        const double U = p.rec[c].U, V = p.rec[c].V, C = sound(p, c);
+        double ls = 0.0, lw = 0.0;
+        for (int s = 0; s < 4; ++s) {
+            if (cs[s].type == FT_SELF) continue;
+            const double l = (fabs(U * cs[s].nx + V * cs[s].ny) + C) * cs[s].S;
+            ls += l;
+            if (cs[s].type == FT_WALL) lw += l;
+        }
+        const double dti = p.cfl_imp * p.area[c] / ls;
+        p.dtimp[c] = dti;
+        p.DWd[c] = p.area[c] / dti + 0.5 * ls + 0.5 * lw;
+    }
+    __syncthreads();
+    double *f0 = front, *f1 = front + 4 * ni;
+    // lower sweep
+    for (int s = 0; s < nh; ++s) {
+        const int ilo = s - nj + 1 > 0 ? s - nj + 1 : 0, ihi = s < ni - 1 ? s : ni - 1;
+        for (int i = ilo + threadIdx.x; i <= ihi; i += blockDim.x) {
+            const int c = i + (s - i) * ni;
+            const CellSide *cs = p.cs + 4 * c;
+            double r[4];
+            for (int a = 0; a < 4; ++a) r[a] = p.MW[(size_t)c * 4 + a];
+            for (int sd = 0; sd < 4; ++sd) {
+                const int j = cs[sd].nb;
+                if (cs[sd].type == FT_SELF || j < 0 || j > c) continue;
+                double dWj[4], t[4];
+                if (cs[sd].hp_adj) {
+                    const int ij = j % ni;
+                    for (int a = 0; a < 4; ++a) dWj[a] = f0[4 * ij + a];
+                } else {
+                    for (int a = 0; a < 4; ++a) dWj[a] = p.dW[(size_t)j * 4 + a];
+                }
+                macro_term(p, j, cs[sd], dWj, t);
+                for (int a = 0; a < 4; ++a) r[a] -= t[a];
+            }
+            const double D = p.DWd[c];
+            for (int a = 0; a < 4; ++a) {
+                const double d = r[a] / D;
+                p.dW[(size_t)c * 4 + a] = d;
+                f1[4 * i + a] = d;
+            }
+        }
+        __syncthreads();
+        double *t = f0; f0 = f1; f1 = t;
+    }
+    // upper sweep
+    for (int s = nh - 1; s >= 0; --s) {
+        const int ilo = s - nj + 1 > 0 ? s - nj + 1 : 0, ihi = s < ni - 1 ? s : ni - 1;
+        for (int i = ilo + threadIdx.x; i <= ihi; i += blockDim.x) {
+            const int c = i + (s - i) * ni;
+            const CellSide *cs = p.cs + 4 * c;
+            double r[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int sd = 0; sd < 4; ++sd) {
+                const int j = cs[sd].nb;
+                if (cs[sd].type == FT_SELF || j < 0 || j < c) continue;
+                double dWj[4], t[4];
+                if (cs[sd].hp_adj) {
+                    const int ij = j % ni;
+                    for (int a = 0; a < 4; ++a) dWj[a] = f0[4 * ij + a];
+                } else {
+                    for (int a = 0; a < 4; ++a) dWj[a] = p.dW[(size_t)j * 4 + a];
+                }
+                macro_term(p, j, cs[sd], dWj, t);
+                for (int a = 0; a < 4; ++a) r[a] += t[a];
+            }
+            const double D = p.DWd[c];
+            for (int a = 0; a < 4; ++a) {
+                const double d = p.dW[(size_t)c * 4 + a] - r[a] / D;
+                p.dW[(size_t)c * 4 + a] = d;
+                f1[4 * i + a] = d;
+            }
+        }
+        __syncthreads();
+        double *t = f0; f0 = f1; f1 = t;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// micro LU-SGS sweeps (Eq. 24-26) over i+j hyperplanes.  One block per (velocity slice,
+// species); lanes = VB velocities x (blockDim/VB) cells of the hyperplane.  The previous
+// hyperplane's increments stay in LDS; periodic-wrap neighbours are read back from HBM.
+// ---------------------------------------------------------------------------------------
+template <class T>
+DEV T micro_diag(const CellSide *cs, T x, T y, T base) {
+    T D = base;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if (cs[s].type == FT_SELF) continue;
+        const T un = x * (T)cs[s].nx + y * (T)cs[s].ny;
+        if (un > T(0)) D += un * (T)cs[s].S;
+    }
+    return D;
+}
+
+template <class S, bool SHAK, int VB>
+__global__ __launch_bounds__(1024) void k_lower(Params p) {
+    using T = S;
+    extern __shared__ unsigned char lds_raw[];
+    T *front = (T *)lds_raw;  // [2][ni][VB]
+    const int ni = p.ni, nj = p.nj, nh = ni + nj - 1;
+    const int sp = blockIdx.y;
+    const int vl = threadIdx.x % VB, slot = threadIdx.x / VB, cpp = blockDim.x / VB;
+    const int v = blockIdx.x * VB + vl;
+    const bool vok = v < p.nv;
+    const int vv = vok ? v : 0;
+    const T x = (T)p.xi[vv], y = (T)p.eta[vv];
+    const int ix = p.vix[vv], iy = p.viy[vv];
+    const T sc = (T)p.scal[SC_SCALE], dt = (T)p.dt;
+    const int TW = p.nvx + p.nvy;
+    T *f0 = front, *f1 = front + ni * VB;
+    for (int s = 0; s < nh; ++s) {
+        const int ilo = s - nj + 1 > 0 ? s - nj + 1 : 0, ihi = s < ni - 1 ? s : ni - 1;
+        for (int i = ilo + slot; i <= ihi; i += cpp) {
+            const int c = i + (s - i) * ni;
+            if (vok) {
+                const CellSide *cs = p.cs + 4 * c;
+                const RecT<T> r = load_rec<T>(p.recs[c]);
+                const S *tb = (const S *)p.tabs + (size_t)c * TW;
+                T eG, eH;
+                eq_eval<T, SHAK>(r, x, y, (T)tb[ix] * (T)tb[p.nvx + iy], eG, eH);
+                const T area = (T)p.area[c];
+                const T cst = T(2) * area / (T(2) * (T)p.recs[c].tau + dt);
+                const size_t o = ((size_t)c * 2 + sp) * p.nvp + v;
+                const T X = sc * (T)((const S *)p.f)[o];
+                const T M = (T)((const S *)p.d1)[o];
+                T sum = M - cst * (X - (sp == 0 ? eG : eH));
+#pragma unroll
+                for (int sd = 0; sd < 4; ++sd) {
+                    const int j = cs[sd].nb;
+                    if (cs[sd].type == FT_SELF || j < 0 || j > c) continue;
+                    const T un = x * (T)cs[sd].nx + y * (T)cs[sd].ny;
+                    if (!(un < T(0))) continue;
+                    const T dj = cs[sd].hp_adj ? f0[(j % ni) * VB + vl]
+                                               : (T)((const S *)p.d1)[((size_t)j * 2 + sp) * p.nvp + v];
+                    sum -= un * (T)cs[sd].S * dj;
+                }
+                const T D = micro_diag<T>(cs, x, y, area / (T)p.dtimp[c] + cst);
+                const T d = sum / D;
+                ((S *)p.d1)[o] = (S)d;
+                f1[i * VB + vl] = d;
+            }
+        }
+        __syncthreads();
+        T *t = f0; f0 = f1; f1 = t;
+    }
+}
+
+template <class S, bool SHAK, int VB>
+__global__ __launch_bounds__(1024) void k_upper(Params p) {
+    using T = S;
+    extern __shared__ unsigned char lds_raw[];
+    T *front = (T *)lds_raw;
+    const int ni = p.ni, nj = p.nj, nh = ni + nj - 1;
+    const int sp = blockIdx.y;
+    const int vl = threadIdx.x % VB, slot = threadIdx.x / VB, cpp = blockDim.x / VB;
+    const int v = blockIdx.x * VB + vl;
+    const bool vok = v < p.nv;
+    const int vv = vok ? v : 0;
+    const T x = (T)p.xi[vv], y = (T)p.eta[vv];
+    const T sc = (T)p.scal[SC_SCALE], dt = (T)p.dt;
+    T *f0 = front, *f1 = front + ni * VB;
+    for (int s = nh - 1; s >= 0; --s) {
+        const int ilo = s - nj + 1 > 0 ? s - nj + 1 : 0, ihi = s < ni - 1 ? s : ni - 1;
+        for (int i = ilo + slot; i <= ihi; i += cpp) {
+            const int c = i + (s - i) * ni;
+            if (vok) {
+                const CellSide *cs = p.cs + 4 * c;
+                const T area = (T)p.area[c];
+                const T cst = T(2) * area / (T(2) * (T)p.recs[c].tau + dt);
+                const size_t o = ((size_t)c * 2 + sp) * p.nvp + v;
+                T sum = T(0);
+#pragma unroll
+                for (int sd = 0; sd < 4; ++sd) {
+                    const int j = cs[sd].nb;
+                    const int type = cs[sd].type;
+                    const T un = x * (T)cs[sd].nx + y * (T)cs[sd].ny;
+                    if (type == FT_WALL) {
+                        if (un < T(0)) {
+                            const int ws = cs[sd].wside;
+                            const T in = -un * (T)cs[sd].S * (T)p.drho[cs[sd].face] *
+                                         (T)p.gw[(size_t)ws * p.nvp + v];
+                            sum += sp == 0 ? in : in * (T)p.wKRT[ws];
+                        }
+                        continue;
+                    }
+                    if (type == FT_SELF || j < 0 || j < c) continue;
+                    if (!(un < T(0))) continue;
+                    const T dj = cs[sd].hp_adj ? f0[(j % ni) * VB + vl]
+                                               : (T)((const S *)p.d1)[((size_t)j * 2 + sp) * p.nvp + v];
+                    sum -= un * (T)cs[sd].S * dj;
+                }
+                const T D = micro_diag<T>(cs, x, y, area / (T)p.dtimp[c] + cst);
+                const T d = (T)((const S *)p.d1)[o] + sum / D;
+                ((S *)p.d1)[o] = (S)d;
+                f1[i * VB + vl] = d;
+                S *fp = (S *)p.f + o;
+                *fp = (S)(sc * (T)(*fp) + d);
+            }
+        }
+        __syncthreads();
+        T *t = f0; f0 = f1; f1 = t;
+    }
+}
+
+// wall ghost density increment of each wall face from the forward-sweep G increment
+template <class S>
+__global__ __launch_bounds__(256) void k_wall_ghost(Params p) {
+    const int lane = threadIdx.x & 63;
+    const int wi = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wi >= p.nwall) return;
+    const int k = p.wall_faces[wi];
+    const Face F = p.faces[k];
+    const S *d = (const S *)p.d1 + ((size_t)F.L * 2) * p.nvp;
+    double a[1] = {0.0};
+    for (int v = lane; v < p.nv; v += 64) {
+        const double un = p.xi[v] * F.nx + p.eta[v] * F.ny;
+        if (un > 0.0) a[0] += p.w[v] * un * (double)d[v];
+    }
+    wave_sum<1>(a);
+    if (lane == 0) p.drho[k] = -a[0] / p.wden[k];
+}
+
+// explicit DUGKS update (Eq. 21)
+template <class S, bool SHAK>
+__global__ __launch_bounds__(256) void k_explicit(Params p) {
+    using T = S;
+    const int c = xcd_remap(blockIdx.x, p.nc);
+    const RecT<T> r = load_rec<T>(p.rec[c]);
+    const S *tb = (const S *)p.tab + (size_t)c * (p.nvx + p.nvy);
+    const T area = (T)p.area[c], dt = (T)p.dt, sc = (T)p.scal[SC_SCALE];
+    const T cst = T(2) * area / (T(2) * (T)p.rec[c].tau + dt), g = dt / area;
+    for (int v = threadIdx.x; v < p.nv; v += blockDim.x) {
+        T eG, eH;
+        eq_eval<T, SHAK>(r, (T)p.xi[v], (T)p.eta[v], (T)tb[p.vix[v]] * (T)tb[p.nvx + p.viy[v]], eG, eH);
+        for (int sp = 0; sp < 2; ++sp) {
+            const size_t o = ((size_t)c * 2 + sp) * p.nvp + v;
+            const T X = sc * (T)((const S *)p.f)[o];
+            const T M = (T)((const S *)p.d1)[o];
+            ((S *)p.f)[o] = (S)(X + g * (M - cst * (X - (sp == 0 ? eG : eH))));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// state conversion between the device layout and the canonical FP64 [2][nc][nv] layout
+// ---------------------------------------------------------------------------------------
+template <class S>
+__global__ void k_pack(Params p, const void *src_dev_layout, double *dst, int sp, int nsp,
+                       int scaled) {
+    const size_t n = (size_t)p.nc * p.nv;
+    const double sc = scaled ? p.scal[SC_SCALE] : 1.0;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n * nsp;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const int s = sp + (int)(t / n);
+        const size_t r = t % n;
+        const int c = (int)(r / p.nv), v = (int)(r % p.nv);
+        dst[t] = sc * (double)((const S *)src_dev_layout)[((size_t)c * 2 + s) * p.nvp + v];
+    }
+}
+
+template <class S>
+__global__ void k_unpack(Params p, const double *src, int sp, int nsp) {
+    const size_t n = (size_t)p.nc * p.nv;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n * nsp;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const int s = sp + (int)(t / n);
+        const size_t r = t % n;
+        const int c = (int)(r / p.nv), v = (int)(r % p.nv);
+        ((S *)p.f)[((size_t)c * 2 + s) * p.nvp + v] = (S)src[t];
+    }
+}
+
+// uniform initial state: f[c][s][v] = eq[s][v] (eq staged as FP64 [2][nvp] in d1)
+template <class S>
+__global__ void k_fill_uniform(Params p, const double *eq) {
+    const size_t n = (size_t)p.nc * 2 * p.nvp;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const size_t r = t % ((size_t)2 * p.nvp);
+        const int s = (int)(r / p.nvp), v = (int)(r % p.nvp);
+        ((S *)p.f)[t] = (S)(v < p.nv ? eq[(size_t)s * p.nvp + v] : 0.0);
+    }
+}
+
+// cell output fields [nc][8] from 12 raw moments
+__global__ void k_fields(Params p, double *out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= p.nc) return;
+    const double s = p.scal[SC_SCALE];
+    double m[12];
+    for (int a = 0; a < 12; ++a) m[a] = s * p.raw[(size_t)c * NM_MAX + a];
+    const double rho = m[0], U = m[1] / rho, V = m[2] / rho;
+    const double RT = (2.0 * m[3] / rho - U * U - V * V) / (p.K + 2);
+    const double tau = tau_of(p, rho, RT);
+    double qx, qy;
+    heat_from_raw(m, U, V, qx, qy);
+    const double Pr = p.model == 1 ? p.Pr : 1.0, t2 = 2.0 * tau;
+    double *o = out + (size_t)c * 8;
+    o[0] = rho; o[1] = U; o[2] = V; o[3] = 2.0 * RT; o[4] = rho * RT;
+    o[5] = t2 * qx / (t2 + p.dt * Pr);
+    o[6] = t2 * qy / (t2 + p.dt * Pr);
+    o[7] = tau;
+}
+
+// ---------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------
+#define DISPATCH_S(fp32, ...) \
+    do { if (fp32) { using S = float; __VA_ARGS__; } else { using S = double; __VA_ARGS__; } } while (0)
+
+hipError_t launch_raw(const Params &p, bool fp32, int nm, hipStream_t st) {
+    DISPATCH_S(fp32, {
+        if (nm == 12) hipLaunchKernelGGL((k_raw<S, 12>), dim3(p.nc), dim3(256), 0, st, p);
+        else hipLaunchKernelGGL((k_raw<S, 4>), dim3(p.nc), dim3(256), 0, st, p);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Params &p, int mode, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, p, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_records(const Params &p, bool fp32, int which, hipStream_t st) {
+    const dim3 g((p.nc + 3) / 4);
+    DISPATCH_S(fp32, {
+        if (p.model == 1) hipLaunchKernelGGL((k_records<S, true>), g, dim3(256), 0, st, p, which);
+        else hipLaunchKernelGGL((k_records<S, false>), g, dim3(256), 0, st, p, which);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_partials(const Params &p, bool fp32, hipStream_t st) {
+    DISPATCH_S(fp32, {
+        if (p.model == 1) {
+            if (p.limiter) hipLaunchKernelGGL((k_partials<S, true, true>), dim3(p.nc), dim3(256), 0, st, p);
+            else hipLaunchKernelGGL((k_partials<S, true, false>), dim3(p.nc), dim3(256), 0, st, p);
+        } else {
+            if (p.limiter) hipLaunchKernelGGL((k_partials<S, false, true>), dim3(p.nc), dim3(256), 0, st, p);
+            else hipLaunchKernelGGL((k_partials<S, false, false>), dim3(p.nc), dim3(256), 0, st, p);
+        }
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_face_records(const Params &p, bool fp32, hipStream_t st) {
+    const dim3 g((p.nf + 3) / 4);
+    DISPATCH_S(fp32, {
+        if (p.model == 1) hipLaunchKernelGGL((k_face_records<S, true>), g, dim3(256), 0, st, p);
+        else hipLaunchKernelGGL((k_face_records<S, false>), g, dim3(256), 0, st, p);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_flux(const Params &p, bool fp32, hipStream_t st) {
+    DISPATCH_S(fp32, {
+        if (p.model == 1) {
+            if (p.limiter) hipLaunchKernelGGL((k_flux<S, true, true>), dim3(p.nc), dim3(256), 0, st, p);
+            else hipLaunchKernelGGL((k_flux<S, true, false>), dim3(p.nc), dim3(256), 0, st, p);
+        } else {
+            if (p.limiter) hipLaunchKernelGGL((k_flux<S, false, true>), dim3(p.nc), dim3(256), 0, st, p);
+            else hipLaunchKernelGGL((k_flux<S, false, false>), dim3(p.nc), dim3(256), 0, st, p);
+        }
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_macro(const Params &p, hipStream_t st) {
+    const size_t lds = (size_t)2 * p.ni * 4 * sizeof(double);
+    hipLaunchKernelGGL(k_macro, dim3(1), dim3(1024), lds, st, p);
+    return hipGetLastError();
+}
+
+template <int VB>
+static hipError_t launch_sweeps_vb(const Params &p, bool fp32, bool upper, hipStream_t st) {
+    const dim3 g((p.nv + VB - 1) / VB, 2);
+    DISPATCH_S(fp32, {
+        const size_t lds = (size_t)2 * p.ni * VB * sizeof(S);
+        const void *fn = !upper ? (p.model == 1 ? (const void *)k_lower<S, true, VB> : (const void *)k_lower<S, false, VB>)
+                                : (p.model == 1 ? (const void *)k_upper<S, true, VB> : (const void *)k_upper<S, false, VB>);
+        if (lds > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        if (!upper) {
+            if (p.model == 1) hipLaunchKernelGGL((k_lower<S, true, VB>), g, dim3(1024), lds, st, p);
+            else hipLaunchKernelGGL((k_lower<S, false, VB>), g, dim3(1024), lds, st, p);
+        } else {
+            if (p.model == 1) hipLaunchKernelGGL((k_upper<S, true, VB>), g, dim3(1024), lds, st, p);
+            else hipLaunchKernelGGL((k_upper<S, false, VB>), g, dim3(1024), lds, st, p);
+        }
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const Params &p, bool fp32, bool upper, int vb, hipStream_t st) {
+    switch (vb) {
+    case 8: return launch_sweeps_vb<8>(p, fp32, upper, st);
+    case 16: return launch_sweeps_vb<16>(p, fp32, upper, st);
+    case 32: return launch_sweeps_vb<32>(p, fp32, upper, st);
+    default: return launch_sweeps_vb<64>(p, fp32, upper, st);
+    }
+}
+
+hipError_t launch_wall_ghost(const Params &p, bool fp32, hipStream_t st) {
+    if (p.nwall == 0) return hipSuccess;
+    const dim3 g((p.nwall + 3) / 4);
+    DISPATCH_S(fp32, hipLaunchKernelGGL((k_wall_ghost<S>), g, dim3(256), 0, st, p));
+    return hipGetLastError();
+}
+
+hipError_t launch_explicit(const Params &p, bool fp32, hipStream_t st) {
+    DISPATCH_S(fp32, {
+        if (p.model == 1) hipLaunchKernelGGL((k_explicit<S, true>), dim3(p.nc), dim3(256), 0, st, p);
+        else hipLaunchKernelGGL((k_explicit<S, false>), dim3(p.nc), dim3(256), 0, st, p);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const Params &p, bool fp32, const void *src, double *dst, int sp, int nsp,
+                       int scaled, hipStream_t st) {
+    DISPATCH_S(fp32, hipLaunchKernelGGL((k_pack<S>), dim3(2048), dim3(256), 0, st, p, src, dst, sp,
+                                        nsp, scaled));
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const Params &p, bool fp32, const double *src, int sp, int nsp,
+                         hipStream_t st) {
+    DISPATCH_S(fp32, hipLaunchKernelGGL((k_unpack<S>), dim3(2048), dim3(256), 0, st, p, src, sp, nsp));
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_uniform(const Params &p, bool fp32, const double *eq, hipStream_t st) {
+    DISPATCH_S(fp32, hipLaunchKernelGGL((k_fill_uniform<S>), dim3(2048), dim3(256), 0, st, p, eq));
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(const Params &p, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_fields, dim3((p.nc + 255) / 256), dim3(256), 0, st, p, out);
+    return hipGetLastError();
+}
+
+}  // namespace idugks

@@ -1,0 +1,128 @@
+"""Python front end of the C ABI: workspace and stream from PyTorch, everything else in HIP."""
+import ctypes as C
+
+import numpy as np
+
+from .abi import IMPLICIT, IdugksError, Info, load_library, make_config
+
+_D = C.POINTER(C.c_double)
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D)
+
+
+class Solver:
+    """One IDUGKS problem on one GPU (see include/idugks.h for the semantics of each call)."""
+
+    def __init__(self, cfg, device="cuda:0", stream=None):
+        import torch
+        self._lib = load_library()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        c, keep = make_config(cfg)
+        nbytes = C.c_size_t(0)
+        self._check(self._lib.idugks_workspace_size(C.byref(c), C.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        self._check(self._lib.idugks_init(C.byref(c), C.c_void_p(self.workspace.data_ptr()),
+                                          nbytes.value, C.c_void_p(self.stream.cuda_stream),
+                                          C.byref(h)))
+        del keep
+        self._h = h
+        info = self.info()
+        self.nc, self.nv, self.nf = info.nc, info.nv, info.nf
+        self.dt = info.dt
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.idugks_destroy(h)
+            self._h = None
+
+    def close(self):
+        self.__del__()
+
+    def _check(self, rc):
+        if rc:
+            raise IdugksError(rc, self._lib.idugks_last_error().decode())
+
+    def info(self):
+        i = Info()
+        self._check(self._lib.idugks_get_info(self._h, C.byref(i)))
+        return i
+
+    def velocities(self):
+        xi, eta, w = (np.zeros(self.nv) for _ in range(3))
+        self._check(self._lib.idugks_velocities(self._h, _dp(xi), _dp(eta), _dp(w)))
+        return xi, eta, w
+
+    def step(self, mode=IMPLICIT, n=1):
+        r = C.c_double(0.0)
+        self._check(self._lib.idugks_step(self._h, mode, n, C.byref(r)))
+        return r.value
+
+    def solve(self, tol, max_iter):
+        it = C.c_int32(0)
+        r = C.c_double(0.0)
+        rc = self._lib.idugks_solve(self._h, tol, max_iter, C.byref(it), C.byref(r))
+        if rc not in (0, 5):
+            self._check(rc)
+        return it.value, r.value, rc == 0
+
+    def residual(self):
+        out = np.zeros(4)
+        self._check(self._lib.idugks_residual(self._h, _dp(out)))
+        return out
+
+    def moments(self):
+        out = np.zeros((self.nc, 8))
+        self._check(self._lib.idugks_moments(self._h, C.c_void_p(out.ctypes.data), 1))
+        return out
+
+    def flux(self):
+        M = np.zeros((2, self.nc, self.nv))
+        self._check(self._lib.idugks_flux(self._h, C.c_void_p(M.ctypes.data), 1))
+        return M
+
+    def face_moments(self):
+        Wf = np.zeros((self.nf, 4))
+        rw = np.zeros(self.nf)
+        self._check(self._lib.idugks_face_moments(self._h, C.c_void_p(Wf.ctypes.data),
+                                                  C.c_void_p(rw.ctypes.data), 1))
+        return Wf, rw
+
+    def macro_residual(self):
+        MW = np.zeros((self.nc, 4))
+        self._check(self._lib.idugks_macro_residual(self._h, C.c_void_p(MW.ctypes.data), 1))
+        return MW
+
+    def predict(self):
+        Ws = np.zeros((self.nc, 4))
+        dti = np.zeros(self.nc)
+        self._check(self._lib.idugks_predict(self._h, C.c_void_p(Ws.ctypes.data),
+                                             C.c_void_p(dti.ctypes.data), 1))
+        return Ws, dti
+
+    def get_state(self):
+        f = np.zeros((2, self.nc, self.nv))
+        self._check(self._lib.idugks_get_state(self._h, C.c_void_p(f.ctypes.data), 1))
+        return f
+
+    def set_state(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(2, self.nc, self.nv)
+        self._check(self._lib.idugks_set_state(self._h, C.c_void_p(f.ctypes.data), 1))
+
+    def kernel_names(self):
+        n = self._lib.idugks_num_kernels()
+        return [self._lib.idugks_kernel_name(k).decode() for k in range(n)]
+
+    def profile(self, mode=IMPLICIT, n=1):
+        """Per-kernel HIP-event milliseconds over n steps: {name: (ms_total, launches)}."""
+        nk = self._lib.idugks_num_kernels()
+        ms = np.zeros(nk)
+        cnt = np.zeros(nk, dtype=np.int64)
+        self._check(self._lib.idugks_profile(self._h, mode, n, _dp(ms),
+                                             cnt.ctypes.data_as(C.POINTER(C.c_int64))))
+        return {name: (float(ms[k]), int(cnt[k])) for k, name in enumerate(self.kernel_names())}

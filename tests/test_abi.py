@@ -1,0 +1,126 @@
+"""The C-ABI library loads, exports every function include/idugks.h declares, and rejects
+invalid configurations on the host before any device work (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from paper_1709_01819_amd import abi
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "idugks.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(idugks_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = abi.load_library()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(abi.EXPORTED)
+
+
+def test_kernel_names():
+    lib = abi.load_library()
+    n = lib.idugks_num_kernels()
+    names = [lib.idugks_kernel_name(k).decode() for k in range(n)]
+    assert "flux" in names and "sweep_lower" in names and "macro_lusgs" in names
+    assert lib.idugks_kernel_name(n) == b""
+
+
+def _size(cfg):
+    lib = abi.load_library()
+    c, keep = abi.make_config(cfg)
+    n = C.c_size_t(0)
+    rc = lib.idugks_workspace_size(C.byref(c), C.byref(n))
+    return rc, n.value, lib.idugks_last_error().decode()
+
+
+def test_workspace_size_scales_with_precision():
+    rc64, n64, _ = _size(wl.case("cavity_kn0.075"))
+    rc32, n32, _ = _size(wl.case("cavity_kn0.075", precision=wl.FP32_MIXED))
+    assert rc64 == 0 and rc32 == 0
+    nc, nvp = 64 * 64, 832
+    # two FP64 state arrays at least, and the FP32 form needs less
+    assert n64 >= 2 * 2 * nc * nvp * 8
+    assert n32 < n64
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("Kn", 0.0, "Kn"), ("Kn", -1.0, "Kn"), ("Pr", 0.0, "Pr"), ("K", -1, "K must"),
+    ("nvx", 1, "nv >= 2"), ("model", 7, "model"), ("precision", 3, "precision"),
+    ("cfl_imp", 0.0, "CFL"), ("limiter", 5, "limiter"),
+])
+def test_invalid_configs_rejected(field, value, msg):
+    cfg = wl.case("couette")
+    cfg[field] = value
+    rc, _, err = _size(cfg)
+    assert rc == 1 and msg in err
+
+
+def test_invalid_geometry_and_boundaries_rejected():
+    cfg = wl.cavity(n=4, nv=4)
+    cfg["xn"] = cfg["xn"][::-1].copy()   # clockwise cells: negative area
+    lib = abi.load_library()
+    c, keep = abi.make_config(cfg)
+    h = C.c_void_p()
+    # init validates geometry on the host; a dummy non-null workspace is never touched
+    rc = lib.idugks_init(C.byref(c), C.c_void_p(1), 1 << 40, None, C.byref(h))
+    assert rc == 1 and "area" in lib.idugks_last_error().decode()
+    cfg = wl.case("couette")
+    cfg["bc"] = [wl.BC_PERIODIC, wl.BC_WALL, wl.BC_WALL, wl.BC_WALL]
+    assert _size(cfg)[0] == 1
+    cfg = wl.cavity(n=4, nv=4, model=wl.SHAKHOV, K=3, Pr=2 / 3)
+    rc, _, err = _size(cfg)
+    assert rc == 1 and "Shakhov" in err
+
+
+def test_init_rejects_small_workspace_and_null_pointers():
+    lib = abi.load_library()
+    c, keep = abi.make_config(wl.case("couette"))
+    h = C.c_void_p()
+    assert lib.idugks_init(C.byref(c), None, 1 << 30, None, C.byref(h)) == 1
+    assert lib.idugks_init(C.byref(c), C.c_void_p(1), 16, None, C.byref(h)) == 1
+    assert "small" in lib.idugks_last_error().decode()
+    assert lib.idugks_step(None, 1, 1, None) == 1
+    lib.idugks_destroy(None)  # NULL-safe
+
+
+# ------------------------------------------------------------------ host-built problem
+# The GPU library builds its velocity set and geometry on the host with code of its own
+# (Sturm-bisection Gauss-Hermite nodes, per-cell edges); these must equal the oracle's.
+from oracle import Oracle  # noqa: E402
+
+HOST_CASES = {
+    "couette": lambda: wl.case("couette"),
+    "cavity_c2": lambda: wl.case("cavity_kn0.075"),
+    "cavity_c3_nc": lambda: wl.shrink(wl.case("cavity_kn10"), ni=16, nj=16, nv=101),
+    "cylinder_c4_nc": lambda: wl.shrink(wl.case("cylinder_ma5"), ni=12, nj=20, nv=100),
+    "box": lambda: wl.periodic_box(n=5, nv=9),
+    "gh60": lambda: wl.cavity(n=3, nv=60),
+}
+
+
+@pytest.mark.parametrize("name", list(HOST_CASES))
+def test_host_description_matches_oracle(name):
+    cfg = HOST_CASES[name]()
+    d = abi.describe(cfg)
+    o = Oracle(cfg)
+    for k, ref in zip(("xi", "eta", "w"), o.velocities()):
+        assert np.max(np.abs(d[k] - ref)) <= 1e-13 * max(1.0, np.abs(ref).max()), k
+    assert abs(d["dt"] - o.dt) <= 1e-14 * o.dt
+    area, _, _ = o.cells()
+    assert np.max(np.abs(d["area"] - area)) <= 1e-15 * area.max()
+    sd = o.cell_sides()
+    assert np.array_equal(d["nb"], sd["nb"])
+    for k in ("nx", "ny", "S"):
+        assert np.max(np.abs(d[k] - sd[k])) <= 1e-13 * max(1.0, np.abs(sd[k]).max()), k
+    for k in ("ax", "ay"):
+        assert np.max(np.abs(d[k] - sd[k])) <= 1e-11 * np.abs(sd[k]).max(), k
