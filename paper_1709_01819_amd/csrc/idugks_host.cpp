@@ -172,7 +172,8 @@ idugks_status validate(const idugks_config *c) {
     if (!c) return fail(IDUGKS_E_INVALID, "null config");
     if (c->struct_size != sizeof(idugks_config)) return fail(IDUGKS_E_INVALID, "struct_size mismatch");
     if (c->ni < 1 || c->nj < 1) return fail(IDUGKS_E_INVALID, "mesh needs ni, nj >= 1");
-    if (c->ni > 2048) return fail(IDUGKS_E_INVALID, "ni > 2048 is not supported");
+    if ((size_t)(12 * c->ni + 4 * c->nj) * 8 > 128 * 1024 || (size_t)(3 * c->ni + c->nj) * 8 * 8 > 128 * 1024)
+        return fail(IDUGKS_E_INVALID, "mesh too large for the LDS-resident sweep fronts");
     if (!c->xn || !c->yn) return fail(IDUGKS_E_INVALID, "missing node coordinates");
     if (c->nvx < 2 || c->nvy < 2) return fail(IDUGKS_E_INVALID, "need nv >= 2 per direction");
     if (c->nvx > 4096 || c->nvy > 4096) return fail(IDUGKS_E_INVALID, "velocity grid too large");
@@ -518,7 +519,7 @@ enum Region {
     R_CS, R_FACES, R_WALLF, R_AREA, R_XI, R_ETA, R_W, R_X1, R_WX1, R_Y1, R_WY1, R_VIX, R_VIY,
     R_GW, R_WKRT, R_GINF, R_HINF, R_WDEN, R_BHALF, R_F, R_D1, R_TAB, R_TABS, R_TABF, R_REC,
     R_RECS, R_RECF, R_PART, R_RAW, R_WC, R_MW, R_DW, R_DWD, R_DTIMP, R_RHOOLD, R_DRHO, R_SCAL,
-    R_STAGE, R_COUNT
+    R_STAGE, R_MPREP, R_SWB, R_SWC, R_COUNT
 };
 
 Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy, int nwall) {
@@ -533,7 +534,7 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
         S * (size_t)nf * TW, sizeof(Rec) * (size_t)nc, sizeof(Rec) * (size_t)nc, sizeof(Rec) * (size_t)nf,
         8 * (size_t)nc * 4 * NM_MAX, 8 * (size_t)nc * NM_MAX, 8 * 4 * (size_t)nc, 8 * 4 * (size_t)nc,
         8 * 4 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nf, 8 * SC_NUM,
-        8 * (size_t)std::max(nc, 2) * nvp};
+        8 * (size_t)std::max(nc, 2) * nvp, 8 * 20 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc};
     for (int r = 0; r < R_COUNT; ++r) L.add(sizes[r]);
     L.bytes = (L.bytes + 255) & ~size_t(255);
     return L;
@@ -609,9 +610,9 @@ idugks_status read_scalars(idugks_ctx *x, double *sc) {
 
 // Velocities per sweep block: enough slices to occupy the chip, at least 8 velocities per
 // slice, and the two LDS fronts (2 x ni x vb values) within 128 KiB.
-int choose_vb(int nv, int ni, size_t s_bytes) {
+int choose_vb(int nv, int ni, int nj, size_t s_bytes) {
     int vb = nv >= 64 * 256 ? 64 : nv >= 32 * 256 ? 32 : nv >= 16 * 128 ? 16 : 8;
-    while (vb > 8 && (size_t)2 * ni * vb * s_bytes > 128 * 1024) vb /= 2;
+    while (vb > 8 && sweep_lds_bytes(ni, nj, vb, s_bytes) > 128 * 1024) vb /= 2;
     return vb;
 }
 
@@ -686,7 +687,7 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     x->cfg.xn = x->cfg.yn = nullptr;
     x->fp32 = cfg->precision == IDUGKS_FP32_MIXED;
     x->st = (hipStream_t)hip_stream;
-    x->vb = choose_vb(b.nv, b.ni, x->fp32 ? 4 : 8);
+    x->vb = choose_vb(b.nv, b.ni, b.nj, x->fp32 ? 4 : 8);
     x->iters = 0;
     x->prof = false;
     x->ev_used = 0;
@@ -716,6 +717,7 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     p.MW = (double *)R(R_MW); p.dW = (double *)R(R_DW); p.DWd = (double *)R(R_DWD);
     p.dtimp = (double *)R(R_DTIMP); p.rho_old = (double *)R(R_RHOOLD); p.drho = (double *)R(R_DRHO);
     p.scal = (double *)R(R_SCAL);
+    p.mprep = (double *)R(R_MPREP); p.swb = (double *)R(R_SWB); p.swc = (double *)R(R_SWC);
     x->stage = (double *)R(R_STAGE);
 
     auto up = [&](void *dst, const void *src, size_t n) {

@@ -87,6 +87,8 @@ struct Params {
     void *f, *d1, *tab, *tabs, *tabf;
     Rec *rec, *recs, *recf;
     double *part, *raw, *Wc, *MW, *dW, *DWd, *dtimp, *rho_old, *drho, *scal;
+    double *mprep;           // [nc][4][5] lambda_j and F_n(W_j) per cell side (macro LU-SGS)
+    double *swb, *swc;       // [nc] diagonal base and collision coefficient of the micro sweeps
 };
 
 }  // namespace idugks

@@ -339,6 +339,11 @@ __global__ __launch_bounds__(256) void k_records(Params p, int which) {
             qy = p.rec[c].qy;
         }
     }
+    if (which == 1 && lane == 0) {
+        const double cst = 2.0 * p.area[c] / (2.0 * tau + p.dt);
+        p.swc[c] = cst;                             // collision coefficient of Eq. 26
+        p.swb[c] = p.area[c] / p.dtimp[c] + cst;    // cell part of the diagonal of Eq. 26
+    }
     Rec *out = which == 0 ? p.rec + c : p.recs + c;
     S *tab = (S *)(which == 0 ? p.tab : p.tabs) + (size_t)c * TW;
     build_eq<S, SHAK>(p, rho, U, V, RT, tau, qx, qy, out, tab, lane);
@@ -569,125 +574,169 @@ DEV void euler_flux(const double W[4], double nx, double ny, int K, double F[4])
     F[3] = (W[3] + pr) * un;
 }
 
-DEV double sound(const Params &p, int c) { return sqrt(p.gam * p.rec[c].RT); }
-
-// contribution 1/2 S (F_n(W_j + dW_j) - F_n(W_j) - lambda_j dW_j) of neighbour j
-DEV void macro_term(const Params &p, int j, const CellSide &cs, const double dWj[4], double out[4]) {
-    const double *Wj = p.Wc + (size_t)j * 4;
-    const double lam = fabs((Wj[1] * cs.nx + Wj[2] * cs.ny) / Wj[0]) + sound(p, j);
-    double Wn[4], F1[4], F0[4];
-    for (int a = 0; a < 4; ++a) Wn[a] = Wj[a] + dWj[a];
-    euler_flux(Wn, cs.nx, cs.ny, p.K, F1);
-    euler_flux(Wj, cs.nx, cs.ny, p.K, F0);
-    for (int a = 0; a < 4; ++a) out[a] = 0.5 * cs.S * (F1[a] - F0[a] - lam * dWj[a]);
+// All data exchanged inside the sweep kernels goes through LDS, so their barrier orders
+// LDS only: global loads issued for the next hyperplane stay in flight across it.
+DEV void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-__global__ __launch_bounds__(1024) void k_macro(Params p) {
-    extern __shared__ double front[];  // [2][ni][4]
-    const int ni = p.ni, nj = p.nj, nh = ni + nj - 1;
-    // diagonal and implicit time step
-    for (int c = threadIdx.x; c < p.nc; c += blockDim.x) {
-        const CellSide *cs = p.cs + 4 * c;
-        const double U = p.rec[c].U, V = p.rec[c].V, C = sound(p, c);
-        double ls = 0.0, lw = 0.0;
-        for (int s = 0; s < 4; ++s) {
-            if (cs[s].type == FT_SELF) continue;
-            const double l = (fabs(U * cs[s].nx + V * cs[s].ny) + C) * cs[s].S;
-            ls += l;
-            if (cs[s].type == FT_WALL) lw += l;
-        }
-        const double dti = p.cfl_imp * p.area[c] / ls;
-        p.dtimp[c] = dti;
-        p.DWd[c] = p.area[c] / dti + 0.5 * ls + 0.5 * lw;
+DEV void hp_bounds(int s, int ni, int nj, int &lo, int &hi) {
+    lo = s - nj + 1 > 0 ? s - nj + 1 : 0;
+    hi = s < ni - 1 ? s : ni - 1;
+}
+
+// Everything of Eq. 30-31 that does not depend on the increments, all cells in parallel:
+// implicit time step, diagonal (a wall face carries its whole lambda S: mirrored ghost),
+// and per cell side with a neighbour j the neighbour's lambda_j and F_n(W_j).
+__global__ __launch_bounds__(256) void k_macro_prep(Params p) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= p.nc) return;
+    const CellSide *cs = p.cs + 4 * c;
+    const double U = p.rec[c].U, V = p.rec[c].V, C = sqrt(p.gam * p.rec[c].RT);
+    double ls = 0.0, lw = 0.0;
+    for (int s = 0; s < 4; ++s) {
+        if (cs[s].type == FT_SELF) continue;
+        const double l = (fabs(U * cs[s].nx + V * cs[s].ny) + C) * cs[s].S;
+        ls += l;
+        if (cs[s].type == FT_WALL) lw += l;
+        const int j = cs[s].nb;
+        if (j < 0) continue;
+        const double *Wj = p.Wc + (size_t)j * 4;
+        double *mp = p.mprep + ((size_t)c * 4 + s) * 5;
+        mp[0] = fabs((Wj[1] * cs[s].nx + Wj[2] * cs[s].ny) / Wj[0]) + sqrt(p.gam * p.rec[j].RT);
+        double F0[4];
+        euler_flux(Wj, cs[s].nx, cs[s].ny, p.K, F0);
+        for (int a = 0; a < 4; ++a) mp[1 + a] = F0[a];
     }
-    __syncthreads();
-    double *f0 = front, *f1 = front + 4 * ni;
-    // lower sweep
+    const double dti = p.cfl_imp * p.area[c] / ls;
+    p.dtimp[c] = dti;
+    p.DWd[c] = p.area[c] / dti + 0.5 * ls + 0.5 * lw;
+}
+
+// r += sign * 1/2 S (F_n(W_j + dW_j) - F_n(W_j) - lambda_j dW_j) for neighbour j on side sd
+DEV void macro_add(const Params &p, int c, int sd, const CellSide &q, const double dWj[4],
+                   double r[4], double sign) {
+    const double *mp = p.mprep + ((size_t)c * 4 + sd) * 5;
+    const double *Wj = p.Wc + (size_t)q.nb * 4;
+    double Wn[4], F1[4];
+    for (int a = 0; a < 4; ++a) Wn[a] = Wj[a] + dWj[a];
+    euler_flux(Wn, q.nx, q.ny, p.K, F1);
+    for (int a = 0; a < 4; ++a) r[a] += sign * 0.5 * q.S * (F1[a] - mp[1 + a] - mp[0] * dWj[a]);
+}
+
+// Macro LU-SGS sweeps over i+j hyperplanes in one block (one lane per cell of a
+// hyperplane).  LDS holds the previous hyperplane's increments (fronts) and the
+// increments of the cells next to a periodic seam (wI: column i = 0 / ni-1, wJ: row
+// j = 0 / nj-1), which are the only non-adjacent neighbours.
+__global__ __launch_bounds__(1024) void k_macro_sweep(Params p) {
+    extern __shared__ double lds[];
+    const int ni = p.ni, nj = p.nj, nh = ni + nj - 1;
+    double *f0 = lds, *f1 = lds + 4 * ni, *wI = lds + 8 * ni, *wJ = wI + 4 * nj;
     for (int s = 0; s < nh; ++s) {
-        const int ilo = s - nj + 1 > 0 ? s - nj + 1 : 0, ihi = s < ni - 1 ? s : ni - 1;
-        for (int i = ilo + threadIdx.x; i <= ihi; i += blockDim.x) {
-            const int c = i + (s - i) * ni;
+        int lo, hi;
+        hp_bounds(s, ni, nj, lo, hi);
+        for (int i = lo + threadIdx.x; i <= hi; i += blockDim.x) {
+            const int j = s - i, c = i + j * ni;
             const CellSide *cs = p.cs + 4 * c;
             double r[4];
             for (int a = 0; a < 4; ++a) r[a] = p.MW[(size_t)c * 4 + a];
             for (int sd = 0; sd < 4; ++sd) {
-                const int j = cs[sd].nb;
-                if (cs[sd].type == FT_SELF || j < 0 || j > c) continue;
-                double dWj[4], t[4];
-                if (cs[sd].hp_adj) {
-                    const int ij = j % ni;
-                    for (int a = 0; a < 4; ++a) dWj[a] = f0[4 * ij + a];
-                } else {
-                    for (int a = 0; a < 4; ++a) dWj[a] = p.dW[(size_t)j * 4 + a];
-                }
-                macro_term(p, j, cs[sd], dWj, t);
-                for (int a = 0; a < 4; ++a) r[a] -= t[a];
+                const CellSide q = cs[sd];
+                if (q.type == FT_SELF || q.nb < 0 || q.nb > c) continue;
+                const double *src = q.hp_adj ? f0 + 4 * (sd == 0 ? i - 1 : i)
+                                             : (sd < 2 ? wI + 4 * j : wJ + 4 * i);
+                double dWj[4] = {src[0], src[1], src[2], src[3]};
+                macro_add(p, c, sd, q, dWj, r, -1.0);
             }
             const double D = p.DWd[c];
             for (int a = 0; a < 4; ++a) {
                 const double d = r[a] / D;
                 p.dW[(size_t)c * 4 + a] = d;
                 f1[4 * i + a] = d;
+                if (i == 0) wI[4 * j + a] = d;
+                if (j == 0) wJ[4 * i + a] = d;
             }
         }
-        __syncthreads();
+        lds_barrier();
         double *t = f0; f0 = f1; f1 = t;
     }
-    // upper sweep
     for (int s = nh - 1; s >= 0; --s) {
-        const int ilo = s - nj + 1 > 0 ? s - nj + 1 : 0, ihi = s < ni - 1 ? s : ni - 1;
-        for (int i = ilo + threadIdx.x; i <= ihi; i += blockDim.x) {
-            const int c = i + (s - i) * ni;
+        int lo, hi;
+        hp_bounds(s, ni, nj, lo, hi);
+        for (int i = lo + threadIdx.x; i <= hi; i += blockDim.x) {
+            const int j = s - i, c = i + j * ni;
             const CellSide *cs = p.cs + 4 * c;
             double r[4] = {0.0, 0.0, 0.0, 0.0};
             for (int sd = 0; sd < 4; ++sd) {
-                const int j = cs[sd].nb;
-                if (cs[sd].type == FT_SELF || j < 0 || j < c) continue;
-                double dWj[4], t[4];
-                if (cs[sd].hp_adj) {
-                    const int ij = j % ni;
-                    for (int a = 0; a < 4; ++a) dWj[a] = f0[4 * ij + a];
-                } else {
-                    for (int a = 0; a < 4; ++a) dWj[a] = p.dW[(size_t)j * 4 + a];
-                }
-                macro_term(p, j, cs[sd], dWj, t);
-                for (int a = 0; a < 4; ++a) r[a] += t[a];
+                const CellSide q = cs[sd];
+                if (q.type == FT_SELF || q.nb < 0 || q.nb < c) continue;
+                const double *src = q.hp_adj ? f0 + 4 * (sd == 1 ? i + 1 : i)
+                                             : (sd < 2 ? wI + 4 * j : wJ + 4 * i);
+                double dWj[4] = {src[0], src[1], src[2], src[3]};
+                macro_add(p, c, sd, q, dWj, r, 1.0);
             }
             const double D = p.DWd[c];
             for (int a = 0; a < 4; ++a) {
-                const double d = p.dW[(size_t)c * 4 + a] - r[a] / D;
+                const double d = p.dW[(size_t)c * 4 + a] - r[a] / D;  // written by this lane
                 p.dW[(size_t)c * 4 + a] = d;
                 f1[4 * i + a] = d;
+                if (i == ni - 1) wI[4 * j + a] = d;
+                if (j == nj - 1) wJ[4 * i + a] = d;
             }
         }
-        __syncthreads();
+        lds_barrier();
         double *t = f0; f0 = f1; f1 = t;
     }
 }
 
 // ---------------------------------------------------------------------------------------
 // micro LU-SGS sweeps (Eq. 24-26) over i+j hyperplanes.  One block per (velocity slice,
-// species); lanes = VB velocities x (blockDim/VB) cells of the hyperplane.  The previous
-// hyperplane's increments stay in LDS; periodic-wrap neighbours are read back from HBM.
+// species); lanes = VB velocities x (blockDim/VB) cells of a hyperplane.  Increments of
+// the previous hyperplane and of the cells next to a periodic seam stay in LDS.  Each
+// lane issues the HBM loads of its next (cell, v) item before computing the current one,
+// so they overlap the dependent chain and the barrier.
 // ---------------------------------------------------------------------------------------
 template <class T>
-DEV T micro_diag(const CellSide *cs, T x, T y, T base) {
-    T D = base;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        if (cs[s].type == FT_SELF) continue;
-        const T un = x * (T)cs[s].nx + y * (T)cs[s].ny;
-        if (un > T(0)) D += un * (T)cs[s].S;
+struct SweepItem {
+    int c, i, j;
+    bool ok;
+    T a, b, e;  // lower: M, phi~, factored Maxwellian; upper: forward increment, phi~
+};
+
+template <class S, bool SHAK, int VB, bool UPPER>
+DEV SweepItem<S> sweep_load(const Params &p, int s, int pass, int slot, int cpp, int sp, int v,
+                            bool vok, int ix, int iy) {
+    SweepItem<S> it;
+    it.ok = false;
+    it.c = it.i = it.j = 0;
+    it.a = it.b = it.e = S(0);
+    int lo, hi;
+    hp_bounds(s, p.ni, p.nj, lo, hi);
+    const int i = lo + slot + pass * cpp;
+    if (vok && i <= hi) {
+        it.ok = true;
+        it.i = i;
+        it.j = s - i;
+        it.c = i + it.j * p.ni;
+        const size_t o = ((size_t)it.c * 2 + sp) * p.nvp + v;
+        it.a = ((const S *)p.d1)[o];
+        it.b = ((const S *)p.f)[o];
+        if (!UPPER) {
+            const S *tb = (const S *)p.tabs + (size_t)it.c * (p.nvx + p.nvy);
+            it.e = tb[ix] * tb[p.nvx + iy];
+        }
     }
-    return D;
+    return it;
 }
 
-template <class S, bool SHAK, int VB>
-__global__ __launch_bounds__(1024) void k_lower(Params p) {
+template <class S, bool SHAK, int VB, bool UPPER>
+__global__ __launch_bounds__(1024) void k_sweep(Params p) {
     using T = S;
     extern __shared__ unsigned char lds_raw[];
-    T *front = (T *)lds_raw;  // [2][ni][VB]
     const int ni = p.ni, nj = p.nj, nh = ni + nj - 1;
+    T *f0 = (T *)lds_raw, *f1 = f0 + ni * VB, *wI = f1 + ni * VB, *wJ = wI + nj * VB;
     const int sp = blockIdx.y;
     const int vl = threadIdx.x % VB, slot = threadIdx.x / VB, cpp = blockDim.x / VB;
     const int v = blockIdx.x * VB + vl;
@@ -695,99 +744,65 @@ __global__ __launch_bounds__(1024) void k_lower(Params p) {
     const int vv = vok ? v : 0;
     const T x = (T)p.xi[vv], y = (T)p.eta[vv];
     const int ix = p.vix[vv], iy = p.viy[vv];
-    const T sc = (T)p.scal[SC_SCALE], dt = (T)p.dt;
-    const int TW = p.nvx + p.nvy;
-    T *f0 = front, *f1 = front + ni * VB;
-    for (int s = 0; s < nh; ++s) {
-        const int ilo = s - nj + 1 > 0 ? s - nj + 1 : 0, ihi = s < ni - 1 ? s : ni - 1;
-        for (int i = ilo + slot; i <= ihi; i += cpp) {
-            const int c = i + (s - i) * ni;
-            if (vok) {
-                const CellSide *cs = p.cs + 4 * c;
+    const T sc = (T)p.scal[SC_SCALE];
+    auto npass_of = [&](int s) {
+        int lo, hi;
+        hp_bounds(s, ni, nj, lo, hi);
+        return (hi - lo) / cpp + 1;
+    };
+    int s = UPPER ? nh - 1 : 0;
+    SweepItem<T> nxt = sweep_load<S, SHAK, VB, UPPER>(p, s, 0, slot, cpp, sp, v, vok, ix, iy);
+    for (int step = 0; step < nh; ++step, s += UPPER ? -1 : 1) {
+        const int npass = npass_of(s);
+        for (int pass = 0; pass < npass; ++pass) {
+            const SweepItem<T> cur = nxt;
+            if (pass + 1 < npass)
+                nxt = sweep_load<S, SHAK, VB, UPPER>(p, s, pass + 1, slot, cpp, sp, v, vok, ix, iy);
+            else if (step + 1 < nh)
+                nxt = sweep_load<S, SHAK, VB, UPPER>(p, UPPER ? s - 1 : s + 1, 0, slot, cpp, sp, v,
+                                                     vok, ix, iy);
+            if (!cur.ok) continue;
+            const int c = cur.c, i = cur.i, j = cur.j;
+            const CellSide *cs = p.cs + 4 * c;
+            T D = (T)p.swb[c], sum;
+            if (!UPPER) {
                 const RecT<T> r = load_rec<T>(p.recs[c]);
-                const S *tb = (const S *)p.tabs + (size_t)c * TW;
                 T eG, eH;
-                eq_eval<T, SHAK>(r, x, y, (T)tb[ix] * (T)tb[p.nvx + iy], eG, eH);
-                const T area = (T)p.area[c];
-                const T cst = T(2) * area / (T(2) * (T)p.recs[c].tau + dt);
-                const size_t o = ((size_t)c * 2 + sp) * p.nvp + v;
-                const T X = sc * (T)((const S *)p.f)[o];
-                const T M = (T)((const S *)p.d1)[o];
-                T sum = M - cst * (X - (sp == 0 ? eG : eH));
-#pragma unroll
-                for (int sd = 0; sd < 4; ++sd) {
-                    const int j = cs[sd].nb;
-                    if (cs[sd].type == FT_SELF || j < 0 || j > c) continue;
-                    const T un = x * (T)cs[sd].nx + y * (T)cs[sd].ny;
-                    if (!(un < T(0))) continue;
-                    const T dj = cs[sd].hp_adj ? f0[(j % ni) * VB + vl]
-                                               : (T)((const S *)p.d1)[((size_t)j * 2 + sp) * p.nvp + v];
-                    sum -= un * (T)cs[sd].S * dj;
-                }
-                const T D = micro_diag<T>(cs, x, y, area / (T)p.dtimp[c] + cst);
-                const T d = sum / D;
-                ((S *)p.d1)[o] = (S)d;
-                f1[i * VB + vl] = d;
+                eq_eval<T, SHAK>(r, x, y, cur.e, eG, eH);
+                sum = cur.a - (T)p.swc[c] * (sc * cur.b - (sp == 0 ? eG : eH));
+            } else {
+                sum = T(0);
             }
-        }
-        __syncthreads();
-        T *t = f0; f0 = f1; f1 = t;
-    }
-}
-
-template <class S, bool SHAK, int VB>
-__global__ __launch_bounds__(1024) void k_upper(Params p) {
-    using T = S;
-    extern __shared__ unsigned char lds_raw[];
-    T *front = (T *)lds_raw;
-    const int ni = p.ni, nj = p.nj, nh = ni + nj - 1;
-    const int sp = blockIdx.y;
-    const int vl = threadIdx.x % VB, slot = threadIdx.x / VB, cpp = blockDim.x / VB;
-    const int v = blockIdx.x * VB + vl;
-    const bool vok = v < p.nv;
-    const int vv = vok ? v : 0;
-    const T x = (T)p.xi[vv], y = (T)p.eta[vv];
-    const T sc = (T)p.scal[SC_SCALE], dt = (T)p.dt;
-    T *f0 = front, *f1 = front + ni * VB;
-    for (int s = nh - 1; s >= 0; --s) {
-        const int ilo = s - nj + 1 > 0 ? s - nj + 1 : 0, ihi = s < ni - 1 ? s : ni - 1;
-        for (int i = ilo + slot; i <= ihi; i += cpp) {
-            const int c = i + (s - i) * ni;
-            if (vok) {
-                const CellSide *cs = p.cs + 4 * c;
-                const T area = (T)p.area[c];
-                const T cst = T(2) * area / (T(2) * (T)p.recs[c].tau + dt);
-                const size_t o = ((size_t)c * 2 + sp) * p.nvp + v;
-                T sum = T(0);
 #pragma unroll
-                for (int sd = 0; sd < 4; ++sd) {
-                    const int j = cs[sd].nb;
-                    const int type = cs[sd].type;
-                    const T un = x * (T)cs[sd].nx + y * (T)cs[sd].ny;
-                    if (type == FT_WALL) {
-                        if (un < T(0)) {
-                            const int ws = cs[sd].wside;
-                            const T in = -un * (T)cs[sd].S * (T)p.drho[cs[sd].face] *
-                                         (T)p.gw[(size_t)ws * p.nvp + v];
-                            sum += sp == 0 ? in : in * (T)p.wKRT[ws];
-                        }
-                        continue;
+            for (int sd = 0; sd < 4; ++sd) {
+                const int type = cs[sd].type;
+                if (type == FT_SELF) continue;
+                const T un = x * (T)cs[sd].nx + y * (T)cs[sd].ny, Sk = (T)cs[sd].S;
+                if (un > T(0)) {
+                    D += un * Sk;
+                } else if (un < T(0)) {
+                    const int nb = cs[sd].nb;
+                    if (UPPER && type == FT_WALL) {
+                        const int ws = cs[sd].wside;
+                        const T in = -un * Sk * (T)p.drho[cs[sd].face] * (T)p.gw[(size_t)ws * p.nvp + v];
+                        sum += sp == 0 ? in : in * (T)p.wKRT[ws];
+                    } else if (nb >= 0 && (UPPER ? nb > c : nb < c)) {
+                        const int fi = UPPER ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
+                        const T dj = cs[sd].hp_adj ? f0[fi * VB + vl]
+                                                   : (sd < 2 ? wI[j * VB + vl] : wJ[i * VB + vl]);
+                        sum -= un * Sk * dj;
                     }
-                    if (type == FT_SELF || j < 0 || j < c) continue;
-                    if (!(un < T(0))) continue;
-                    const T dj = cs[sd].hp_adj ? f0[(j % ni) * VB + vl]
-                                               : (T)((const S *)p.d1)[((size_t)j * 2 + sp) * p.nvp + v];
-                    sum -= un * (T)cs[sd].S * dj;
                 }
-                const T D = micro_diag<T>(cs, x, y, area / (T)p.dtimp[c] + cst);
-                const T d = (T)((const S *)p.d1)[o] + sum / D;
-                ((S *)p.d1)[o] = (S)d;
-                f1[i * VB + vl] = d;
-                S *fp = (S *)p.f + o;
-                *fp = (S)(sc * (T)(*fp) + d);
             }
+            const size_t o = ((size_t)c * 2 + sp) * p.nvp + v;
+            const T d = UPPER ? cur.a + sum / D : sum / D;
+            if (UPPER) ((S *)p.f)[o] = (S)(sc * cur.b + d);
+            else ((S *)p.d1)[o] = (S)d;
+            f1[i * VB + vl] = d;
+            if (i == (UPPER ? ni - 1 : 0)) wI[j * VB + vl] = d;
+            if (j == (UPPER ? nj - 1 : 0)) wJ[i * VB + vl] = d;
         }
-        __syncthreads();
+        lds_barrier();
         T *t = f0; f0 = f1; f1 = t;
     }
 }
@@ -955,29 +970,46 @@ hipError_t launch_flux(const Params &p, bool fp32, hipStream_t st) {
     return hipGetLastError();
 }
 
+static int round64(int n) { return (n + 63) / 64 * 64; }
+
 hipError_t launch_macro(const Params &p, hipStream_t st) {
-    const size_t lds = (size_t)2 * p.ni * 4 * sizeof(double);
-    hipLaunchKernelGGL(k_macro, dim3(1), dim3(1024), lds, st, p);
+    hipLaunchKernelGGL(k_macro_prep, dim3((p.nc + 255) / 256), dim3(256), 0, st, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int L = p.ni < p.nj ? p.ni : p.nj;
+    const int threads = round64(L) < 1024 ? round64(L) : 1024;
+    const size_t lds = (size_t)(12 * p.ni + 4 * p.nj) * sizeof(double);
+    if (lds > 64 * 1024) {
+        e = hipFuncSetAttribute((const void *)k_macro_sweep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_macro_sweep, dim3(1), dim3(threads), lds, st, p);
     return hipGetLastError();
+}
+
+size_t sweep_lds_bytes(int ni, int nj, int vb, size_t s_bytes) {
+    return (size_t)(3 * ni + nj) * vb * s_bytes;
 }
 
 template <int VB>
 static hipError_t launch_sweeps_vb(const Params &p, bool fp32, bool upper, hipStream_t st) {
     const dim3 g((p.nv + VB - 1) / VB, 2);
+    const int L = p.ni < p.nj ? p.ni : p.nj;
+    const int threads = round64(VB * L) < 1024 ? round64(VB * L) : 1024;
     DISPATCH_S(fp32, {
-        const size_t lds = (size_t)2 * p.ni * VB * sizeof(S);
-        const void *fn = !upper ? (p.model == 1 ? (const void *)k_lower<S, true, VB> : (const void *)k_lower<S, false, VB>)
-                                : (p.model == 1 ? (const void *)k_upper<S, true, VB> : (const void *)k_upper<S, false, VB>);
+        const size_t lds = sweep_lds_bytes(p.ni, p.nj, VB, sizeof(S));
+        const void *fn = !upper ? (p.model == 1 ? (const void *)k_sweep<S, true, VB, false> : (const void *)k_sweep<S, false, VB, false>)
+                                : (p.model == 1 ? (const void *)k_sweep<S, true, VB, true> : (const void *)k_sweep<S, false, VB, true>);
         if (lds > 64 * 1024) {
             hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }
         if (!upper) {
-            if (p.model == 1) hipLaunchKernelGGL((k_lower<S, true, VB>), g, dim3(1024), lds, st, p);
-            else hipLaunchKernelGGL((k_lower<S, false, VB>), g, dim3(1024), lds, st, p);
+            if (p.model == 1) hipLaunchKernelGGL((k_sweep<S, true, VB, false>), g, dim3(threads), lds, st, p);
+            else hipLaunchKernelGGL((k_sweep<S, false, VB, false>), g, dim3(threads), lds, st, p);
         } else {
-            if (p.model == 1) hipLaunchKernelGGL((k_upper<S, true, VB>), g, dim3(1024), lds, st, p);
-            else hipLaunchKernelGGL((k_upper<S, false, VB>), g, dim3(1024), lds, st, p);
+            if (p.model == 1) hipLaunchKernelGGL((k_sweep<S, true, VB, true>), g, dim3(threads), lds, st, p);
+            else hipLaunchKernelGGL((k_sweep<S, false, VB, true>), g, dim3(threads), lds, st, p);
         }
     });
     return hipGetLastError();

@@ -16,6 +16,7 @@ hipError_t launch_face_records(const Params &p, bool fp32, hipStream_t st);
 hipError_t launch_flux(const Params &p, bool fp32, hipStream_t st);
 hipError_t launch_macro(const Params &p, hipStream_t st);
 hipError_t launch_sweep(const Params &p, bool fp32, bool upper, int vb, hipStream_t st);
+size_t sweep_lds_bytes(int ni, int nj, int vb, size_t s_bytes);
 hipError_t launch_wall_ghost(const Params &p, bool fp32, hipStream_t st);
 hipError_t launch_explicit(const Params &p, bool fp32, hipStream_t st);
 hipError_t launch_pack(const Params &p, bool fp32, const void *src, double *dst, int sp, int nsp,

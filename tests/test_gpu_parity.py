@@ -123,3 +123,45 @@ def test_cavity_c2_full_size_steps():
     o.implicit_step(2)
     g.step(wl.IMPLICIT, 2)
     assert _rel_species(g.get_state(), o.get_state()) <= 1e-12
+
+
+# ------------------------------------------------------------------ full C2, converged
+@pytest.fixture(scope="module")
+def c2_oracle_converged():
+    """FP64 oracle on the 64^2 / GH 28^2 cavity (Kn = 0.075, CFL 1000) to Res < 1e-8."""
+    o = Oracle(wl.case("cavity_kn0.075"))
+    it, res, ok = o.solve(1e-8, 2000)
+    assert ok
+    return it, o.moments()
+
+
+def test_c2_fp64_converged_fields(c2_oracle_converged):
+    it_o, mo = c2_oracle_converged
+    g = _solver(wl.case("cavity_kn0.075"))
+    it_g, res, ok = g.solve(1e-8, 2000)
+    assert ok and it_g == it_o
+    mg = g.moments()
+    for k in range(4):   # rho, U, V, T
+        assert np.max(np.abs(mg[:, k] - mo[:, k])) <= 1e-10
+
+
+def test_c2_fp32_mixed_converged_fields(c2_oracle_converged):
+    """FP32 distributions/fluxes/sweeps, FP64 moments and predictor: stated bound 1e-5."""
+    it_o, mo = c2_oracle_converged
+    g = _solver(wl.case("cavity_kn0.075", precision=wl.FP32_MIXED))
+    it_g, res, ok = g.solve(1e-8, 2000)
+    assert ok and abs(it_g - it_o) <= 0.25 * it_o
+    mg = g.moments()
+    errs = [float(np.max(np.abs(mg[:, k] - mo[:, k]))) for k in range(4)]
+    print("FP32-mixed converged max abs errors rho, U, V, T:", errs)
+    assert max(errs) <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["cavity_tanh", "cavity_shakhov_nc", "cylinder_limiter"])
+def test_fp32_mixed_step_close_to_fp64_oracle(name):
+    cfg = CASES[name]()
+    cfg["precision"] = wl.FP32_MIXED
+    o, g = _pair(cfg, seed=8)
+    o.implicit_step(2)
+    g.step(wl.IMPLICIT, 2)
+    assert _rel_species(g.get_state(), o.get_state()) <= 2e-6
