@@ -172,7 +172,8 @@ idugks_status validate(const idugks_config *c) {
     if (!c) return fail(IDUGKS_E_INVALID, "null config");
     if (c->struct_size != sizeof(idugks_config)) return fail(IDUGKS_E_INVALID, "struct_size mismatch");
     if (c->ni < 1 || c->nj < 1) return fail(IDUGKS_E_INVALID, "mesh needs ni, nj >= 1");
-    if ((size_t)(12 * c->ni + 4 * c->nj) * 8 > 128 * 1024 || (size_t)(3 * c->ni + c->nj) * 8 * 8 > 128 * 1024)
+    if (std::min(c->ni, c->nj) > 280 || macro_lds_bytes(c->ni, c->nj) > 150 * 1024 ||
+        sweep_lds_bytes(c->ni, c->nj, 8, 8) > 150 * 1024)
         return fail(IDUGKS_E_INVALID, "mesh too large for the LDS-resident sweep fronts");
     if (!c->xn || !c->yn) return fail(IDUGKS_E_INVALID, "missing node coordinates");
     if (c->nvx < 2 || c->nvy < 2) return fail(IDUGKS_E_INVALID, "need nv >= 2 per direction");
@@ -216,6 +217,8 @@ struct Built {
     std::vector<int16_t> vix, viy;
     std::vector<double> area, xc, yc;
     std::vector<CellSide> cs;
+    std::vector<int> hp_off, hp_pos;
+    std::vector<double> sgeo;
     std::vector<Face> faces;
     std::vector<int> wall_faces;
     std::vector<double> gw, wKRT, ginf, hinf, wden, bhalf, eq0;
@@ -457,6 +460,30 @@ idugks_status build(const idugks_config *c, Built &b) {
                 q.ay = (a11 * q.ndy - a12 * q.ndx) / det;
             }
         }
+    // i+j hyperplane ordering of the cells and the static sweep geometry in that order
+    const int nh = ni + nj - 1;
+    b.hp_off.assign(nh + 1, 0);
+    b.hp_pos.assign(b.nc, 0);
+    for (int s = 0, pos = 0; s < nh; ++s) {
+        b.hp_off[s] = pos;
+        const int lo = std::max(0, s - nj + 1), hi = std::min(ni - 1, s);
+        for (int i = lo; i <= hi; ++i) b.hp_pos[i + (s - i) * ni] = pos++;
+        b.hp_off[s + 1] = pos;
+    }
+    b.sgeo.assign((size_t)b.nc * SG_N, 0.0);
+    for (int cidx = 0; cidx < b.nc; ++cidx)
+        for (int s = 0; s < 4; ++s) {
+            const CellSide &q = b.cs[(size_t)4 * cidx + s];
+            double *g = &b.sgeo[(size_t)b.hp_pos[cidx] * SG_N];
+            g[s] = q.nx; g[4 + s] = q.ny; g[8 + s] = q.S;
+            int code = 0;
+            if (q.type != FT_SELF) {
+                code |= SG_DIAG;
+                if (q.nb >= 0) code |= (q.nb < cidx ? SG_LOWER : SG_UPPER) | (q.hp_adj ? SG_ADJ : 0);
+                if (q.type == FT_WALL) code |= SG_WALL | (q.wside << 8);
+            }
+            g[12 + s] = code;
+        }
     // physical time step
     double hmin = 1e300, smax = 0.0;
     for (int cidx = 0; cidx < b.nc; ++cidx) {
@@ -519,7 +546,7 @@ enum Region {
     R_CS, R_FACES, R_WALLF, R_AREA, R_XI, R_ETA, R_W, R_X1, R_WX1, R_Y1, R_WY1, R_VIX, R_VIY,
     R_GW, R_WKRT, R_GINF, R_HINF, R_WDEN, R_BHALF, R_F, R_D1, R_TAB, R_TABS, R_TABF, R_REC,
     R_RECS, R_RECF, R_PART, R_RAW, R_WC, R_MW, R_DW, R_DWD, R_DTIMP, R_RHOOLD, R_DRHO, R_SCAL,
-    R_STAGE, R_MPREP, R_SWB, R_SWC, R_COUNT
+    R_STAGE, R_HPOFF, R_HPPOS, R_SGEO, R_SREC, R_SDRHO, R_MH, R_GR, R_COUNT
 };
 
 Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy, int nwall) {
@@ -534,7 +561,9 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
         S * (size_t)nf * TW, sizeof(Rec) * (size_t)nc, sizeof(Rec) * (size_t)nc, sizeof(Rec) * (size_t)nf,
         8 * (size_t)nc * 4 * NM_MAX, 8 * (size_t)nc * NM_MAX, 8 * 4 * (size_t)nc, 8 * 4 * (size_t)nc,
         8 * 4 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nf, 8 * SC_NUM,
-        8 * (size_t)std::max(nc, 2) * nvp, 8 * 20 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc};
+        8 * (size_t)std::max(nc, 2) * nvp, sizeof(int) * (size_t)(nc + 2), sizeof(int) * (size_t)nc,
+        8 * (size_t)SG_N * nc, 8 * (size_t)SR_N * nc, 8 * 4 * (size_t)nc, 8 * (size_t)MH_N * nc,
+        S * 6 * (size_t)nc * nvp};
     for (int r = 0; r < R_COUNT; ++r) L.add(sizes[r]);
     L.bytes = (L.bytes + 255) & ~size_t(255);
     return L;
@@ -612,7 +641,7 @@ idugks_status read_scalars(idugks_ctx *x, double *sc) {
 // slice, and the two LDS fronts (2 x ni x vb values) within 128 KiB.
 int choose_vb(int nv, int ni, int nj, size_t s_bytes) {
     int vb = nv >= 64 * 256 ? 64 : nv >= 32 * 256 ? 32 : nv >= 16 * 128 ? 16 : 8;
-    while (vb > 8 && sweep_lds_bytes(ni, nj, vb, s_bytes) > 128 * 1024) vb /= 2;
+    while (vb > 8 && sweep_lds_bytes(ni, nj, vb, s_bytes) > 150 * 1024) vb /= 2;
     return vb;
 }
 
@@ -717,7 +746,9 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     p.MW = (double *)R(R_MW); p.dW = (double *)R(R_DW); p.DWd = (double *)R(R_DWD);
     p.dtimp = (double *)R(R_DTIMP); p.rho_old = (double *)R(R_RHOOLD); p.drho = (double *)R(R_DRHO);
     p.scal = (double *)R(R_SCAL);
-    p.mprep = (double *)R(R_MPREP); p.swb = (double *)R(R_SWB); p.swc = (double *)R(R_SWC);
+    p.hp_off = (const int *)R(R_HPOFF); p.hp_pos = (const int *)R(R_HPPOS);
+    p.sgeo = (const double *)R(R_SGEO); p.srec = (double *)R(R_SREC); p.sdrho = (double *)R(R_SDRHO);
+    p.mh = (double *)R(R_MH); p.gr = R(R_GR);
     x->stage = (double *)R(R_STAGE);
 
     auto up = [&](void *dst, const void *src, size_t n) {
@@ -725,13 +756,14 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     };
     hipError_t e = hipSuccess;
 #define UP(r, vec) if (e == hipSuccess && !(vec).empty()) e = up(R(r), (vec).data(), (vec).size() * sizeof((vec)[0]))
-    UP(R_CS, b.cs); UP(R_FACES, b.faces); UP(R_WALLF, b.wall_faces); UP(R_AREA, b.area);
+    UP(R_CS, b.cs); UP(R_HPOFF, b.hp_off); UP(R_HPPOS, b.hp_pos); UP(R_SGEO, b.sgeo); UP(R_FACES, b.faces); UP(R_WALLF, b.wall_faces); UP(R_AREA, b.area);
     UP(R_XI, b.xi); UP(R_ETA, b.eta); UP(R_W, b.w); UP(R_X1, b.x1); UP(R_WX1, b.wx1);
     UP(R_Y1, b.y1); UP(R_WY1, b.wy1); UP(R_VIX, b.vix); UP(R_VIY, b.viy); UP(R_GW, b.gw);
     UP(R_WKRT, b.wKRT); UP(R_GINF, b.ginf); UP(R_HINF, b.hinf); UP(R_WDEN, b.wden); UP(R_BHALF, b.bhalf);
     UP(R_STAGE, b.eq0);
 #undef UP
     if (e == hipSuccess) e = hipMemsetAsync(p.drho, 0, sizeof(double) * b.nf, x->st);
+    if (e == hipSuccess) e = hipMemsetAsync(p.sdrho, 0, sizeof(double) * 4 * b.nc, x->st);
     if (e == hipSuccess) e = hipMemsetAsync(p.rho_old, 0, sizeof(double) * b.nc, x->st);
     if (e == hipSuccess) e = hipMemsetAsync(p.scal, 0, sizeof(double) * SC_NUM, x->st);
     if (e == hipSuccess) e = hipMemsetAsync(p.dW, 0, sizeof(double) * 4 * b.nc, x->st);
@@ -950,6 +982,7 @@ idugks_status idugks_set_state(idugks_ctx *x, const double *f, int32_t on_host) 
     }
     HIPCHK(hipMemsetAsync(x->p.rho_old, 0, sizeof(double) * x->p.nc, x->st));
     HIPCHK(hipMemsetAsync(x->p.drho, 0, sizeof(double) * x->p.nf, x->st));
+    HIPCHK(hipMemsetAsync(x->p.sdrho, 0, sizeof(double) * 4 * x->p.nc, x->st));
     idugks_status s = finalize_state(x, 0);
     double sc[SC_NUM];
     if (s == IDUGKS_OK) s = read_scalars(x, sc);

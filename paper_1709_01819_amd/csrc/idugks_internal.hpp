@@ -62,6 +62,13 @@ struct Rec {
     double rw;               // wall faces: density of the reflected Maxwellian
 };
 
+constexpr int SG_N = 16, SR_N = 12, MH_N = 57;
+
+// Static per-cell geometry of the micro and macro sweeps (built on the host).
+// code bits: SG_DIAG the side counts in the diagonal (not self-periodic), SG_LOWER /
+// SG_UPPER the neighbour has a lower / higher index, SG_ADJ the neighbour is on an adjacent
+// i+j hyperplane (else it sits across a periodic seam), SG_WALL wall side.
+enum SweepCode : int { SG_DIAG = 1, SG_LOWER = 2, SG_UPPER = 4, SG_ADJ = 8, SG_WALL = 16 };
 // Scalars kept on the device (FP64).
 enum Scalar : int { SC_SCALE = 0, SC_RES = 1, SC_MASS = 2, SC_FLAG = 3, SC_NUM = 8 };
 
@@ -85,10 +92,18 @@ struct Params {
     const double *bhalf;     // [nf][NM] moments of the incoming half of the ghost distribution
     // state and work (S-typed arrays as void*)
     void *f, *d1, *tab, *tabs, *tabf;
+    void *gr;                // [nc][6][nvp] phi-bar-plus and its limited gradient (G: b, gx, gy; H: b, gx, gy)
     Rec *rec, *recs, *recf;
     double *part, *raw, *Wc, *MW, *dW, *DWd, *dtimp, *rho_old, *drho, *scal;
-    double *mprep;           // [nc][4][5] lambda_j and F_n(W_j) per cell side (macro LU-SGS)
-    double *swb, *swc;       // [nc] diagonal base and collision coefficient of the micro sweeps
+    // per-cell data of the sweeps stored in i+j hyperplane order (position hp_pos[c]), so
+    // that the cells of one hyperplane are contiguous and can be staged into LDS at once
+    const int *hp_off;       // [nh+1] first position of each hyperplane
+    const int *hp_pos;       // [nc] position of each cell
+    const double *sgeo;      // [nc][SG_N] nx[4], ny[4], S[4], code[4] (static)
+    double *srec;            // [nc][SR_N] U, V, c0, c1, c2c, c3, kqx, kqy, iRT, KRT, cst, base
+    double *sdrho;           // [nc][4] wall ghost density increment per cell side
+    double *mh;              // [nc][MH_N] macro: M_W, diagonal, codes, per side nx, ny, S,
+                             //                lambda_j, F_n(W_j), W_j
 };
 
 }  // namespace idugks

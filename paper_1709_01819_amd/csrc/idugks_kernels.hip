@@ -65,6 +65,23 @@ DEV void block_sum(double (&a)[N], double *sh) {
     __syncthreads();
 }
 
+// Sum over the whole block written to out[0..N) by lanes 0..N-1 (fixed order; no dynamic
+// indexing of the register array).  sh must hold (blockDim/64)*N doubles.
+template <int N>
+DEV void block_sum_store(double (&a)[N], double *sh, double *out) {
+    wave_sum<N>(a);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int m = 0; m < N; ++m) sh[wid * N + m] = a[m];
+    __syncthreads();
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += sh[w * N + m];
+        out[m] = s;
+    }
+}
+
 template <class T>
 struct RecT {
     T U, V, c0, c1, c2c, c3, kqx, kqy, iRT, KRT, ab, bb;
@@ -266,8 +283,7 @@ __global__ __launch_bounds__(256) void k_raw(Params p) {
     for (int m = 0; m < NM; ++m) a[m] = 0.0;
     for (int v = threadIdx.x; v < p.nv; v += blockDim.x)
         acc_moments<NM>(a, p.w[v], p.xi[v], p.eta[v], (double)G[v], (double)H[v]);
-    block_sum<NM>(a, sh);
-    if (threadIdx.x < NM) p.raw[(size_t)c * NM_MAX + threadIdx.x] = a[threadIdx.x];
+    block_sum_store<NM>(a, sh, p.raw + (size_t)c * NM_MAX);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -339,14 +355,17 @@ __global__ __launch_bounds__(256) void k_records(Params p, int which) {
             qy = p.rec[c].qy;
         }
     }
-    if (which == 1 && lane == 0) {
-        const double cst = 2.0 * p.area[c] / (2.0 * tau + p.dt);
-        p.swc[c] = cst;                             // collision coefficient of Eq. 26
-        p.swb[c] = p.area[c] / p.dtimp[c] + cst;    // cell part of the diagonal of Eq. 26
-    }
     Rec *out = which == 0 ? p.rec + c : p.recs + c;
     S *tab = (S *)(which == 0 ? p.tab : p.tabs) + (size_t)c * TW;
     build_eq<S, SHAK>(p, rho, U, V, RT, tau, qx, qy, out, tab, lane);
+    if (which == 1 && lane == 0) {
+        const Rec r = *out;  // written by this lane
+        double *o = p.srec + (size_t)p.hp_pos[c] * SR_N;
+        o[0] = r.U; o[1] = r.V; o[2] = r.c0; o[3] = r.c1; o[4] = r.c2c; o[5] = r.c3;
+        o[6] = r.kqx; o[7] = r.kqy; o[8] = r.iRT; o[9] = r.KRT;
+        o[10] = 2.0 * p.area[c] / (2.0 * tau + p.dt);    // collision coefficient (Eq. 26)
+        o[11] = p.area[c] / p.dtimp[c] + o[10];           // cell part of the diagonal
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -428,6 +447,9 @@ __global__ __launch_bounds__(256) void k_partials(Params p) {
         const T x = (T)p.xi[v], y = (T)p.eta[v];
         T bG, bH, gxG, gyG, gxH, gyH;
         recon_cell<S, T, SHAK, LIM>(p, c, v, ix, iy, x, y, sc, bG, bH, gxG, gyG, gxH, gyH);
+        S *gr = (S *)p.gr + (size_t)c * 6 * p.nvp + v;
+        gr[0] = (S)bG; gr[p.nvp] = (S)gxG; gr[2 * p.nvp] = (S)gyG;
+        gr[3 * p.nvp] = (S)bH; gr[4 * p.nvp] = (S)gxH; gr[5 * p.nvp] = (S)gyH;
         const double wv = p.w[v];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -444,8 +466,7 @@ __global__ __launch_bounds__(256) void k_partials(Params p) {
             for (int m = 0; m < NM; ++m) acc[s * NM + m] += a[m];
         }
     }
-    block_sum<4 * NM>(acc, sh);
-    if (threadIdx.x < 4 * NM) p.part[(size_t)c * 4 * NM + threadIdx.x] = acc[threadIdx.x];
+    block_sum_store<4 * NM>(acc, sh, p.part + (size_t)c * 4 * NM);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -498,15 +519,16 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
     __shared__ double sh[4 * 4];
     const int c = xcd_remap(blockIdx.x, p.nc);
     const CellSide *cs = p.cs + 4 * c;
-    const T sc = (T)p.scal[SC_SCALE], h = (T)p.h;
+    const T h = (T)p.h;
     const int TW = p.nvx + p.nvy;
     S *MG = (S *)p.d1 + ((size_t)c * 2) * p.nvp, *MH = MG + p.nvp;
     double mw[4] = {0.0, 0.0, 0.0, 0.0};
     for (int v = threadIdx.x; v < p.nv; v += blockDim.x) {
         const int ix = p.vix[v], iy = p.viy[v];
         const T x = (T)p.xi[v], y = (T)p.eta[v];
-        T bG, bH, gxG, gyG, gxH, gyH;
-        recon_cell<S, T, SHAK, LIM>(p, c, v, ix, iy, x, y, sc, bG, bH, gxG, gyG, gxH, gyH);
+        const S *gr = (const S *)p.gr + (size_t)c * 6 * p.nvp + v;
+        const T bG = gr[0], gxG = gr[p.nvp], gyG = gr[2 * p.nvp];
+        const T bH = gr[3 * p.nvp], gxH = gr[4 * p.nvp], gyH = gr[5 * p.nvp];
         T accG = T(0), accH = T(0);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -522,9 +544,9 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
                 fG = bG + gxG * rx + gyG * ry;
                 fH = bH + gxH * rx + gyH * ry;
             } else if (type == FT_INTERIOR) {
-                T nG, nH, ngxG, ngyG, ngxH, ngyH;
-                recon_cell<S, T, SHAK, LIM>(p, cs[s].nb, v, ix, iy, x, y, sc, nG, nH, ngxG, ngyG,
-                                            ngxH, ngyH);
+                const S *ng = (const S *)p.gr + (size_t)cs[s].nb * 6 * p.nvp + v;
+                const T nG = ng[0], ngxG = ng[p.nvp], ngyG = ng[2 * p.nvp];
+                const T nH = ng[3 * p.nvp], ngxH = ng[4 * p.nvp], ngyH = ng[5 * p.nvp];
                 const T rx = (T)(cs[s].dx - cs[s].ndx) - h * x;
                 const T ry = (T)(cs[s].dy - cs[s].ndy) - h * y;
                 fG = nG + ngxG * rx + ngyG * ry;
@@ -556,8 +578,7 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
         mw[2] += wv * dy * dG;
         mw[3] += 0.5 * wv * ((dx * dx + dy * dy) * dG + (double)accH);
     }
-    block_sum<4>(mw, sh);
-    if (threadIdx.x < 4) p.MW[(size_t)c * 4 + threadIdx.x] = mw[threadIdx.x];
+    block_sum_store<4>(mw, sh, p.MW + (size_t)c * 4);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -594,9 +615,13 @@ __global__ __launch_bounds__(256) void k_macro_prep(Params p) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= p.nc) return;
     const CellSide *cs = p.cs + 4 * c;
+    double *m = p.mh + (size_t)p.hp_pos[c] * MH_N;
     const double U = p.rec[c].U, V = p.rec[c].V, C = sqrt(p.gam * p.rec[c].RT);
     double ls = 0.0, lw = 0.0;
     for (int s = 0; s < 4; ++s) {
+        m[5 + s] = p.sgeo[(size_t)p.hp_pos[c] * SG_N + 12 + s];  // code
+        double *ms = m + 9 + 12 * s;
+        ms[0] = cs[s].nx; ms[1] = cs[s].ny; ms[2] = cs[s].S;
         if (cs[s].type == FT_SELF) continue;
         const double l = (fabs(U * cs[s].nx + V * cs[s].ny) + C) * cs[s].S;
         ls += l;
@@ -604,140 +629,186 @@ __global__ __launch_bounds__(256) void k_macro_prep(Params p) {
         const int j = cs[s].nb;
         if (j < 0) continue;
         const double *Wj = p.Wc + (size_t)j * 4;
-        double *mp = p.mprep + ((size_t)c * 4 + s) * 5;
-        mp[0] = fabs((Wj[1] * cs[s].nx + Wj[2] * cs[s].ny) / Wj[0]) + sqrt(p.gam * p.rec[j].RT);
+        ms[3] = fabs((Wj[1] * cs[s].nx + Wj[2] * cs[s].ny) / Wj[0]) + sqrt(p.gam * p.rec[j].RT);
         double F0[4];
         euler_flux(Wj, cs[s].nx, cs[s].ny, p.K, F0);
-        for (int a = 0; a < 4; ++a) mp[1 + a] = F0[a];
+        for (int a = 0; a < 4; ++a) {
+            ms[4 + a] = F0[a];
+            ms[8 + a] = Wj[a];
+        }
     }
     const double dti = p.cfl_imp * p.area[c] / ls;
     p.dtimp[c] = dti;
-    p.DWd[c] = p.area[c] / dti + 0.5 * ls + 0.5 * lw;
+    for (int a = 0; a < 4; ++a) m[a] = p.MW[(size_t)c * 4 + a];
+    m[4] = p.area[c] / dti + 0.5 * ls + 0.5 * lw;
 }
 
-// r += sign * 1/2 S (F_n(W_j + dW_j) - F_n(W_j) - lambda_j dW_j) for neighbour j on side sd
-DEV void macro_add(const Params &p, int c, int sd, const CellSide &q, const double dWj[4],
-                   double r[4], double sign) {
-    const double *mp = p.mprep + ((size_t)c * 4 + sd) * 5;
-    const double *Wj = p.Wc + (size_t)q.nb * 4;
-    double Wn[4], F1[4];
-    for (int a = 0; a < 4; ++a) Wn[a] = Wj[a] + dWj[a];
-    euler_flux(Wn, q.nx, q.ny, p.K, F1);
-    for (int a = 0; a < 4; ++a) r[a] += sign * 0.5 * q.S * (F1[a] - mp[1 + a] - mp[0] * dWj[a]);
-}
+// Cooperative staging of per-cell sweep data: every lane of the block loads a few of the
+// values of the next hyperplane's cells (one step ahead, into registers), then stores
+// them into an LDS buffer after the current hyperplane is done.
+constexpr int PF = 16;
 
-// Macro LU-SGS sweeps over i+j hyperplanes in one block (one lane per cell of a
-// hyperplane).  LDS holds the previous hyperplane's increments (fronts) and the
-// increments of the cells next to a periodic seam (wI: column i = 0 / ni-1, wJ: row
-// j = 0 / nj-1), which are the only non-adjacent neighbours.
+template <class T>
+struct Stager {
+    T v[PF];
+    DEV void load(const double *src, int n) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int e = threadIdx.x + q * blockDim.x;
+            v[q] = e < n ? (T)src[e] : T(0);
+        }
+    }
+    DEV void store(T *dst, int n) const {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int e = threadIdx.x + q * blockDim.x;
+            if (e < n) dst[e] = v[q];
+        }
+    }
+};
+
+// Macro LU-SGS sweeps over i+j hyperplanes in one block, one lane per cell of a
+// hyperplane: r -= 1/2 S (F_n(W_j + dW_j) - F_n(W_j) - lambda_j dW_j) over the lower
+// (forward) or upper (backward) neighbours.  LDS holds the previous hyperplane's
+// increments (fronts), those of the cells next to a periodic seam (wI: column i = 0 /
+// ni-1, wJ: row j = 0 / nj-1; the only non-adjacent neighbours) and the staged per-cell
+// data of the current and the next hyperplane.
 __global__ __launch_bounds__(1024) void k_macro_sweep(Params p) {
     extern __shared__ double lds[];
-    const int ni = p.ni, nj = p.nj, nh = ni + nj - 1;
+    const int ni = p.ni, nj = p.nj, nh = ni + nj - 1, L = ni < nj ? ni : nj;
     double *f0 = lds, *f1 = lds + 4 * ni, *wI = lds + 8 * ni, *wJ = wI + 4 * nj;
-    for (int s = 0; s < nh; ++s) {
-        int lo, hi;
-        hp_bounds(s, ni, nj, lo, hi);
-        for (int i = lo + threadIdx.x; i <= hi; i += blockDim.x) {
-            const int j = s - i, c = i + j * ni;
-            const CellSide *cs = p.cs + 4 * c;
-            double r[4];
-            for (int a = 0; a < 4; ++a) r[a] = p.MW[(size_t)c * 4 + a];
-            for (int sd = 0; sd < 4; ++sd) {
-                const CellSide q = cs[sd];
-                if (q.type == FT_SELF || q.nb < 0 || q.nb > c) continue;
-                const double *src = q.hp_adj ? f0 + 4 * (sd == 0 ? i - 1 : i)
-                                             : (sd < 2 ? wI + 4 * j : wJ + 4 * i);
-                double dWj[4] = {src[0], src[1], src[2], src[3]};
-                macro_add(p, c, sd, q, dWj, r, -1.0);
-            }
-            const double D = p.DWd[c];
-            for (int a = 0; a < 4; ++a) {
-                const double d = r[a] / D;
-                p.dW[(size_t)c * 4 + a] = d;
-                f1[4 * i + a] = d;
-                if (i == 0) wI[4 * j + a] = d;
-                if (j == 0) wJ[4 * i + a] = d;
-            }
-        }
+    double *st0 = wJ + 4 * ni, *st1 = st0 + (size_t)L * MH_N;
+    Stager<double> pf;
+    for (int dir = 0; dir < 2; ++dir) {
+        const bool upper = dir == 1;
+        const int need = upper ? SG_UPPER : SG_LOWER;
+        int s = upper ? nh - 1 : 0;
+        pf.load(p.mh + (size_t)p.hp_off[s] * MH_N, (p.hp_off[s + 1] - p.hp_off[s]) * MH_N);
+        pf.store(st0, (p.hp_off[s + 1] - p.hp_off[s]) * MH_N);
         lds_barrier();
-        double *t = f0; f0 = f1; f1 = t;
-    }
-    for (int s = nh - 1; s >= 0; --s) {
-        int lo, hi;
-        hp_bounds(s, ni, nj, lo, hi);
-        for (int i = lo + threadIdx.x; i <= hi; i += blockDim.x) {
-            const int j = s - i, c = i + j * ni;
-            const CellSide *cs = p.cs + 4 * c;
-            double r[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int sd = 0; sd < 4; ++sd) {
-                const CellSide q = cs[sd];
-                if (q.type == FT_SELF || q.nb < 0 || q.nb < c) continue;
-                const double *src = q.hp_adj ? f0 + 4 * (sd == 1 ? i + 1 : i)
-                                             : (sd < 2 ? wI + 4 * j : wJ + 4 * i);
-                double dWj[4] = {src[0], src[1], src[2], src[3]};
-                macro_add(p, c, sd, q, dWj, r, 1.0);
+        for (int step = 0; step < nh; ++step, s += upper ? -1 : 1) {
+            const int sn = upper ? s - 1 : s + 1;
+            const bool more = step + 1 < nh;
+            const int nn = more ? (p.hp_off[sn + 1] - p.hp_off[sn]) * MH_N : 0;
+            if (more) pf.load(p.mh + (size_t)p.hp_off[sn] * MH_N, nn);
+            int lo, hi;
+            hp_bounds(s, ni, nj, lo, hi);
+            const int k = threadIdx.x, i = lo + k;
+            if (i <= hi) {
+                const int j = s - i, c = i + j * ni;
+                const double *m = st0 + (size_t)k * MH_N;
+                double r[4];
+                for (int a = 0; a < 4; ++a) r[a] = upper ? 0.0 : m[a];
+#pragma unroll
+                for (int sd = 0; sd < 4; ++sd) {
+                    const int code = (int)m[5 + sd];
+                    if (!(code & need)) continue;
+                    const double *ms = m + 9 + 12 * sd;
+                    const int fi = upper ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
+                    const double *src = (code & SG_ADJ) ? f0 + 4 * fi : (sd < 2 ? wI + 4 * j : wJ + 4 * i);
+                    double Wn[4], F1[4];
+                    for (int a = 0; a < 4; ++a) Wn[a] = ms[8 + a] + src[a];
+                    euler_flux(Wn, ms[0], ms[1], p.K, F1);
+                    const double h = (upper ? 0.5 : -0.5) * ms[2];
+                    for (int a = 0; a < 4; ++a) r[a] += h * (F1[a] - ms[4 + a] - ms[3] * src[a]);
+                }
+                for (int a = 0; a < 4; ++a) {
+                    // backward sweep: this lane wrote dW of this cell in the forward sweep
+                    const double d = upper ? p.dW[(size_t)c * 4 + a] - r[a] / m[4] : r[a] / m[4];
+                    p.dW[(size_t)c * 4 + a] = d;
+                    f1[4 * i + a] = d;
+                    if (i == (upper ? ni - 1 : 0)) wI[4 * j + a] = d;
+                    if (j == (upper ? nj - 1 : 0)) wJ[4 * i + a] = d;
+                }
             }
-            const double D = p.DWd[c];
-            for (int a = 0; a < 4; ++a) {
-                const double d = p.dW[(size_t)c * 4 + a] - r[a] / D;  // written by this lane
-                p.dW[(size_t)c * 4 + a] = d;
-                f1[4 * i + a] = d;
-                if (i == ni - 1) wI[4 * j + a] = d;
-                if (j == nj - 1) wJ[4 * i + a] = d;
-            }
+            if (more) pf.store(st1, nn);
+            lds_barrier();
+            double *t = f0; f0 = f1; f1 = t;
+            t = st0; st0 = st1; st1 = t;
         }
-        lds_barrier();
-        double *t = f0; f0 = f1; f1 = t;
     }
 }
 
 // ---------------------------------------------------------------------------------------
 // micro LU-SGS sweeps (Eq. 24-26) over i+j hyperplanes.  One block per (velocity slice,
-// species); lanes = VB velocities x (blockDim/VB) cells of a hyperplane.  Increments of
-// the previous hyperplane and of the cells next to a periodic seam stay in LDS.  Each
-// lane issues the HBM loads of its next (cell, v) item before computing the current one,
-// so they overlap the dependent chain and the barrier.
+// species); lanes = VB velocities x (blockDim/VB) cells of a hyperplane.  LDS holds the
+// increments of the previous hyperplane and of the cells next to a periodic seam, and the
+// staged per-cell data (equilibrium record, diagonal, geometry) of the current and next
+// hyperplane; each lane also loads the HBM values of its next (cell, v) item before
+// computing the current one.
 // ---------------------------------------------------------------------------------------
+constexpr int STG = 28;  // staged values per cell: record (12), nx ny S (12), codes (4)
+
 template <class T>
 struct SweepItem {
-    int c, i, j;
     bool ok;
-    T a, b, e;  // lower: M, phi~, factored Maxwellian; upper: forward increment, phi~
+    int i;
+    T aG, aH, bG, bH, e;  // forward: M, phi~ (G, H), factored Maxwellian; backward: increment, phi~
 };
 
-template <class S, bool SHAK, int VB, bool UPPER>
-DEV SweepItem<S> sweep_load(const Params &p, int s, int pass, int slot, int cpp, int sp, int v,
-                            bool vok, int ix, int iy) {
+// the item of (hyperplane s, pass) for this lane; cells of a hyperplane by increasing i
+template <class S, bool UPPER>
+DEV SweepItem<S> sweep_load(const Params &p, int s, int pass, int slot, int cpp, int v, bool vok,
+                            int ix, int iy) {
     SweepItem<S> it;
     it.ok = false;
-    it.c = it.i = it.j = 0;
-    it.a = it.b = it.e = S(0);
+    it.i = 0;
+    it.aG = it.aH = it.bG = it.bH = it.e = S(0);
+    if (s < 0 || s >= p.ni + p.nj - 1) return it;
     int lo, hi;
     hp_bounds(s, p.ni, p.nj, lo, hi);
     const int i = lo + slot + pass * cpp;
-    if (vok && i <= hi) {
-        it.ok = true;
-        it.i = i;
-        it.j = s - i;
-        it.c = i + it.j * p.ni;
-        const size_t o = ((size_t)it.c * 2 + sp) * p.nvp + v;
-        it.a = ((const S *)p.d1)[o];
-        it.b = ((const S *)p.f)[o];
-        if (!UPPER) {
-            const S *tb = (const S *)p.tabs + (size_t)it.c * (p.nvx + p.nvy);
-            it.e = tb[ix] * tb[p.nvx + iy];
-        }
+    if (!(vok && i <= hi)) return it;
+    it.ok = true;
+    it.i = i;
+    const int c = i + (s - i) * p.ni;
+    const size_t o = (size_t)c * 2 * p.nvp + v;
+    it.aG = ((const S *)p.d1)[o];
+    it.aH = ((const S *)p.d1)[o + p.nvp];
+    it.bG = ((const S *)p.f)[o];
+    it.bH = ((const S *)p.f)[o + p.nvp];
+    if (!UPPER) {
+        const S *tb = (const S *)p.tabs + (size_t)c * (p.nvx + p.nvy);
+        it.e = tb[ix] * tb[p.nvx + iy];
     }
     return it;
 }
 
+// staged values of hyperplane s: forward sweep record (12) + geometry (16); backward sweep
+// replaces the equilibrium part of the record by the wall ghost increments of the 4 sides
+template <class T, bool UPPER>
+DEV void stage_load(const Params &p, Stager<T> &pf, int s) {
+    const int off = p.hp_off[s], n = (p.hp_off[s + 1] - off) * STG;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        const int e = threadIdx.x + q * blockDim.x;
+        T val = T(0);
+        if (e < n) {
+            const int k = e / STG, r = e % STG;
+            if (r >= SR_N) val = (T)p.sgeo[(size_t)(off + k) * SG_N + (r - SR_N)];
+            else if (!UPPER || r >= 10) val = (T)p.srec[(size_t)(off + k) * SR_N + r];
+            else if (r < 4) val = (T)p.sdrho[(size_t)(off + k) * 4 + r];
+        }
+        pf.v[q] = val;
+    }
+}
+
+constexpr int RING = 4;  // items in flight per lane
+
+// Micro LU-SGS sweeps (Eq. 24-26) over i+j hyperplanes.  One block per velocity slice;
+// lanes = VB velocities x (blockDim/VB) cells of a hyperplane, each lane handling both
+// species (they share the diagonal and the couplings).  LDS holds the increments of the
+// previous hyperplane and of the cells next to a periodic seam, and the staged per-cell
+// data (record, diagonal, geometry) of the current and next hyperplane.  Each lane keeps
+// the HBM loads of its next RING items in flight.
 template <class S, bool SHAK, int VB, bool UPPER>
-__global__ __launch_bounds__(1024) void k_sweep(Params p) {
+__global__ __launch_bounds__(512) void k_sweep(Params p) {
     using T = S;
     extern __shared__ unsigned char lds_raw[];
-    const int ni = p.ni, nj = p.nj, nh = ni + nj - 1;
+    const int ni = p.ni, nj = p.nj, nh = ni + nj - 1, L = ni < nj ? ni : nj;
+    const int FR = (3 * ni + nj) * VB;   // one species' fronts
     T *f0 = (T *)lds_raw, *f1 = f0 + ni * VB, *wI = f1 + ni * VB, *wJ = wI + nj * VB;
-    const int sp = blockIdx.y;
+    T *st0 = (T *)lds_raw + 2 * FR, *st1 = st0 + L * STG;
     const int vl = threadIdx.x % VB, slot = threadIdx.x / VB, cpp = blockDim.x / VB;
     const int v = blockIdx.x * VB + vl;
     const bool vok = v < p.nv;
@@ -745,65 +816,100 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p) {
     const T x = (T)p.xi[vv], y = (T)p.eta[vv];
     const int ix = p.vix[vv], iy = p.viy[vv];
     const T sc = (T)p.scal[SC_SCALE];
-    auto npass_of = [&](int s) {
+    const int need = UPPER ? SG_UPPER : SG_LOWER;
+    const int dirn = UPPER ? -1 : 1;
+    int s = UPPER ? nh - 1 : 0;
+    Stager<T> pf;
+    stage_load<T, UPPER>(p, pf, s);
+    pf.store(st0, (p.hp_off[s + 1] - p.hp_off[s]) * STG);
+    // prefetch ring: items (ls, lp) ahead of the current one
+    SweepItem<T> ring[RING];
+    int ls = s, lp = 0;
+    auto npass_of = [&](int h) {
         int lo, hi;
-        hp_bounds(s, ni, nj, lo, hi);
+        hp_bounds(h, ni, nj, lo, hi);
         return (hi - lo) / cpp + 1;
     };
-    int s = UPPER ? nh - 1 : 0;
-    SweepItem<T> nxt = sweep_load<S, SHAK, VB, UPPER>(p, s, 0, slot, cpp, sp, v, vok, ix, iy);
-    for (int step = 0; step < nh; ++step, s += UPPER ? -1 : 1) {
-        const int npass = npass_of(s);
+#pragma unroll
+    for (int q = 0; q < RING; ++q) {
+        ring[q] = sweep_load<S, UPPER>(p, ls, lp, slot, cpp, v, vok, ix, iy);
+        if (ls >= 0 && ls < nh && ++lp == npass_of(ls)) { lp = 0; ls += dirn; }
+    }
+    lds_barrier();
+    for (int step = 0; step < nh; ++step, s += dirn) {
+        const int sn = s + dirn;
+        const bool more = step + 1 < nh;
+        if (more) stage_load<T, UPPER>(p, pf, sn);
+        int lo, hi;
+        hp_bounds(s, ni, nj, lo, hi);
+        const int npass = (hi - lo) / cpp + 1;
         for (int pass = 0; pass < npass; ++pass) {
-            const SweepItem<T> cur = nxt;
-            if (pass + 1 < npass)
-                nxt = sweep_load<S, SHAK, VB, UPPER>(p, s, pass + 1, slot, cpp, sp, v, vok, ix, iy);
-            else if (step + 1 < nh)
-                nxt = sweep_load<S, SHAK, VB, UPPER>(p, UPPER ? s - 1 : s + 1, 0, slot, cpp, sp, v,
-                                                     vok, ix, iy);
+            const SweepItem<T> cur = ring[0];
+#pragma unroll
+            for (int q = 0; q + 1 < RING; ++q) ring[q] = ring[q + 1];
+            ring[RING - 1] = sweep_load<S, UPPER>(p, ls, lp, slot, cpp, v, vok, ix, iy);
+            if (ls >= 0 && ls < nh && ++lp == npass_of(ls)) { lp = 0; ls += dirn; }
             if (!cur.ok) continue;
-            const int c = cur.c, i = cur.i, j = cur.j;
-            const CellSide *cs = p.cs + 4 * c;
-            T D = (T)p.swb[c], sum;
+            const int i = cur.i, j = s - i;
+            const T *m = st0 + (i - lo) * STG;
+            T D = m[11], sG, sH;
             if (!UPPER) {
-                const RecT<T> r = load_rec<T>(p.recs[c]);
+                RecT<T> r;
+                r.U = m[0]; r.V = m[1]; r.c0 = m[2]; r.c1 = m[3]; r.c2c = m[4]; r.c3 = m[5];
+                r.kqx = m[6]; r.kqy = m[7]; r.iRT = m[8]; r.KRT = m[9];
                 T eG, eH;
                 eq_eval<T, SHAK>(r, x, y, cur.e, eG, eH);
-                sum = cur.a - (T)p.swc[c] * (sc * cur.b - (sp == 0 ? eG : eH));
+                sG = cur.aG - m[10] * (sc * cur.bG - eG);
+                sH = cur.aH - m[10] * (sc * cur.bH - eH);
             } else {
-                sum = T(0);
+                sG = sH = T(0);
             }
 #pragma unroll
             for (int sd = 0; sd < 4; ++sd) {
-                const int type = cs[sd].type;
-                if (type == FT_SELF) continue;
-                const T un = x * (T)cs[sd].nx + y * (T)cs[sd].ny, Sk = (T)cs[sd].S;
+                const int code = (int)m[SR_N + 12 + sd];
+                if (!(code & SG_DIAG)) continue;
+                const T un = x * m[SR_N + sd] + y * m[SR_N + 4 + sd], Sk = m[SR_N + 8 + sd];
                 if (un > T(0)) {
                     D += un * Sk;
                 } else if (un < T(0)) {
-                    const int nb = cs[sd].nb;
-                    if (UPPER && type == FT_WALL) {
-                        const int ws = cs[sd].wside;
-                        const T in = -un * Sk * (T)p.drho[cs[sd].face] * (T)p.gw[(size_t)ws * p.nvp + v];
-                        sum += sp == 0 ? in : in * (T)p.wKRT[ws];
-                    } else if (nb >= 0 && (UPPER ? nb > c : nb < c)) {
+                    if (code & need) {
                         const int fi = UPPER ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
-                        const T dj = cs[sd].hp_adj ? f0[fi * VB + vl]
-                                                   : (sd < 2 ? wI[j * VB + vl] : wJ[i * VB + vl]);
-                        sum -= un * Sk * dj;
+                        const int li = (code & SG_ADJ) ? fi * VB + vl
+                                                       : (sd < 2 ? (2 * ni + j) * VB + vl : (2 * ni + nj + i) * VB + vl);
+                        const T cf = -un * Sk;
+                        // li indexes the front arrays of this step: f0 (adjacent) or wI / wJ
+                        const T dG = (code & SG_ADJ) ? f0[li] : ((T *)lds_raw)[li];
+                        const T dH = (code & SG_ADJ) ? f0[FR + li] : ((T *)lds_raw)[FR + li];
+                        sG += cf * dG;
+                        sH += cf * dH;
+                    } else if (UPPER && (code & SG_WALL)) {
+                        const int ws = (code >> 8) & 3;
+                        const T gw = (T)p.gw[(size_t)ws * p.nvp + v] * m[sd] * (-un * Sk);
+                        sG += gw;
+                        sH += gw * (T)p.wKRT[ws];
                     }
                 }
             }
-            const size_t o = ((size_t)c * 2 + sp) * p.nvp + v;
-            const T d = UPPER ? cur.a + sum / D : sum / D;
-            if (UPPER) ((S *)p.f)[o] = (S)(sc * cur.b + d);
-            else ((S *)p.d1)[o] = (S)d;
-            f1[i * VB + vl] = d;
-            if (i == (UPPER ? ni - 1 : 0)) wI[j * VB + vl] = d;
-            if (j == (UPPER ? nj - 1 : 0)) wJ[i * VB + vl] = d;
+            const size_t o = (size_t)(i + j * ni) * 2 * p.nvp + v;
+            const T iD = T(1) / D;
+            const T dG = UPPER ? cur.aG + sG * iD : sG * iD;
+            const T dH = UPPER ? cur.aH + sH * iD : sH * iD;
+            if (UPPER) {
+                ((S *)p.f)[o] = (S)(sc * cur.bG + dG);
+                ((S *)p.f)[o + p.nvp] = (S)(sc * cur.bH + dH);
+            } else {
+                ((S *)p.d1)[o] = (S)dG;
+                ((S *)p.d1)[o + p.nvp] = (S)dH;
+            }
+            f1[i * VB + vl] = dG;
+            f1[FR + i * VB + vl] = dH;
+            if (i == (UPPER ? ni - 1 : 0)) { wI[j * VB + vl] = dG; wI[FR + j * VB + vl] = dH; }
+            if (j == (UPPER ? nj - 1 : 0)) { wJ[i * VB + vl] = dG; wJ[FR + i * VB + vl] = dH; }
         }
+        if (more) pf.store(st1, (p.hp_off[sn + 1] - p.hp_off[sn]) * STG);
         lds_barrier();
         T *t = f0; f0 = f1; f1 = t;
+        t = st0; st0 = st1; st1 = t;
     }
 }
 
@@ -822,7 +928,11 @@ __global__ __launch_bounds__(256) void k_wall_ghost(Params p) {
         if (un > 0.0) a[0] += p.w[v] * un * (double)d[v];
     }
     wave_sum<1>(a);
-    if (lane == 0) p.drho[k] = -a[0] / p.wden[k];
+    if (lane == 0) {
+        const double d = -a[0] / p.wden[k];
+        p.drho[k] = d;
+        p.sdrho[(size_t)p.hp_pos[F.L] * 4 + F.sL] = d;
+    }
 }
 
 // explicit DUGKS update (Eq. 21)
@@ -977,8 +1087,9 @@ hipError_t launch_macro(const Params &p, hipStream_t st) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int L = p.ni < p.nj ? p.ni : p.nj;
-    const int threads = round64(L) < 1024 ? round64(L) : 1024;
-    const size_t lds = (size_t)(12 * p.ni + 4 * p.nj) * sizeof(double);
+    (void)L;
+    const int threads = macro_threads(p.ni, p.nj);
+    const size_t lds = macro_lds_bytes(p.ni, p.nj);
     if (lds > 64 * 1024) {
         e = hipFuncSetAttribute((const void *)k_macro_sweep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -987,15 +1098,34 @@ hipError_t launch_macro(const Params &p, hipStream_t st) {
     return hipGetLastError();
 }
 
+size_t macro_lds_bytes(int ni, int nj) {
+    const int L = ni < nj ? ni : nj;
+    return (size_t)(12 * ni + 4 * nj + 2 * L * MH_N) * sizeof(double);
+}
+
+int macro_threads(int ni, int nj) {
+    const int L = ni < nj ? ni : nj;
+    const int t = round64((L * MH_N + PF - 1) / PF);
+    return t < 64 ? 64 : t;
+}
+
+int sweep_threads(int ni, int nj, int vb) {
+    const int L = ni < nj ? ni : nj;
+    int t = round64(vb * L);
+    const int need = round64((L * STG + PF - 1) / PF);
+    t = t < need ? need : t;
+    return t < 512 ? t : 512;
+}
+
 size_t sweep_lds_bytes(int ni, int nj, int vb, size_t s_bytes) {
-    return (size_t)(3 * ni + nj) * vb * s_bytes;
+    const int L = ni < nj ? ni : nj;
+    return ((size_t)2 * (3 * ni + nj) * vb + (size_t)2 * L * STG) * s_bytes;
 }
 
 template <int VB>
 static hipError_t launch_sweeps_vb(const Params &p, bool fp32, bool upper, hipStream_t st) {
-    const dim3 g((p.nv + VB - 1) / VB, 2);
-    const int L = p.ni < p.nj ? p.ni : p.nj;
-    const int threads = round64(VB * L) < 1024 ? round64(VB * L) : 1024;
+    const dim3 g((p.nv + VB - 1) / VB);
+    const int threads = sweep_threads(p.ni, p.nj, VB);
     DISPATCH_S(fp32, {
         const size_t lds = sweep_lds_bytes(p.ni, p.nj, VB, sizeof(S));
         const void *fn = !upper ? (p.model == 1 ? (const void *)k_sweep<S, true, VB, false> : (const void *)k_sweep<S, false, VB, false>)

@@ -17,6 +17,9 @@ hipError_t launch_flux(const Params &p, bool fp32, hipStream_t st);
 hipError_t launch_macro(const Params &p, hipStream_t st);
 hipError_t launch_sweep(const Params &p, bool fp32, bool upper, int vb, hipStream_t st);
 size_t sweep_lds_bytes(int ni, int nj, int vb, size_t s_bytes);
+size_t macro_lds_bytes(int ni, int nj);
+int macro_threads(int ni, int nj);
+int sweep_threads(int ni, int nj, int vb);
 hipError_t launch_wall_ghost(const Params &p, bool fp32, hipStream_t st);
 hipError_t launch_explicit(const Params &p, bool fp32, hipStream_t st);
 hipError_t launch_pack(const Params &p, bool fp32, const void *src, double *dst, int sp, int nsp,
