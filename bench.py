@@ -35,7 +35,32 @@ def parse():
     ap.add_argument("--no-ttr", action="store_true", help="skip the time-to-residual runs")
     ap.add_argument("--cpu-sample-iters", type=int, default=0,
                     help="oracle iterations of the CPU baseline (0 = sized to ~15 s)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times (the "
+                         "reference kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """Five copies of a MIB-MiB buffer: each reads and writes exactly MIB MiB."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms = []
+    for _ in range(5):
+        ev[0].record()
+        dst.copy_(src)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    assert torch.equal(dst, src)
+    best = min(ms)
+    print(json.dumps({"copy_MiB": mib, "bytes_read_per_copy": mib << 20,
+                      "bytes_written_per_copy": mib << 20, "ms": ms,
+                      "GB/s (read+write)": 2 * (mib << 20) / (best * 1e-3) / 1e9}))
 
 
 def cpu_baseline(cfg, nc, nv, budget_s=15.0, iters=0):
@@ -59,6 +84,9 @@ def cpu_baseline(cfg, nc, nv, budget_s=15.0, iters=0):
 
 def main():
     args = parse()
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU (--gpus 1); the "
                                    "velocity-sharded multi-GPU design is documented, not built"}))

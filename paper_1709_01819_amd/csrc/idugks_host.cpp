@@ -151,7 +151,7 @@ struct idugks_ctx {
     idugks_config cfg;
     Params p;
     bool fp32;
-    int vb;
+    SweepShape sweep;
     hipStream_t st;
     std::vector<double> area_h, xi_h, eta_h, w_h;
     double *stage;  // [nc][nvp] FP64 staging of one canonical species
@@ -172,8 +172,8 @@ idugks_status validate(const idugks_config *c) {
     if (!c) return fail(IDUGKS_E_INVALID, "null config");
     if (c->struct_size != sizeof(idugks_config)) return fail(IDUGKS_E_INVALID, "struct_size mismatch");
     if (c->ni < 1 || c->nj < 1) return fail(IDUGKS_E_INVALID, "mesh needs ni, nj >= 1");
-    if (std::min(c->ni, c->nj) > 280 || macro_lds_bytes(c->ni, c->nj) > 150 * 1024 ||
-        sweep_lds_bytes(c->ni, c->nj, 8, 8) > 150 * 1024)
+    if (std::min(c->ni, c->nj) > 280 || macro_shape(c->ni, c->nj).lds > 150 * 1024 ||
+        macro_shape(c->ni, c->nj).threads > 768 || sweep_shape(c->ni, c->nj, 1, 8).vb == 0)
         return fail(IDUGKS_E_INVALID, "mesh too large for the LDS-resident sweep fronts");
     if (!c->xn || !c->yn) return fail(IDUGKS_E_INVALID, "missing node coordinates");
     if (c->nvx < 2 || c->nvy < 2) return fail(IDUGKS_E_INVALID, "need nv >= 2 per direction");
@@ -552,6 +552,9 @@ enum Region {
 Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy, int nwall) {
     Layout L;
     const size_t S = c->precision == IDUGKS_FP32_MIXED ? 4 : 8, TW = (size_t)nvx + nvy;
+    // rows of the hyperplane-ordered sweep arrays: the staging waves read whole passes past
+    // the last cell of a hyperplane, so these arrays carry min(ni, nj) + 32 spare rows
+    const size_t ncs = (size_t)nc + std::min(c->ni, c->nj) + 32;
     const size_t sizes[R_COUNT] = {
         sizeof(CellSide) * 4 * (size_t)nc, sizeof(Face) * (size_t)nf, sizeof(int) * (size_t)std::max(nwall, 1),
         8 * (size_t)nc, 8 * (size_t)nvp, 8 * (size_t)nvp, 8 * (size_t)nvp, 8 * (size_t)nvx, 8 * (size_t)nvx,
@@ -562,7 +565,7 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
         8 * (size_t)nc * 4 * NM_MAX, 8 * (size_t)nc * NM_MAX, 8 * 4 * (size_t)nc, 8 * 4 * (size_t)nc,
         8 * 4 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nf, 8 * SC_NUM,
         8 * (size_t)std::max(nc, 2) * nvp, sizeof(int) * (size_t)(nc + 2), sizeof(int) * (size_t)nc,
-        8 * (size_t)SG_N * nc, 8 * (size_t)SR_N * nc, 8 * 4 * (size_t)nc, 8 * (size_t)MH_N * nc,
+        8 * (size_t)SG_N * ncs, 8 * (size_t)SR_N * ncs, 8 * 4 * (size_t)ncs, 8 * (size_t)MH_N * ncs,
         S * 6 * (size_t)nc * nvp};
     for (int r = 0; r < R_COUNT; ++r) L.add(sizes[r]);
     L.bytes = (L.bytes + 255) & ~size_t(255);
@@ -622,9 +625,9 @@ idugks_status one_step(idugks_ctx *x, int mode) {
     if (mode == IDUGKS_IMPLICIT) {
         RUN(KID_MACRO, launch_macro(p, x->st));
         RUN(KID_RECORDS_PRED, launch_records(p, x->fp32, 1, x->st));
-        RUN(KID_LOWER, launch_sweep(p, x->fp32, false, x->vb, x->st));
+        RUN(KID_LOWER, launch_sweep(p, x->fp32, false, x->sweep, x->st));
         RUN(KID_WALL_GHOST, launch_wall_ghost(p, x->fp32, x->st));
-        RUN(KID_UPPER, launch_sweep(p, x->fp32, true, x->vb, x->st));
+        RUN(KID_UPPER, launch_sweep(p, x->fp32, true, x->sweep, x->st));
     } else {
         RUN(KID_EXPLICIT, launch_explicit(p, x->fp32, x->st));
     }
@@ -635,14 +638,6 @@ idugks_status read_scalars(idugks_ctx *x, double *sc) {
     HIPCHK(hipMemcpyAsync(sc, x->p.scal, sizeof(double) * SC_NUM, hipMemcpyDeviceToHost, x->st));
     HIPCHK(hipStreamSynchronize(x->st));
     return IDUGKS_OK;
-}
-
-// Velocities per sweep block: enough slices to occupy the chip, at least 8 velocities per
-// slice, and the two LDS fronts (2 x ni x vb values) within 128 KiB.
-int choose_vb(int nv, int ni, int nj, size_t s_bytes) {
-    int vb = nv >= 64 * 256 ? 64 : nv >= 32 * 256 ? 32 : nv >= 16 * 128 ? 16 : 8;
-    while (vb > 8 && sweep_lds_bytes(ni, nj, vb, s_bytes) > 150 * 1024) vb /= 2;
-    return vb;
 }
 
 }  // namespace
@@ -716,7 +711,11 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     x->cfg.xn = x->cfg.yn = nullptr;
     x->fp32 = cfg->precision == IDUGKS_FP32_MIXED;
     x->st = (hipStream_t)hip_stream;
-    x->vb = choose_vb(b.nv, b.ni, b.nj, x->fp32 ? 4 : 8);
+    x->sweep = sweep_shape(b.ni, b.nj, b.nv, x->fp32 ? 4 : 8);
+    if (x->sweep.vb == 0) {
+        delete x;
+        return fail(IDUGKS_E_INVALID, "no sweep launch shape fits this mesh");
+    }
     x->iters = 0;
     x->prof = false;
     x->ev_used = 0;

@@ -585,38 +585,41 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
 // predicted macroscopic step: LU-SGS of Eq. 29-31 (Rusanov split, matrix-free flux
 // differences, mirrored wall ghost) over i+j hyperplanes in one block
 // ---------------------------------------------------------------------------------------
-DEV void euler_flux(const double W[4], double nx, double ny, int K, double F[4]) {
-    const double rho = W[0], U = W[1] / rho, V = W[2] / rho;
-    const double pr = (2.0 * W[3] - rho * (U * U + V * V)) / (K + 2);
+// 1/x within about an ulp: the hardware estimate refined by two Newton steps (a shorter
+// dependency chain than a correctly rounded division; x is a positive density here)
+DEV double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Euler flux through a face of unit normal n of the state W = (rho, rho U, rho V, rho E);
+// ik2 = 1/(K+2), so that p = (2 rho E - rho |U|^2)/(K+2)
+DEV void euler_flux_n(const double W[4], double nx, double ny, double ik2, double F[4]) {
+    const double ir = rcp_nr(W[0]);
+    const double U = W[1] * ir, V = W[2] * ir;
+    const double pr = (2.0 * W[3] - W[0] * (U * U + V * V)) * ik2;
     const double un = U * nx + V * ny;
-    F[0] = rho * un;
+    F[0] = W[0] * un;
     F[1] = W[1] * un + pr * nx;
     F[2] = W[2] * un + pr * ny;
     F[3] = (W[3] + pr) * un;
 }
 
-// All data exchanged inside the sweep kernels goes through LDS, so their barrier orders
-// LDS only: global loads issued for the next hyperplane stay in flight across it.
-DEV void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-DEV void hp_bounds(int s, int ni, int nj, int &lo, int &hi) {
-    lo = s - nj + 1 > 0 ? s - nj + 1 : 0;
-    hi = s < ni - 1 ? s : ni - 1;
-}
-
 // Everything of Eq. 30-31 that does not depend on the increments, all cells in parallel:
-// implicit time step, diagonal (a wall face carries its whole lambda S: mirrored ghost),
-// and per cell side with a neighbour j the neighbour's lambda_j and F_n(W_j).
+// implicit time step, inverse diagonal (a wall face carries its whole lambda S: mirrored
+// ghost), and per cell side with a neighbour j the neighbour's lambda_j and F_n(W_j).
+// Rows are stored in i+j hyperplane order: M_W, 1/D, codes, per side nx, ny, S, lambda_j,
+// F_n(W_j), W_j.
 __global__ __launch_bounds__(256) void k_macro_prep(Params p) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= p.nc) return;
     const CellSide *cs = p.cs + 4 * c;
     double *m = p.mh + (size_t)p.hp_pos[c] * MH_N;
     const double U = p.rec[c].U, V = p.rec[c].V, C = sqrt(p.gam * p.rec[c].RT);
+    const double ik2 = 1.0 / (p.K + 2);
     double ls = 0.0, lw = 0.0;
     for (int s = 0; s < 4; ++s) {
         m[5 + s] = p.sgeo[(size_t)p.hp_pos[c] * SG_N + 12 + s];  // code
@@ -631,7 +634,7 @@ __global__ __launch_bounds__(256) void k_macro_prep(Params p) {
         const double *Wj = p.Wc + (size_t)j * 4;
         ms[3] = fabs((Wj[1] * cs[s].nx + Wj[2] * cs[s].ny) / Wj[0]) + sqrt(p.gam * p.rec[j].RT);
         double F0[4];
-        euler_flux(Wj, cs[s].nx, cs[s].ny, p.K, F0);
+        euler_flux_n(Wj, cs[s].nx, cs[s].ny, ik2, F0);
         for (int a = 0; a < 4; ++a) {
             ms[4 + a] = F0[a];
             ms[8 + a] = Wj[a];
@@ -640,225 +643,287 @@ __global__ __launch_bounds__(256) void k_macro_prep(Params p) {
     const double dti = p.cfl_imp * p.area[c] / ls;
     p.dtimp[c] = dti;
     for (int a = 0; a < 4; ++a) m[a] = p.MW[(size_t)c * 4 + a];
-    m[4] = p.area[c] / dti + 0.5 * ls + 0.5 * lw;
+    m[4] = 1.0 / (p.area[c] / dti + 0.5 * ls + 0.5 * lw);
 }
 
-// Cooperative staging of per-cell sweep data: every lane of the block loads a few of the
-// values of the next hyperplane's cells (one step ahead, into registers), then stores
-// them into an LDS buffer after the current hyperplane is done.
-constexpr int PF = 16;
+// All data exchanged inside the sweep kernels goes through LDS, so their barrier orders
+// LDS only: global loads issued for later hyperplanes stay in flight across it.
+DEV void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+DEV void hp_bounds(int s, int ni, int nj, int &lo, int &hi) {
+    lo = s - nj + 1 > 0 ? s - nj + 1 : 0;
+    hi = s < ni - 1 ? s : ni - 1;
+}
+
+// Both sweep kernels split their block into compute waves and staging waves.  The
+// staging waves copy the per-cell rows of hyperplane t+1 (contiguous in hyperplane order)
+// from HBM into one of two LDS buffers during step t, having issued the loads during step
+// t-1; the compute waves read only LDS for per-cell data.  A wave's loads complete in
+// order, so keeping these copies out of the compute waves lets the compute waves' own
+// prefetches run ahead without waiting for them.
+constexpr int SPW = 16;  // staged values per staging lane and hyperplane (macro sweep)
 
 template <class T>
-struct Stager {
-    T v[PF];
-    DEV void load(const double *src, int n) {
+DEV void stage_store(const T (&reg)[SPW], T *dst, int n, int sl, int nsl) {
 #pragma unroll
-        for (int q = 0; q < PF; ++q) {
-            const int e = threadIdx.x + q * blockDim.x;
-            v[q] = e < n ? (T)src[e] : T(0);
-        }
+    for (int q = 0; q < SPW; ++q) {
+        const int e = sl + q * nsl;
+        if (e < n) dst[e] = reg[q];
     }
-    DEV void store(T *dst, int n) const {
-#pragma unroll
-        for (int q = 0; q < PF; ++q) {
-            const int e = threadIdx.x + q * blockDim.x;
-            if (e < n) dst[e] = v[q];
-        }
-    }
-};
+}
 
-// Macro LU-SGS sweeps over i+j hyperplanes in one block, one lane per cell of a
-// hyperplane: r -= 1/2 S (F_n(W_j + dW_j) - F_n(W_j) - lambda_j dW_j) over the lower
-// (forward) or upper (backward) neighbours.  LDS holds the previous hyperplane's
-// increments (fronts), those of the cells next to a periodic seam (wI: column i = 0 /
-// ni-1, wJ: row j = 0 / nj-1; the only non-adjacent neighbours) and the staged per-cell
-// data of the current and the next hyperplane.
-__global__ __launch_bounds__(1024) void k_macro_sweep(Params p) {
+// Macro LU-SGS sweeps (Eq. 29-31) over i+j hyperplanes in one block.  Waves below nct
+// compute, one lane per cell of a hyperplane:
+//   r -= 1/2 S (F_n(W_j + dW_j) - F_n(W_j) - lambda_j dW_j)
+// over the lower (forward) or upper (backward) neighbours.  LDS holds the previous
+// hyperplane's increments (fronts), those of the cells next to a periodic seam (wI:
+// column i = 0 / ni-1, wJ: row j = 0 / nj-1, the only non-adjacent neighbours) and the
+// staged rows of the current and the next hyperplane.  The forward sweep writes dW* into
+// the first four values of each cell's row, which the backward sweep stages back.
+__global__ __launch_bounds__(768) void k_macro_sweep(Params p, int nct) {
     extern __shared__ double lds[];
     const int ni = p.ni, nj = p.nj, nh = ni + nj - 1, L = ni < nj ? ni : nj;
-    double *f0 = lds, *f1 = lds + 4 * ni, *wI = lds + 8 * ni, *wJ = wI + 4 * nj;
+    double *fr0 = lds, *fr1 = lds + 4 * ni, *wI = lds + 8 * ni, *wJ = wI + 4 * nj;
     double *st0 = wJ + 4 * ni, *st1 = st0 + (size_t)L * MH_N;
-    Stager<double> pf;
+    int *hpo = (int *)(st1 + (size_t)L * MH_N);
+    for (int h = threadIdx.x; h <= nh; h += blockDim.x) hpo[h] = p.hp_off[h];
+    __syncthreads();
+    const double ik2 = 1.0 / (p.K + 2);
+    // Both roles run the same number of barriers: one after the prologue and one per
+    // hyperplane in each direction, plus the block-wide one between the directions.
+    if ((int)threadIdx.x >= nct) {
+        const int sl = (int)threadIdx.x - nct, nsl = (int)blockDim.x - nct;
+        double reg[SPW];
+        // rows past the hyperplane are read (spare rows at the end of mh) but never staged
+        auto issue = [&](int h) {
+            const double *src = p.mh + (size_t)hpo[h] * MH_N + sl;
+#pragma unroll
+            for (int q = 0; q < SPW; ++q) reg[q] = src[q * nsl];
+        };
+        for (int dir = 0; dir < 2; ++dir) {
+            const bool upper = dir == 1;
+            auto hp = [&](int t) { return upper ? nh - 1 - t : t; };
+            issue(hp(0));
+            stage_store(reg, st0, (hpo[hp(0) + 1] - hpo[hp(0)]) * MH_N, sl, nsl);
+            if (nh > 1) issue(hp(1));
+            lds_barrier();
+            for (int t = 0; t < nh; ++t) {
+                if (t + 1 < nh) {
+                    const int h = hp(t + 1);
+                    stage_store(reg, (t + 1) & 1 ? st1 : st0, (hpo[h + 1] - hpo[h]) * MH_N, sl, nsl);
+                }
+                if (t + 2 < nh) issue(hp(t + 2));
+                lds_barrier();
+            }
+            __syncthreads();
+        }
+        return;
+    }
     for (int dir = 0; dir < 2; ++dir) {
         const bool upper = dir == 1;
         const int need = upper ? SG_UPPER : SG_LOWER;
-        int s = upper ? nh - 1 : 0;
-        pf.load(p.mh + (size_t)p.hp_off[s] * MH_N, (p.hp_off[s + 1] - p.hp_off[s]) * MH_N);
-        pf.store(st0, (p.hp_off[s + 1] - p.hp_off[s]) * MH_N);
         lds_barrier();
-        for (int step = 0; step < nh; ++step, s += upper ? -1 : 1) {
-            const int sn = upper ? s - 1 : s + 1;
-            const bool more = step + 1 < nh;
-            const int nn = more ? (p.hp_off[sn + 1] - p.hp_off[sn]) * MH_N : 0;
-            if (more) pf.load(p.mh + (size_t)p.hp_off[sn] * MH_N, nn);
+        for (int t = 0; t < nh; ++t) {
+            const int s = upper ? nh - 1 - t : t;
             int lo, hi;
             hp_bounds(s, ni, nj, lo, hi);
             const int k = threadIdx.x, i = lo + k;
             if (i <= hi) {
                 const int j = s - i, c = i + j * ni;
-                const double *m = st0 + (size_t)k * MH_N;
-                double r[4];
-                for (int a = 0; a < 4; ++a) r[a] = upper ? 0.0 : m[a];
+                const double *m = (t & 1 ? st1 : st0) + (size_t)k * MH_N;
+                double r[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int sd = 0; sd < 4; ++sd) {
                     const int code = (int)m[5 + sd];
                     if (!(code & need)) continue;
                     const double *ms = m + 9 + 12 * sd;
                     const int fi = upper ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
-                    const double *src = (code & SG_ADJ) ? f0 + 4 * fi : (sd < 2 ? wI + 4 * j : wJ + 4 * i);
+                    const double *src = (code & SG_ADJ) ? fr0 + 4 * fi : (sd < 2 ? wI + 4 * j : wJ + 4 * i);
                     double Wn[4], F1[4];
                     for (int a = 0; a < 4; ++a) Wn[a] = ms[8 + a] + src[a];
-                    euler_flux(Wn, ms[0], ms[1], p.K, F1);
-                    const double h = (upper ? 0.5 : -0.5) * ms[2];
-                    for (int a = 0; a < 4; ++a) r[a] += h * (F1[a] - ms[4 + a] - ms[3] * src[a]);
+                    euler_flux_n(Wn, ms[0], ms[1], ik2, F1);
+                    const double hS = 0.5 * ms[2];
+                    for (int a = 0; a < 4; ++a) r[a] += hS * (F1[a] - ms[4 + a] - ms[3] * src[a]);
                 }
+                const double iD = m[4];
+                double *row = p.mh + (size_t)(hpo[s] + k) * MH_N;
                 for (int a = 0; a < 4; ++a) {
-                    // backward sweep: this lane wrote dW of this cell in the forward sweep
-                    const double d = upper ? p.dW[(size_t)c * 4 + a] - r[a] / m[4] : r[a] / m[4];
-                    p.dW[(size_t)c * 4 + a] = d;
-                    f1[4 * i + a] = d;
+                    // forward: dW* = (M_W - r)/D; backward: dW = dW* - r/D
+                    const double d = upper ? m[a] - r[a] * iD : (m[a] - r[a]) * iD;
+                    if (upper) p.dW[(size_t)c * 4 + a] = d;
+                    else row[a] = d;
+                    fr1[4 * i + a] = d;
                     if (i == (upper ? ni - 1 : 0)) wI[4 * j + a] = d;
                     if (j == (upper ? nj - 1 : 0)) wJ[4 * i + a] = d;
                 }
             }
-            if (more) pf.store(st1, nn);
             lds_barrier();
-            double *t = f0; f0 = f1; f1 = t;
-            t = st0; st0 = st1; st1 = t;
+            double *tp = fr0; fr0 = fr1; fr1 = tp;
         }
+        // the forward sweep's row writes must be visible to the backward staging loads
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------------------
-// micro LU-SGS sweeps (Eq. 24-26) over i+j hyperplanes.  One block per (velocity slice,
-// species); lanes = VB velocities x (blockDim/VB) cells of a hyperplane.  LDS holds the
-// increments of the previous hyperplane and of the cells next to a periodic seam, and the
-// staged per-cell data (equilibrium record, diagonal, geometry) of the current and next
-// hyperplane; each lane also loads the HBM values of its next (cell, v) item before
-// computing the current one.
+// micro LU-SGS sweeps (Eq. 24-26) over i+j hyperplanes.  One block per slice of vb
+// velocities (slices of one XCD are contiguous, so neighbouring slices share cache lines
+// in its L2); compute lane = (cell of the hyperplane, velocity of the slice), handling
+// both species (they share the diagonal and the couplings).  LDS holds the increments of
+// the previous hyperplane and of the cells next to a periodic seam, and the staged
+// per-cell data (record, diagonal, geometry) of the current and next hyperplane.  Each
+// compute lane keeps the HBM loads of its next RING items (one per hyperplane) in flight
+// in fixed registers.
 // ---------------------------------------------------------------------------------------
 constexpr int STG = 28;  // staged values per cell: record (12), nx ny S (12), codes (4)
+constexpr int RING = 4;
 
-template <class T>
+template <class S>
 struct SweepItem {
-    bool ok;
-    int i;
-    T aG, aH, bG, bH, e;  // forward: M, phi~ (G, H), factored Maxwellian; backward: increment, phi~
+    int i;                        // cell column, -1 if the lane has no cell at this step
+    S aG, aH, bG, bH, e1, e2;     // forward: M, phi~ (G, H), factored Maxwellian;
+                                  // backward: increment, phi~
 };
 
-// the item of (hyperplane s, pass) for this lane; cells of a hyperplane by increasing i
+// the item of hyperplane h for this lane; every lane issues the same loads (lanes without
+// a cell read cell 0, velocity 0)
 template <class S, bool UPPER>
-DEV SweepItem<S> sweep_load(const Params &p, int s, int pass, int slot, int cpp, int v, bool vok,
-                            int ix, int iy) {
-    SweepItem<S> it;
-    it.ok = false;
-    it.i = 0;
-    it.aG = it.aH = it.bG = it.bH = it.e = S(0);
-    if (s < 0 || s >= p.ni + p.nj - 1) return it;
-    int lo, hi;
-    hp_bounds(s, p.ni, p.nj, lo, hi);
-    const int i = lo + slot + pass * cpp;
-    if (!(vok && i <= hi)) return it;
-    it.ok = true;
+DEV void sweep_load(const Params &p, SweepItem<S> &it, int h, int nh, int slot, int v, bool vok,
+                    int ix, int iy) {
+    int c = 0, i = -1;
+    if (vok && h >= 0 && h < nh) {
+        int lo, hi;
+        hp_bounds(h, p.ni, p.nj, lo, hi);
+        if (lo + slot <= hi) {
+            i = lo + slot;
+            c = i + (h - i) * p.ni;
+        }
+    }
     it.i = i;
-    const int c = i + (s - i) * p.ni;
-    const size_t o = (size_t)c * 2 * p.nvp + v;
+    const size_t o = (size_t)c * 2 * p.nvp + (i >= 0 ? v : 0);
     it.aG = ((const S *)p.d1)[o];
     it.aH = ((const S *)p.d1)[o + p.nvp];
     it.bG = ((const S *)p.f)[o];
     it.bH = ((const S *)p.f)[o + p.nvp];
     if (!UPPER) {
         const S *tb = (const S *)p.tabs + (size_t)c * (p.nvx + p.nvy);
-        it.e = tb[ix] * tb[p.nvx + iy];
+        it.e1 = tb[i >= 0 ? ix : 0];
+        it.e2 = tb[p.nvx + (i >= 0 ? iy : 0)];
     }
-    return it;
 }
 
-// staged values of hyperplane s: forward sweep record (12) + geometry (16); backward sweep
-// replaces the equilibrium part of the record by the wall ghost increments of the 4 sides
+// Staging of the micro sweeps: staging lane sl copies column r = sl % STG of the staged
+// rows of cells k = sl / STG + q * KP (KP = cells per pass, q < SPW_MICRO) of a
+// hyperplane.  Columns: forward sweep record (12) + geometry (16); the backward sweep
+// replaces the equilibrium part of the record by the wall ghost increments of the 4
+// sides.  Each lane reads one source column with a fixed stride: one load per value and
+// no divergence between the lanes of a wave.
+constexpr int SPW_MICRO = 8;
+
+template <bool UPPER>
+struct StageCol {
+    const double *base;  // nullptr: the column is constant 0 (or the lane is idle)
+    int stride, r, k0;
+    DEV StageCol(const Params &p, int sl, int nsl) {
+        const int kp = nsl / STG;
+        r = sl % STG;
+        k0 = sl / STG;
+        base = nullptr;
+        stride = 0;
+        if (k0 >= kp) return;  // idle lane
+        if (r >= SR_N) { base = p.sgeo + (r - SR_N); stride = SG_N; }
+        else if (!UPPER || r >= 10) { base = p.srec + r; stride = SR_N; }
+        else if (r < 4) { base = p.sdrho + r; stride = 4; }
+    }
+};
+
+// rows past the hyperplane's last cell are read but never staged (the arrays have spare
+// rows at their end)
 template <class T, bool UPPER>
-DEV void stage_load(const Params &p, Stager<T> &pf, int s) {
-    const int off = p.hp_off[s], n = (p.hp_off[s + 1] - off) * STG;
+DEV void sweep_issue(const StageCol<UPPER> &col, T (&reg)[SPW_MICRO], const int *hpo, int h, int kp) {
+    if (!col.base) return;
+    const double *src = col.base + (size_t)(hpo[h] + col.k0) * col.stride;
+    const size_t step = (size_t)kp * col.stride;
 #pragma unroll
-    for (int q = 0; q < PF; ++q) {
-        const int e = threadIdx.x + q * blockDim.x;
-        T val = T(0);
-        if (e < n) {
-            const int k = e / STG, r = e % STG;
-            if (r >= SR_N) val = (T)p.sgeo[(size_t)(off + k) * SG_N + (r - SR_N)];
-            else if (!UPPER || r >= 10) val = (T)p.srec[(size_t)(off + k) * SR_N + r];
-            else if (r < 4) val = (T)p.sdrho[(size_t)(off + k) * 4 + r];
-        }
-        pf.v[q] = val;
-    }
+    for (int q = 0; q < SPW_MICRO; ++q) reg[q] = (T)src[q * step];
 }
 
-constexpr int RING = 4;  // items in flight per lane
+template <class T, bool UPPER>
+DEV void sweep_stage(const StageCol<UPPER> &col, const T (&reg)[SPW_MICRO], T *dst, const int *hpo,
+                     int h, int kp, int nsl) {
+    const int cells = hpo[h + 1] - hpo[h];
+    if (col.k0 >= nsl / STG) return;
+    T *d = dst + col.k0 * STG + col.r;
+#pragma unroll
+    for (int q = 0; q < SPW_MICRO; ++q)
+        if (col.k0 + q * kp < cells) d[q * kp * STG] = col.base ? reg[q] : T(0);
+}
 
-// Micro LU-SGS sweeps (Eq. 24-26) over i+j hyperplanes.  One block per velocity slice;
-// lanes = VB velocities x (blockDim/VB) cells of a hyperplane, each lane handling both
-// species (they share the diagonal and the couplings).  LDS holds the increments of the
-// previous hyperplane and of the cells next to a periodic seam, and the staged per-cell
-// data (record, diagonal, geometry) of the current and next hyperplane.  Each lane keeps
-// the HBM loads of its next RING items in flight.
-template <class S, bool SHAK, int VB, bool UPPER>
-__global__ __launch_bounds__(512) void k_sweep(Params p) {
+template <class S, bool SHAK, bool UPPER>
+__global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
     using T = S;
     extern __shared__ unsigned char lds_raw[];
     const int ni = p.ni, nj = p.nj, nh = ni + nj - 1, L = ni < nj ? ni : nj;
-    const int FR = (3 * ni + nj) * VB;   // one species' fronts
-    T *f0 = (T *)lds_raw, *f1 = f0 + ni * VB, *wI = f1 + ni * VB, *wJ = wI + nj * VB;
+    const int FR = (3 * ni + nj) * vb;   // one species' fronts
+    T *f0 = (T *)lds_raw, *f1 = f0 + ni * vb, *wI = f1 + ni * vb, *wJ = wI + nj * vb;
     T *st0 = (T *)lds_raw + 2 * FR, *st1 = st0 + L * STG;
-    const int vl = threadIdx.x % VB, slot = threadIdx.x / VB, cpp = blockDim.x / VB;
-    const int v = blockIdx.x * VB + vl;
-    const bool vok = v < p.nv;
+    int *hpo = (int *)(st1 + L * STG);
+    for (int h = threadIdx.x; h <= nh; h += blockDim.x) hpo[h] = p.hp_off[h];
+    __syncthreads();
+    auto hp = [&](int t) { return UPPER ? nh - 1 - t : t; };
+    // Both roles run one barrier after the prologue and one per hyperplane.
+    if ((int)threadIdx.x >= nct) {
+        const int sl = (int)threadIdx.x - nct, nsl = (int)blockDim.x - nct, kp = nsl / STG;
+        const StageCol<UPPER> col(p, sl, nsl);
+        T reg[SPW_MICRO];
+        sweep_issue<T, UPPER>(col, reg, hpo, hp(0), kp);
+        sweep_stage<T, UPPER>(col, reg, st0, hpo, hp(0), kp, nsl);
+        if (nh > 1) sweep_issue<T, UPPER>(col, reg, hpo, hp(1), kp);
+        lds_barrier();
+        for (int t = 0; t < nh; ++t) {
+            if (t + 1 < nh) sweep_stage<T, UPPER>(col, reg, (t + 1) & 1 ? st1 : st0, hpo, hp(t + 1), kp, nsl);
+            if (t + 2 < nh) sweep_issue<T, UPPER>(col, reg, hpo, hp(t + 2), kp);
+            lds_barrier();
+        }
+        return;
+    }
+    const int vl = threadIdx.x % vb, slot = threadIdx.x / vb;
+    const int v = xcd_remap(blockIdx.x, gridDim.x) * vb + vl;
+    const bool vok = slot < L && v < p.nv;
     const int vv = vok ? v : 0;
     const T x = (T)p.xi[vv], y = (T)p.eta[vv];
     const int ix = p.vix[vv], iy = p.viy[vv];
     const T sc = (T)p.scal[SC_SCALE];
     const int need = UPPER ? SG_UPPER : SG_LOWER;
-    const int dirn = UPPER ? -1 : 1;
-    int s = UPPER ? nh - 1 : 0;
-    Stager<T> pf;
-    stage_load<T, UPPER>(p, pf, s);
-    pf.store(st0, (p.hp_off[s + 1] - p.hp_off[s]) * STG);
-    // prefetch ring: items (ls, lp) ahead of the current one
-    SweepItem<T> ring[RING];
-    int ls = s, lp = 0;
-    auto npass_of = [&](int h) {
-        int lo, hi;
-        hp_bounds(h, ni, nj, lo, hi);
-        return (hi - lo) / cpp + 1;
-    };
+    T gwv[4] = {T(0), T(0), T(0), T(0)}, kw[4] = {T(0), T(0), T(0), T(0)};
+    if (UPPER) {
 #pragma unroll
-    for (int q = 0; q < RING; ++q) {
-        ring[q] = sweep_load<S, UPPER>(p, ls, lp, slot, cpp, v, vok, ix, iy);
-        if (ls >= 0 && ls < nh && ++lp == npass_of(ls)) { lp = 0; ls += dirn; }
+        for (int ws = 0; ws < 4; ++ws) {
+            gwv[ws] = (T)p.gw[(size_t)ws * p.nvp + vv];
+            kw[ws] = (T)p.wKRT[ws];
+        }
     }
-    lds_barrier();
-    for (int step = 0; step < nh; ++step, s += dirn) {
-        const int sn = s + dirn;
-        const bool more = step + 1 < nh;
-        if (more) stage_load<T, UPPER>(p, pf, sn);
-        int lo, hi;
-        hp_bounds(s, ni, nj, lo, hi);
-        const int npass = (hi - lo) / cpp + 1;
-        for (int pass = 0; pass < npass; ++pass) {
-            const SweepItem<T> cur = ring[0];
+    SweepItem<S> ring[RING];
 #pragma unroll
-            for (int q = 0; q + 1 < RING; ++q) ring[q] = ring[q + 1];
-            ring[RING - 1] = sweep_load<S, UPPER>(p, ls, lp, slot, cpp, v, vok, ix, iy);
-            if (ls >= 0 && ls < nh && ++lp == npass_of(ls)) { lp = 0; ls += dirn; }
-            if (!cur.ok) continue;
-            const int i = cur.i, j = s - i;
-            const T *m = st0 + (i - lo) * STG;
+    for (int d = 0; d < RING; ++d) sweep_load<S, UPPER>(p, ring[d], hp(d), nh, slot, v, vok, ix, iy);
+    lds_barrier();
+    // One step: the hyperplane t with ring slot d.  Full groups of RING steps are unrolled
+    // without guards, so that the waits for a slot's loads are exact; the tail is guarded.
+    auto step = [&](const int t, SweepItem<S> &cur) {
+        if (cur.i >= 0) {
+            const int s = hp(t), i = cur.i, j = s - i;
+            const T *m = ((t & 1) ? st1 : st0) + slot * STG;
             T D = m[11], sG, sH;
             if (!UPPER) {
                 RecT<T> r;
                 r.U = m[0]; r.V = m[1]; r.c0 = m[2]; r.c1 = m[3]; r.c2c = m[4]; r.c3 = m[5];
                 r.kqx = m[6]; r.kqy = m[7]; r.iRT = m[8]; r.KRT = m[9];
                 T eG, eH;
-                eq_eval<T, SHAK>(r, x, y, cur.e, eG, eH);
+                eq_eval<T, SHAK>(r, x, y, cur.e1 * cur.e2, eG, eH);
                 sG = cur.aG - m[10] * (sc * cur.bG - eG);
                 sH = cur.aH - m[10] * (sc * cur.bH - eH);
             } else {
@@ -874,19 +939,21 @@ __global__ __launch_bounds__(512) void k_sweep(Params p) {
                 } else if (un < T(0)) {
                     if (code & need) {
                         const int fi = UPPER ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
-                        const int li = (code & SG_ADJ) ? fi * VB + vl
-                                                       : (sd < 2 ? (2 * ni + j) * VB + vl : (2 * ni + nj + i) * VB + vl);
+                        // fronts of this step: f0 (adjacent hyperplane) or wI / wJ
+                        const T *fp = (code & SG_ADJ) ? f0 + fi * vb
+                                                      : (sd < 2 ? wI + j * vb : wJ + i * vb);
                         const T cf = -un * Sk;
-                        // li indexes the front arrays of this step: f0 (adjacent) or wI / wJ
-                        const T dG = (code & SG_ADJ) ? f0[li] : ((T *)lds_raw)[li];
-                        const T dH = (code & SG_ADJ) ? f0[FR + li] : ((T *)lds_raw)[FR + li];
-                        sG += cf * dG;
-                        sH += cf * dH;
+                        sG += cf * fp[vl];
+                        sH += cf * fp[FR + vl];
                     } else if (UPPER && (code & SG_WALL)) {
                         const int ws = (code >> 8) & 3;
-                        const T gw = (T)p.gw[(size_t)ws * p.nvp + v] * m[sd] * (-un * Sk);
+                        T g = T(0), kk = T(0);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (q == ws) { g = gwv[q]; kk = kw[q]; }
+                        const T gw = g * m[sd] * (-un * Sk);
                         sG += gw;
-                        sH += gw * (T)p.wKRT[ws];
+                        sH += gw * kk;
                     }
                 }
             }
@@ -901,15 +968,31 @@ __global__ __launch_bounds__(512) void k_sweep(Params p) {
                 ((S *)p.d1)[o] = (S)dG;
                 ((S *)p.d1)[o + p.nvp] = (S)dH;
             }
-            f1[i * VB + vl] = dG;
-            f1[FR + i * VB + vl] = dH;
-            if (i == (UPPER ? ni - 1 : 0)) { wI[j * VB + vl] = dG; wI[FR + j * VB + vl] = dH; }
-            if (j == (UPPER ? nj - 1 : 0)) { wJ[i * VB + vl] = dG; wJ[FR + i * VB + vl] = dH; }
+            f1[i * vb + vl] = dG;
+            f1[FR + i * vb + vl] = dH;
+            if (i == (UPPER ? ni - 1 : 0)) { wI[j * vb + vl] = dG; wI[FR + j * vb + vl] = dH; }
+            if (j == (UPPER ? nj - 1 : 0)) { wJ[i * vb + vl] = dG; wJ[FR + i * vb + vl] = dH; }
         }
-        if (more) pf.store(st1, (p.hp_off[sn + 1] - p.hp_off[sn]) * STG);
-        lds_barrier();
-        T *t = f0; f0 = f1; f1 = t;
-        t = st0; st0 = st1; st1 = t;
+        // the slot's loads were issued RING steps ago; it is refilled only after use, so
+        // the new loads land in the same registers (no copies that would wait on them)
+        sweep_load<S, UPPER>(p, cur, hp(t + RING), nh, slot, v, vok, ix, iy);
+    };
+    int t0 = 0;
+    for (; t0 + RING <= nh; t0 += RING) {
+#pragma unroll
+        for (int d = 0; d < RING; ++d) {
+            step(t0 + d, ring[d]);
+            lds_barrier();
+            T *tp = f0; f0 = f1; f1 = tp;
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < RING - 1; ++d) {
+        if (t0 + d < nh) {
+            step(t0 + d, ring[d]);
+            lds_barrier();
+            T *tp = f0; f0 = f1; f1 = tp;
+        }
     }
 }
 
@@ -1082,76 +1165,69 @@ hipError_t launch_flux(const Params &p, bool fp32, hipStream_t st) {
 
 static int round64(int n) { return (n + 63) / 64 * 64; }
 
+MacroShape macro_shape(int ni, int nj) {
+    const int L = ni < nj ? ni : nj, nh = ni + nj - 1;
+    MacroShape m;
+    m.nct = round64(L);
+    const int nsw = (L * MH_N + 64 * SPW - 1) / (64 * SPW);
+    m.threads = m.nct + 64 * nsw;
+    m.lds = (size_t)(12 * ni + 4 * nj + 2 * L * MH_N) * sizeof(double) + (size_t)(nh + 1) * sizeof(int);
+    return m;
+}
+
 hipError_t launch_macro(const Params &p, hipStream_t st) {
     hipLaunchKernelGGL(k_macro_prep, dim3((p.nc + 255) / 256), dim3(256), 0, st, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int L = p.ni < p.nj ? p.ni : p.nj;
-    (void)L;
-    const int threads = macro_threads(p.ni, p.nj);
-    const size_t lds = macro_lds_bytes(p.ni, p.nj);
-    if (lds > 64 * 1024) {
-        e = hipFuncSetAttribute((const void *)k_macro_sweep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const MacroShape m = macro_shape(p.ni, p.nj);
+    if (m.lds > 64 * 1024) {
+        e = hipFuncSetAttribute((const void *)k_macro_sweep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)m.lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_macro_sweep, dim3(1), dim3(threads), lds, st, p);
+    hipLaunchKernelGGL(k_macro_sweep, dim3(1), dim3(m.threads), m.lds, st, p, m.nct);
     return hipGetLastError();
 }
 
-size_t macro_lds_bytes(int ni, int nj) {
-    const int L = ni < nj ? ni : nj;
-    return (size_t)(12 * ni + 4 * nj + 2 * L * MH_N) * sizeof(double);
+// Velocities per sweep block: the largest slice (at most 16) that fits one block of at
+// most 1024 lanes with the staging waves and 150 KiB of LDS and still gives at least 192
+// blocks; else the smallest slice that fits.
+SweepShape sweep_shape(int ni, int nj, int nv, size_t s_bytes) {
+    const int L = ni < nj ? ni : nj, nh = ni + nj - 1;
+    // staging waves: KP = 64 nsw / STG cells per pass, SPW_MICRO passes must cover L cells
+    int nsw = 1;
+    while ((64 * nsw / STG) * SPW_MICRO < L) ++nsw;
+    SweepShape best{0, 0, 0, 0};
+    for (int vb = 16; vb >= 1; vb /= 2) {
+        SweepShape c;
+        c.vb = vb;
+        c.nct = round64(vb * L);
+        c.threads = c.nct + 64 * nsw;
+        c.lds = ((size_t)2 * (3 * ni + nj) * vb + (size_t)2 * L * STG) * s_bytes + (size_t)(nh + 1) * sizeof(int);
+        if (c.threads > 1024 || c.lds > 150 * 1024) continue;
+        best = c;
+        if ((nv + vb - 1) / vb >= 192) break;
+    }
+    return best;
 }
 
-int macro_threads(int ni, int nj) {
-    const int L = ni < nj ? ni : nj;
-    const int t = round64((L * MH_N + PF - 1) / PF);
-    return t < 64 ? 64 : t;
-}
-
-int sweep_threads(int ni, int nj, int vb) {
-    const int L = ni < nj ? ni : nj;
-    int t = round64(vb * L);
-    const int need = round64((L * STG + PF - 1) / PF);
-    t = t < need ? need : t;
-    return t < 512 ? t : 512;
-}
-
-size_t sweep_lds_bytes(int ni, int nj, int vb, size_t s_bytes) {
-    const int L = ni < nj ? ni : nj;
-    return ((size_t)2 * (3 * ni + nj) * vb + (size_t)2 * L * STG) * s_bytes;
-}
-
-template <int VB>
-static hipError_t launch_sweeps_vb(const Params &p, bool fp32, bool upper, hipStream_t st) {
-    const dim3 g((p.nv + VB - 1) / VB);
-    const int threads = sweep_threads(p.ni, p.nj, VB);
+hipError_t launch_sweep(const Params &p, bool fp32, bool upper, const SweepShape &sh, hipStream_t st) {
+    const dim3 g((p.nv + sh.vb - 1) / sh.vb);
     DISPATCH_S(fp32, {
-        const size_t lds = sweep_lds_bytes(p.ni, p.nj, VB, sizeof(S));
-        const void *fn = !upper ? (p.model == 1 ? (const void *)k_sweep<S, true, VB, false> : (const void *)k_sweep<S, false, VB, false>)
-                                : (p.model == 1 ? (const void *)k_sweep<S, true, VB, true> : (const void *)k_sweep<S, false, VB, true>);
-        if (lds > 64 * 1024) {
-            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const void *fn = !upper ? (p.model == 1 ? (const void *)k_sweep<S, true, false> : (const void *)k_sweep<S, false, false>)
+                                : (p.model == 1 ? (const void *)k_sweep<S, true, true> : (const void *)k_sweep<S, false, true>);
+        if (sh.lds > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
             if (e != hipSuccess) return e;
         }
         if (!upper) {
-            if (p.model == 1) hipLaunchKernelGGL((k_sweep<S, true, VB, false>), g, dim3(threads), lds, st, p);
-            else hipLaunchKernelGGL((k_sweep<S, false, VB, false>), g, dim3(threads), lds, st, p);
+            if (p.model == 1) hipLaunchKernelGGL((k_sweep<S, true, false>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
+            else hipLaunchKernelGGL((k_sweep<S, false, false>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
         } else {
-            if (p.model == 1) hipLaunchKernelGGL((k_sweep<S, true, VB, true>), g, dim3(threads), lds, st, p);
-            else hipLaunchKernelGGL((k_sweep<S, false, VB, true>), g, dim3(threads), lds, st, p);
+            if (p.model == 1) hipLaunchKernelGGL((k_sweep<S, true, true>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
+            else hipLaunchKernelGGL((k_sweep<S, false, true>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
         }
     });
     return hipGetLastError();
-}
-
-hipError_t launch_sweep(const Params &p, bool fp32, bool upper, int vb, hipStream_t st) {
-    switch (vb) {
-    case 8: return launch_sweeps_vb<8>(p, fp32, upper, st);
-    case 16: return launch_sweeps_vb<16>(p, fp32, upper, st);
-    case 32: return launch_sweeps_vb<32>(p, fp32, upper, st);
-    default: return launch_sweeps_vb<64>(p, fp32, upper, st);
-    }
 }
 
 hipError_t launch_wall_ghost(const Params &p, bool fp32, hipStream_t st) {

@@ -14,12 +14,19 @@ hipError_t launch_records(const Params &p, bool fp32, int which, hipStream_t st)
 hipError_t launch_partials(const Params &p, bool fp32, hipStream_t st);
 hipError_t launch_face_records(const Params &p, bool fp32, hipStream_t st);
 hipError_t launch_flux(const Params &p, bool fp32, hipStream_t st);
+// Launch shapes of the hyperplane sweeps: block = nct compute lanes + staging waves.
+struct MacroShape {
+    int nct, threads;
+    size_t lds;
+};
+struct SweepShape {
+    int vb, nct, threads;  // vb = 0: no shape fits
+    size_t lds;
+};
+MacroShape macro_shape(int ni, int nj);
+SweepShape sweep_shape(int ni, int nj, int nv, size_t s_bytes);
 hipError_t launch_macro(const Params &p, hipStream_t st);
-hipError_t launch_sweep(const Params &p, bool fp32, bool upper, int vb, hipStream_t st);
-size_t sweep_lds_bytes(int ni, int nj, int vb, size_t s_bytes);
-size_t macro_lds_bytes(int ni, int nj);
-int macro_threads(int ni, int nj);
-int sweep_threads(int ni, int nj, int vb);
+hipError_t launch_sweep(const Params &p, bool fp32, bool upper, const SweepShape &sh, hipStream_t st);
 hipError_t launch_wall_ghost(const Params &p, bool fp32, hipStream_t st);
 hipError_t launch_explicit(const Params &p, bool fp32, hipStream_t st);
 hipError_t launch_pack(const Params &p, bool fp32, const void *src, double *dst, int sp, int nsp,
