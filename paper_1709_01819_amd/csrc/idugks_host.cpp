@@ -138,11 +138,11 @@ struct Layout {
 };
 
 enum KernelId {
-    KID_RECORDS, KID_PARTIALS, KID_FACE_RECORDS, KID_FLUX, KID_MACRO, KID_RECORDS_PRED,
+    KID_RECORDS, KID_PARTIALS, KID_FACE_RECORDS, KID_FLUX, KID_MACRO_PREP, KID_MACRO, KID_RECORDS_PRED,
     KID_LOWER, KID_WALL_GHOST, KID_UPPER, KID_EXPLICIT, KID_RAW, KID_FINALIZE, KID_COUNT
 };
 const char *kKernelNames[KID_COUNT] = {
-    "records", "face_partials", "face_records", "flux", "macro_lusgs", "records_pred",
+    "records", "face_partials", "face_records", "flux", "macro_prep", "macro_lusgs", "records_pred",
     "sweep_lower", "wall_ghost", "sweep_upper", "explicit_update", "raw_moments", "finalize"};
 
 }  // namespace
@@ -623,6 +623,7 @@ idugks_status one_step(idugks_ctx *x, int mode) {
     idugks_status s = flux_pipeline(x);
     if (s != IDUGKS_OK) return s;
     if (mode == IDUGKS_IMPLICIT) {
+        RUN(KID_MACRO_PREP, launch_macro_prep(p, x->st));
         RUN(KID_MACRO, launch_macro(p, x->st));
         RUN(KID_RECORDS_PRED, launch_records(p, x->fp32, 1, x->st));
         RUN(KID_LOWER, launch_sweep(p, x->fp32, false, x->sweep, x->st));
@@ -909,6 +910,7 @@ idugks_status idugks_predict(idugks_ctx *x, double *Wstar, double *dt_imp, int32
     if (!x) return fail(IDUGKS_E_INVALID, "null context");
     idugks_status s = flux_pipeline(x);
     if (s != IDUGKS_OK) return s;
+    RUN(KID_MACRO_PREP, launch_macro_prep(x->p, x->st));
     RUN(KID_MACRO, launch_macro(x->p, x->st));
     const int nc = x->p.nc;
     std::vector<double> W(4 * nc), dW(4 * nc);

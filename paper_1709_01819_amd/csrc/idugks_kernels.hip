@@ -661,11 +661,13 @@ DEV void hp_bounds(int s, int ni, int nj, int &lo, int &hi) {
 
 // Both sweep kernels split their block into compute waves and staging waves.  The
 // staging waves copy the per-cell rows of hyperplane t+1 (contiguous in hyperplane order)
-// from HBM into one of two LDS buffers during step t, having issued the loads during step
-// t-1; the compute waves read only LDS for per-cell data.  A wave's loads complete in
+// from HBM into one of two LDS buffers during step t, having issued the loads SDEPTH (or
+// MDEPTH) steps earlier; the compute waves read only LDS for per-cell data.  A wave's loads complete in
 // order, so keeping these copies out of the compute waves lets the compute waves' own
 // prefetches run ahead without waiting for them.
-constexpr int SPW = 16;  // staged values per staging lane and hyperplane (macro sweep)
+constexpr int SPW = 16;    // staged values per staging lane and hyperplane (macro sweep)
+constexpr int SDEPTH = 4;  // hyperplanes of staging loads in flight (micro sweeps)
+constexpr int MDEPTH = 3;  // the same for the macro sweep (its rows are longer)
 
 template <class T>
 DEV void stage_store(const T (&reg)[SPW], T *dst, int n, int sl, int nsl) {
@@ -697,27 +699,42 @@ __global__ __launch_bounds__(768) void k_macro_sweep(Params p, int nct) {
     // hyperplane in each direction, plus the block-wide one between the directions.
     if ((int)threadIdx.x >= nct) {
         const int sl = (int)threadIdx.x - nct, nsl = (int)blockDim.x - nct;
-        double reg[SPW];
+        // register set k holds the row values of a hyperplane t with t % MDEPTH == k; the
+        // loads of hyperplane t+1 are issued MDEPTH steps before it is staged
+        double reg[MDEPTH][SPW];
         // rows past the hyperplane are read (spare rows at the end of mh) but never staged
-        auto issue = [&](int h) {
+        auto issue = [&](double (&rg)[SPW], int h) {
             const double *src = p.mh + (size_t)hpo[h] * MH_N + sl;
 #pragma unroll
-            for (int q = 0; q < SPW; ++q) reg[q] = src[q * nsl];
+            for (int q = 0; q < SPW; ++q) rg[q] = src[q * nsl];
         };
         for (int dir = 0; dir < 2; ++dir) {
             const bool upper = dir == 1;
             auto hp = [&](int t) { return upper ? nh - 1 - t : t; };
-            issue(hp(0));
-            stage_store(reg, st0, (hpo[hp(0) + 1] - hpo[hp(0)]) * MH_N, sl, nsl);
-            if (nh > 1) issue(hp(1));
+            auto hcl = [&](int t) { return hp(t < nh ? t : nh - 1); };  // repeated rows are not staged
+            auto cells = [&](int t) { return hpo[hp(t) + 1] - hpo[hp(t)]; };
+            issue(reg[0], hcl(0));
+            stage_store(reg[0], st0, cells(0) * MH_N, sl, nsl);
+#pragma unroll
+            for (int d = 1; d <= MDEPTH; ++d) issue(reg[d % MDEPTH], hcl(d));
             lds_barrier();
-            for (int t = 0; t < nh; ++t) {
-                if (t + 1 < nh) {
-                    const int h = hp(t + 1);
-                    stage_store(reg, (t + 1) & 1 ? st1 : st0, (hpo[h + 1] - hpo[h]) * MH_N, sl, nsl);
+            int t0 = 0;
+            for (; t0 + MDEPTH <= nh; t0 += MDEPTH) {
+#pragma unroll
+                for (int d = 0; d < MDEPTH; ++d) {
+                    const int t = t0 + d;
+                    if (t + 1 < nh) stage_store(reg[(d + 1) % MDEPTH], (t + 1) & 1 ? st1 : st0, cells(t + 1) * MH_N, sl, nsl);
+                    issue(reg[(d + 1) % MDEPTH], hcl(t + 1 + MDEPTH));
+                    lds_barrier();
                 }
-                if (t + 2 < nh) issue(hp(t + 2));
-                lds_barrier();
+            }
+#pragma unroll
+            for (int d = 0; d < MDEPTH - 1; ++d) {
+                const int t = t0 + d;
+                if (t < nh) {
+                    if (t + 1 < nh) stage_store(reg[(d + 1) % MDEPTH], (t + 1) & 1 ? st1 : st0, cells(t + 1) * MH_N, sl, nsl);
+                    lds_barrier();
+                }
             }
             __syncthreads();
         }
@@ -735,30 +752,52 @@ __global__ __launch_bounds__(768) void k_macro_sweep(Params p, int nct) {
             if (i <= hi) {
                 const int j = s - i, c = i + j * ni;
                 const double *m = (t & 1 ? st1 : st0) + (size_t)k * MH_N;
+                // the whole staged row in one batch of LDS reads (no read waits on a write)
+                double mr[5], ms[4][12];
+                int code[4];
+#pragma unroll
+                for (int a = 0; a < 5; ++a) mr[a] = m[a];
+#pragma unroll
+                for (int sd = 0; sd < 4; ++sd) {
+                    code[sd] = (int)m[5 + sd];
+#pragma unroll
+                    for (int e = 0; e < 12; ++e) ms[sd][e] = m[9 + 12 * sd + e];
+                }
+                // the neighbours' increments, again in one batch (unused sides read fr0)
+                double dW[4][4];
+#pragma unroll
+                for (int sd = 0; sd < 4; ++sd) {
+                    const int fi = upper ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
+                    const double *src = !(code[sd] & need) ? fr0
+                                        : (code[sd] & SG_ADJ) ? fr0 + 4 * fi
+                                        : (sd < 2 ? wI + 4 * j : wJ + 4 * i);
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) dW[sd][a] = src[a];
+                }
                 double r[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int sd = 0; sd < 4; ++sd) {
-                    const int code = (int)m[5 + sd];
-                    if (!(code & need)) continue;
-                    const double *ms = m + 9 + 12 * sd;
-                    const int fi = upper ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
-                    const double *src = (code & SG_ADJ) ? fr0 + 4 * fi : (sd < 2 ? wI + 4 * j : wJ + 4 * i);
+                    if (!(code[sd] & need)) continue;
                     double Wn[4], F1[4];
-                    for (int a = 0; a < 4; ++a) Wn[a] = ms[8 + a] + src[a];
-                    euler_flux_n(Wn, ms[0], ms[1], ik2, F1);
-                    const double hS = 0.5 * ms[2];
-                    for (int a = 0; a < 4; ++a) r[a] += hS * (F1[a] - ms[4 + a] - ms[3] * src[a]);
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) Wn[a] = ms[sd][8 + a] + dW[sd][a];
+                    euler_flux_n(Wn, ms[sd][0], ms[sd][1], ik2, F1);
+                    const double hS = 0.5 * ms[sd][2];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) r[a] += hS * (F1[a] - ms[sd][4 + a] - ms[sd][3] * dW[sd][a]);
                 }
-                const double iD = m[4];
+                double d[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)  // forward: dW* = (M_W - r)/D; backward: dW = dW* - r/D
+                    d[a] = upper ? mr[a] - r[a] * mr[4] : (mr[a] - r[a]) * mr[4];
                 double *row = p.mh + (size_t)(hpo[s] + k) * MH_N;
+#pragma unroll
                 for (int a = 0; a < 4; ++a) {
-                    // forward: dW* = (M_W - r)/D; backward: dW = dW* - r/D
-                    const double d = upper ? m[a] - r[a] * iD : (m[a] - r[a]) * iD;
-                    if (upper) p.dW[(size_t)c * 4 + a] = d;
-                    else row[a] = d;
-                    fr1[4 * i + a] = d;
-                    if (i == (upper ? ni - 1 : 0)) wI[4 * j + a] = d;
-                    if (j == (upper ? nj - 1 : 0)) wJ[4 * i + a] = d;
+                    if (upper) p.dW[(size_t)c * 4 + a] = d[a];
+                    else row[a] = d[a];
+                    fr1[4 * i + a] = d[a];
+                    if (i == (upper ? ni - 1 : 0)) wI[4 * j + a] = d[a];
+                    if (j == (upper ? nj - 1 : 0)) wJ[4 * i + a] = d[a];
                 }
             }
             lds_barrier();
@@ -826,18 +865,20 @@ constexpr int SPW_MICRO = 8;
 
 template <bool UPPER>
 struct StageCol {
-    const double *base;  // nullptr: the column is constant 0 (or the lane is idle)
+    const double *base;
     int stride, r, k0;
+    bool zero;  // the column is constant 0 (or the lane is idle)
     DEV StageCol(const Params &p, int sl, int nsl) {
         const int kp = nsl / STG;
         r = sl % STG;
         k0 = sl / STG;
-        base = nullptr;
+        base = p.srec;  // zero columns and idle lanes read this value and discard it
         stride = 0;
+        zero = true;
         if (k0 >= kp) return;  // idle lane
-        if (r >= SR_N) { base = p.sgeo + (r - SR_N); stride = SG_N; }
-        else if (!UPPER || r >= 10) { base = p.srec + r; stride = SR_N; }
-        else if (r < 4) { base = p.sdrho + r; stride = 4; }
+        if (r >= SR_N) { base = p.sgeo + (r - SR_N); stride = SG_N; zero = false; }
+        else if (!UPPER || r >= 10) { base = p.srec + r; stride = SR_N; zero = false; }
+        else if (r < 4) { base = p.sdrho + r; stride = 4; zero = false; }
     }
 };
 
@@ -845,7 +886,6 @@ struct StageCol {
 // rows at their end)
 template <class T, bool UPPER>
 DEV void sweep_issue(const StageCol<UPPER> &col, T (&reg)[SPW_MICRO], const int *hpo, int h, int kp) {
-    if (!col.base) return;
     const double *src = col.base + (size_t)(hpo[h] + col.k0) * col.stride;
     const size_t step = (size_t)kp * col.stride;
 #pragma unroll
@@ -860,7 +900,7 @@ DEV void sweep_stage(const StageCol<UPPER> &col, const T (&reg)[SPW_MICRO], T *d
     T *d = dst + col.k0 * STG + col.r;
 #pragma unroll
     for (int q = 0; q < SPW_MICRO; ++q)
-        if (col.k0 + q * kp < cells) d[q * kp * STG] = col.base ? reg[q] : T(0);
+        if (col.k0 + q * kp < cells) d[q * kp * STG] = col.zero ? T(0) : reg[q];
 }
 
 template <class S, bool SHAK, bool UPPER>
@@ -879,15 +919,32 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
     if ((int)threadIdx.x >= nct) {
         const int sl = (int)threadIdx.x - nct, nsl = (int)blockDim.x - nct, kp = nsl / STG;
         const StageCol<UPPER> col(p, sl, nsl);
-        T reg[SPW_MICRO];
-        sweep_issue<T, UPPER>(col, reg, hpo, hp(0), kp);
-        sweep_stage<T, UPPER>(col, reg, st0, hpo, hp(0), kp, nsl);
-        if (nh > 1) sweep_issue<T, UPPER>(col, reg, hpo, hp(1), kp);
+        // register set k holds a hyperplane t with t % SDEPTH == k; the loads of hyperplane
+        // t+1 are issued SDEPTH steps before it is staged
+        T reg[SDEPTH][SPW_MICRO];
+        auto hcl = [&](int t) { return hp(t < nh ? t : nh - 1); };  // repeated rows are not staged
+        sweep_issue<T, UPPER>(col, reg[0], hpo, hcl(0), kp);
+        sweep_stage<T, UPPER>(col, reg[0], st0, hpo, hp(0), kp, nsl);
+#pragma unroll
+        for (int d = 1; d <= SDEPTH; ++d) sweep_issue<T, UPPER>(col, reg[d % SDEPTH], hpo, hcl(d), kp);
         lds_barrier();
-        for (int t = 0; t < nh; ++t) {
-            if (t + 1 < nh) sweep_stage<T, UPPER>(col, reg, (t + 1) & 1 ? st1 : st0, hpo, hp(t + 1), kp, nsl);
-            if (t + 2 < nh) sweep_issue<T, UPPER>(col, reg, hpo, hp(t + 2), kp);
-            lds_barrier();
+        int t0 = 0;
+        for (; t0 + SDEPTH <= nh; t0 += SDEPTH) {
+#pragma unroll
+            for (int d = 0; d < SDEPTH; ++d) {
+                const int t = t0 + d;
+                if (t + 1 < nh) sweep_stage<T, UPPER>(col, reg[(d + 1) % SDEPTH], (t + 1) & 1 ? st1 : st0, hpo, hp(t + 1), kp, nsl);
+                sweep_issue<T, UPPER>(col, reg[(d + 1) % SDEPTH], hpo, hcl(t + 1 + SDEPTH), kp);
+                lds_barrier();
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < SDEPTH - 1; ++d) {
+            const int t = t0 + d;
+            if (t < nh) {
+                if (t + 1 < nh) sweep_stage<T, UPPER>(col, reg[(d + 1) % SDEPTH], (t + 1) & 1 ? st1 : st0, hpo, hp(t + 1), kp, nsl);
+                lds_barrier();
+            }
         }
         return;
     }
@@ -1175,10 +1232,13 @@ MacroShape macro_shape(int ni, int nj) {
     return m;
 }
 
-hipError_t launch_macro(const Params &p, hipStream_t st) {
+hipError_t launch_macro_prep(const Params &p, hipStream_t st) {
     hipLaunchKernelGGL(k_macro_prep, dim3((p.nc + 255) / 256), dim3(256), 0, st, p);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_macro(const Params &p, hipStream_t st) {
+    hipError_t e = hipSuccess;
     const MacroShape m = macro_shape(p.ni, p.nj);
     if (m.lds > 64 * 1024) {
         e = hipFuncSetAttribute((const void *)k_macro_sweep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)m.lds);

@@ -25,7 +25,8 @@ struct SweepShape {
 };
 MacroShape macro_shape(int ni, int nj);
 SweepShape sweep_shape(int ni, int nj, int nv, size_t s_bytes);
-hipError_t launch_macro(const Params &p, hipStream_t st);
+hipError_t launch_macro_prep(const Params &p, hipStream_t st);  // k_macro_prep
+hipError_t launch_macro(const Params &p, hipStream_t st);       // k_macro_sweep (after the prep)
 hipError_t launch_sweep(const Params &p, bool fp32, bool upper, const SweepShape &sh, hipStream_t st);
 hipError_t launch_wall_ghost(const Params &p, bool fp32, hipStream_t st);
 hipError_t launch_explicit(const Params &p, bool fp32, hipStream_t st);
