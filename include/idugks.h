@@ -154,6 +154,34 @@ idugks_status idugks_predict(idugks_ctx *ctx, double *Wstar, double *dt_imp, int
 idugks_status idugks_get_state(idugks_ctx *ctx, double *f, int32_t on_host);
 idugks_status idugks_set_state(idugks_ctx *ctx, const double *f, int32_t on_host);
 
+/* Sensitivities (BGK, no limiter, FP64 form; IDUGKS_E_INVALID otherwise).
+   The steady residual is R(f; theta) = M(f) - (2 Omega/(2 tau + dt)) (phi~ - phi_eq) per cell
+   and velocity (Eq. 11-23 in the implicit scheme's form; Eq. 21 and Eq. 22 share its zero),
+   with theta = (tangential speed of the j+ wall, temperature of every wall (one common value),
+   Kn).  Objectives, from the Eq. 18 wall-face distributions phi_k (n_k out of the gas):
+     0: sum over j+ wall faces of S_k sum_v w xi_x (xi.n_k) G_k          (lid x-momentum flux)
+     1: sum over wall faces of S_k sum_v w (xi.n_k) (|xi - U_w|^2 G_k + H_k)/2  (heat flux)
+   Arrays lam, f_bar, dJ_df use the canonical FP64 layout [2][nc][nv], device memory unless
+   on_host; theta-sized arrays are host memory. */
+
+/* f_bar = lam^T dR/df, theta_bar = lam^T dR/dtheta at the current state. */
+idugks_status idugks_vjp(idugks_ctx *ctx, const double *lam, double *f_bar, double theta_bar[3],
+                         int32_t on_host);
+
+/* Objective J, dJ/df and dJ/dtheta at fixed f, at the current state (any may be NULL). */
+idugks_status idugks_objective(idugks_ctx *ctx, int32_t objective, double *J, double *dJ_df,
+                               double dJ_dtheta[3], int32_t on_host);
+
+/* Steady sensitivity of a closed domain at the current (converged) state: solves
+   A^T lam + mu l_M = dJ/df (A = dR/df, l_M the total-mass functional) by the transposed
+   micro LU-SGS iteration (Eq. 26, transposed) and returns grad = dJ/dtheta = dJ/dtheta|_f -
+   lam^T dR/dtheta, J, the iteration count and the relative change of the last iteration.
+   lam (may be NULL) receives the multipliers, defined up to multiples of w on G.  Returns
+   IDUGKS_E_NOT_CONVERGED at the iteration limit (outputs hold the last iterate). */
+idugks_status idugks_adjoint(idugks_ctx *ctx, int32_t objective, double tol, int32_t max_iter,
+                             double *J, double grad[3], int32_t *iters, double *res, double *lam,
+                             int32_t on_host);
+
 /* Kernel timing: runs nsteps steps of `mode` recording a HIP event pair around every
    kernel launch on the context's stream (no waits between launches), then waits once;
    ms (host, [nk]) receives the summed milliseconds per kernel and counts (host, [nk], may

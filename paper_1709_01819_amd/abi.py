@@ -65,6 +65,10 @@ _SIGS = {
     "idugks_predict": (C.c_int, [_P, _P, _P, C.c_int32]),
     "idugks_get_state": (C.c_int, [_P, _P, C.c_int32]),
     "idugks_set_state": (C.c_int, [_P, _P, C.c_int32]),
+    "idugks_vjp": (C.c_int, [_P, _P, _P, _D, C.c_int32]),
+    "idugks_objective": (C.c_int, [_P, C.c_int32, _D, _P, _D, C.c_int32]),
+    "idugks_adjoint": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int32, _D, _D,
+                                 C.POINTER(C.c_int32), _D, _P, C.c_int32]),
     "idugks_num_kernels": (C.c_int32, []),
     "idugks_kernel_name": (C.c_char_p, [C.c_int32]),
     "idugks_profile": (C.c_int, [_P, C.c_int32, C.c_int32, _D, C.POINTER(C.c_int64)]),

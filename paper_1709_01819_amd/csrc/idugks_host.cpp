@@ -152,6 +152,8 @@ struct idugks_ctx {
     Params p;
     bool fp32;
     SweepShape sweep;
+    bool adj;                           // sensitivities available
+    double *lt, *gJ, *ybuf, *adjs;      // adjoint iterate, dJ/df, projection, device scalars
     hipStream_t st;
     std::vector<double> area_h, xi_h, eta_h, w_h;
     double *stage;  // [nc][nvp] FP64 staging of one canonical species
@@ -222,48 +224,75 @@ struct Built {
     std::vector<Face> faces;
     std::vector<int> wall_faces;
     std::vector<double> gw, wKRT, ginf, hinf, wden, bhalf, eq0;
+    std::vector<double> dgw, dwden;  // [2][4][nvp], [2][nf]: d/d(wall speed), d/d(wall T)
 };
 
-// Equilibrium pair with exact discrete conserved moments for a state at rest in its
-// own frame (no heat flux): G = G_M (1 + beta.psi(c)), H = K RT G (Eq. 2, Eq. 5).
-void host_equilibrium(const Built &b, int K, double rho, double U, double V, double T,
-                      double *G, double *H) {
-    const double RT = 0.5 * T, lam = 0.5 / RT, A0 = rho * lam / M_PI;
-    double A[4][4] = {{0}}, r[4] = {rho, 0.0, 0.0, rho * RT};
-    std::vector<double> gm(b.nv);
+// Number with two tangents (derivatives of the wall Maxwellian with respect to the wall
+// speed and temperature).
+struct HD {
+    double v, d[2];
+};
+inline HD hd(double a, double d0 = 0.0, double d1 = 0.0) { return HD{a, {d0, d1}}; }
+inline HD operator+(HD a, HD b) { return HD{a.v + b.v, {a.d[0] + b.d[0], a.d[1] + b.d[1]}}; }
+inline HD operator-(HD a, HD b) { return HD{a.v - b.v, {a.d[0] - b.d[0], a.d[1] - b.d[1]}}; }
+inline HD operator*(HD a, HD b) { return HD{a.v * b.v, {a.d[0] * b.v + a.v * b.d[0], a.d[1] * b.v + a.v * b.d[1]}}; }
+inline HD operator/(HD a, HD b) {
+    const double q = a.v / b.v;
+    return HD{q, {(a.d[0] - q * b.d[0]) / b.v, (a.d[1] - q * b.d[1]) / b.v}};
+}
+inline HD exp(HD a) { const double e = std::exp(a.v); return HD{e, {e * a.d[0], e * a.d[1]}}; }
+inline double val(double a) { return a; }
+inline double val(HD a) { return a.v; }
+template <class R> inline R num(double a) { return R(a); }
+template <> inline HD num<HD>(double a) { return hd(a); }
+
+// Equilibrium G with exact discrete conserved moments for a state at rest in its own
+// frame (no heat flux): G = G_M (1 + beta.psi(c)) (Eq. 2, Eq. 5; H = K RT G).
+template <class R>
+void host_equilibrium_g(const Built &b, R rho, R U, R V, R T, R *G) {
+    using std::exp;
+    const R RT = num<R>(0.5) * T, lam = num<R>(0.5) / RT, A0 = rho * lam / num<R>(M_PI);
+    R A[4][4], r[4] = {rho, num<R>(0.0), num<R>(0.0), rho * RT};
+    for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 4; ++c) A[a][c] = num<R>(0.0);
+    std::vector<R> gm(b.nv);
     for (int v = 0; v < b.nv; ++v) {
-        const double cx = b.xi[v] - U, cy = b.eta[v] - V, c2 = cx * cx + cy * cy;
-        gm[v] = A0 * exp(-lam * c2);
-        const double ps[4] = {1.0, cx, cy, 0.5 * c2};
+        const R cx = num<R>(b.xi[v]) - U, cy = num<R>(b.eta[v]) - V, c2 = cx * cx + cy * cy;
+        gm[v] = A0 * exp(num<R>(0.0) - lam * c2);
+        const R ps[4] = {num<R>(1.0), cx, cy, num<R>(0.5) * c2};
         for (int a = 0; a < 4; ++a) {
-            r[a] -= b.w[v] * ps[a] * gm[v];
-            for (int c = 0; c < 4; ++c) A[a][c] += b.w[v] * ps[a] * ps[c] * gm[v];
+            r[a] = r[a] - num<R>(b.w[v]) * ps[a] * gm[v];
+            for (int c = 0; c < 4; ++c) A[a][c] = A[a][c] + num<R>(b.w[v]) * ps[a] * ps[c] * gm[v];
         }
     }
     // Gaussian elimination with partial pivoting
     for (int k = 0; k < 4; ++k) {
         int pv = k;
         for (int i = k + 1; i < 4; ++i)
-            if (fabs(A[i][k]) > fabs(A[pv][k])) pv = i;
+            if (fabs(val(A[i][k])) > fabs(val(A[pv][k]))) pv = i;
         std::swap(A[k], A[pv]);
         std::swap(r[k], r[pv]);
         for (int i = k + 1; i < 4; ++i) {
-            const double m = A[i][k] / A[k][k];
-            for (int c = k; c < 4; ++c) A[i][c] -= m * A[k][c];
-            r[i] -= m * r[k];
+            const R m = A[i][k] / A[k][k];
+            for (int c = k; c < 4; ++c) A[i][c] = A[i][c] - m * A[k][c];
+            r[i] = r[i] - m * r[k];
         }
     }
     for (int k = 3; k >= 0; --k) {
-        double s = r[k];
-        for (int c = k + 1; c < 4; ++c) s -= A[k][c] * r[c];
+        R s = r[k];
+        for (int c = k + 1; c < 4; ++c) s = s - A[k][c] * r[c];
         r[k] = s / A[k][k];
     }
     for (int v = 0; v < b.nv; ++v) {
-        const double cx = b.xi[v] - U, cy = b.eta[v] - V;
-        const double g = gm[v] * (1.0 + r[0] + r[1] * cx + r[2] * cy + 0.5 * r[3] * (cx * cx + cy * cy));
-        G[v] = g;
-        H[v] = K * RT * g;
+        const R cx = num<R>(b.xi[v]) - U, cy = num<R>(b.eta[v]) - V;
+        G[v] = gm[v] * (num<R>(1.0) + r[0] + r[1] * cx + r[2] * cy + num<R>(0.5) * r[3] * (cx * cx + cy * cy));
     }
+}
+
+void host_equilibrium(const Built &b, int K, double rho, double U, double V, double T,
+                      double *G, double *H) {
+    host_equilibrium_g<double>(b, rho, U, V, T, G);
+    for (int v = 0; v < b.nv; ++v) H[v] = K * 0.5 * T * G[v];
 }
 
 // Normal speed with velocities tangent to the face (within 1e-12 of their speed) snapped
@@ -510,6 +539,22 @@ idugks_status build(const idugks_config *c, Built &b) {
     host_equilibrium(b, c->K, c->far_rho, c->far_u, c->far_v, c->far_T, b.ginf.data(), b.hinf.data());
     b.eq0.assign((size_t)2 * b.nvp, 0.0);
     host_equilibrium(b, c->K, c->init_rho, c->init_u, c->init_v, c->init_T, b.eq0.data(), b.eq0.data() + b.nvp);
+    // derivatives of the wall Maxwellians with respect to the wall's tangential speed (along
+    // x) and its temperature, for the sensitivities
+    b.dgw.assign((size_t)2 * 4 * b.nvp, 0.0);
+    b.dwden.assign((size_t)2 * b.nf, 0.0);
+    {
+        std::vector<HD> gd(b.nv);
+        for (int s = 0; s < 4; ++s) {
+            if (c->bc[s] != IDUGKS_BC_WALL) continue;
+            host_equilibrium_g<HD>(b, hd(1.0), hd(c->wall_u[s], 1.0, 0.0), hd(c->wall_v[s]),
+                                   hd(c->wall_T[s], 0.0, 1.0), gd.data());
+            for (int v = 0; v < b.nv; ++v) {
+                b.dgw[(size_t)s * b.nvp + v] = gd[v].d[0];
+                b.dgw[((size_t)4 + s) * b.nvp + v] = gd[v].d[1];
+            }
+        }
+    }
     b.wden.assign(b.nf, 0.0);
     b.bhalf.assign((size_t)b.nf * NM_MAX, 0.0);
     b.nwall = 0;
@@ -534,6 +579,15 @@ idugks_status build(const idugks_config *c, Built &b) {
             }
             b.wden[k] = den;
             raw12(b, g, gH.data(), use, &b.bhalf[(size_t)k * NM_MAX]);
+            for (int q = 0; q < 2; ++q) {
+                const double *dg = &b.dgw[((size_t)q * 4 + F.wside) * b.nvp];
+                double dd = 0.0;
+                for (int v = 0; v < b.nv; ++v) {
+                    const double un = normal_speed(b.xi[v], b.eta[v], F.nx, F.ny);
+                    if (un < 0.0) dd += b.w[v] * un * dg[v];
+                }
+                b.dwden[(size_t)q * b.nf + k] = dd;
+            }
         } else {
             raw12(b, b.ginf.data(), b.hinf.data(), use, &b.bhalf[(size_t)k * NM_MAX]);
         }
@@ -546,8 +600,19 @@ enum Region {
     R_CS, R_FACES, R_WALLF, R_AREA, R_XI, R_ETA, R_W, R_X1, R_WX1, R_Y1, R_WY1, R_VIX, R_VIY,
     R_GW, R_WKRT, R_GINF, R_HINF, R_WDEN, R_BHALF, R_F, R_D1, R_TAB, R_TABS, R_TABF, R_REC,
     R_RECS, R_RECF, R_PART, R_RAW, R_WC, R_MW, R_DW, R_DWD, R_DTIMP, R_RHOOLD, R_DRHO, R_SCAL,
-    R_STAGE, R_HPOFF, R_HPPOS, R_SGEO, R_SREC, R_SDRHO, R_MH, R_GR, R_COUNT
+    R_STAGE, R_HPOFF, R_HPPOS, R_SGEO, R_SREC, R_SDRHO, R_MH, R_GR,
+    // sensitivities (empty unless BGK, no limiter, FP64)
+    R_LT, R_GJ, R_FBAR, R_YBUF, R_AGR, R_FADJ, R_CADJ, R_DGW, R_DWDEN, R_JACC, R_JACF, R_RED,
+    R_ADJS, R_COUNT
 };
+
+// Sensitivities are available for BGK without limiter in the FP64 form.
+bool adjoint_capable(const idugks_config *c) {
+    return c->model == IDUGKS_BGK && c->limiter == 0 && c->precision == IDUGKS_FP64;
+}
+
+constexpr int ADJS_N = 16;  // device scalars: [0..3] theta-bar, J of the last product;
+                            // [4] mass dot; [5..6] update norms; [8..11] objective theta, J
 
 Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy, int nwall) {
     Layout L;
@@ -555,6 +620,7 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
     // rows of the hyperplane-ordered sweep arrays: the staging waves read whole passes past
     // the last cell of a hyperplane, so these arrays carry min(ni, nj) + 32 spare rows
     const size_t ncs = (size_t)nc + std::min(c->ni, c->nj) + 32;
+    const size_t adj = adjoint_capable(c) ? 1 : 0;
     const size_t sizes[R_COUNT] = {
         sizeof(CellSide) * 4 * (size_t)nc, sizeof(Face) * (size_t)nf, sizeof(int) * (size_t)std::max(nwall, 1),
         8 * (size_t)nc, 8 * (size_t)nvp, 8 * (size_t)nvp, 8 * (size_t)nvp, 8 * (size_t)nvx, 8 * (size_t)nvx,
@@ -566,7 +632,11 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
         8 * 4 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nf, 8 * SC_NUM,
         8 * (size_t)std::max(nc, 2) * nvp, sizeof(int) * (size_t)(nc + 2), sizeof(int) * (size_t)nc,
         8 * (size_t)SG_N * ncs, 8 * (size_t)SR_N * ncs, 8 * 4 * (size_t)ncs, 8 * (size_t)MH_N * ncs,
-        S * 6 * (size_t)nc * nvp};
+        S * 6 * (size_t)nc * nvp,
+        adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 2 * (size_t)nc * nvp,
+        adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 6 * (size_t)nc * nvp, adj * 8 * (size_t)FA_N * nf,
+        adj * 8 * (size_t)CA_N * nc, adj * 8 * 8 * (size_t)nvp, adj * 8 * 2 * (size_t)nf,
+        adj * 8 * 32 * (size_t)nc, adj * 8 * 32 * (size_t)nf, adj * 8 * (size_t)RED_N, adj * 8 * ADJS_N};
     for (int r = 0; r < R_COUNT; ++r) L.add(sizes[r]);
     L.bytes = (L.bytes + 255) & ~size_t(255);
     return L;
@@ -750,6 +820,16 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     p.sgeo = (const double *)R(R_SGEO); p.srec = (double *)R(R_SREC); p.sdrho = (double *)R(R_SDRHO);
     p.mh = (double *)R(R_MH); p.gr = R(R_GR);
     x->stage = (double *)R(R_STAGE);
+    p.Kn = cfg->Kn;
+    for (int s4 = 0; s4 < 4; ++s4) { p.wall_u[s4] = cfg->wall_u[s4]; p.wall_v[s4] = cfg->wall_v[s4]; }
+    x->adj = adjoint_capable(cfg);
+    if (x->adj) {
+        x->lt = (double *)R(R_LT); x->gJ = (double *)R(R_GJ); x->ybuf = (double *)R(R_YBUF);
+        x->adjs = (double *)R(R_ADJS);
+        p.fbar = (double *)R(R_FBAR); p.agr = (double *)R(R_AGR); p.fadj = (double *)R(R_FADJ);
+        p.cadj = (double *)R(R_CADJ); p.dgw = (const double *)R(R_DGW); p.dwden = (const double *)R(R_DWDEN);
+        p.jacc = (double *)R(R_JACC); p.jacf = (double *)R(R_JACF); p.red = (double *)R(R_RED);
+    }
 
     auto up = [&](void *dst, const void *src, size_t n) {
         return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, x->st);
@@ -761,6 +841,7 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     UP(R_Y1, b.y1); UP(R_WY1, b.wy1); UP(R_VIX, b.vix); UP(R_VIY, b.viy); UP(R_GW, b.gw);
     UP(R_WKRT, b.wKRT); UP(R_GINF, b.ginf); UP(R_HINF, b.hinf); UP(R_WDEN, b.wden); UP(R_BHALF, b.bhalf);
     UP(R_STAGE, b.eq0);
+    if (x->adj) { UP(R_DGW, b.dgw); UP(R_DWDEN, b.dwden); }
 #undef UP
     if (e == hipSuccess) e = hipMemsetAsync(p.drho, 0, sizeof(double) * b.nf, x->st);
     if (e == hipSuccess) e = hipMemsetAsync(p.sdrho, 0, sizeof(double) * 4 * b.nc, x->st);
@@ -928,6 +1009,138 @@ idugks_status idugks_predict(idugks_ctx *x, double *Wstar, double *dt_imp, int32
     }
     HIPCHK(hipStreamSynchronize(x->st));
     return IDUGKS_OK;
+}
+
+// ---- sensitivities --------------------------------------------------------------------
+static idugks_status adjoint_check(idugks_ctx *x) {
+    if (!x) return fail(IDUGKS_E_INVALID, "null context");
+    if (!x->adj) return fail(IDUGKS_E_INVALID, "sensitivities need the BGK model, no limiter and the FP64 form");
+    return IDUGKS_OK;
+}
+
+// Forward values the reverse pass reads: records, gr, face records, flux, record Jacobians.
+static idugks_status adjoint_forward(idugks_ctx *x) {
+    idugks_status s = flux_pipeline(x);
+    if (s != IDUGKS_OK) return s;
+    HIPCHK(launch_rec_jac(x->p, x->st));
+    return IDUGKS_OK;
+}
+
+// f-bar = lam^T dR/df (+ seed of objective obj), theta-bar and J into out[0..3]
+static idugks_status vjp_core(idugks_ctx *x, const double *lam, int obj, double *out) {
+    Params q = x->p;
+    q.lam = lam;
+    HIPCHK(launch_adj_face(q, obj, x->st));
+    HIPCHK(launch_adj_gather(q, obj, x->st));
+    HIPCHK(launch_adj_cell(q, x->st));
+    HIPCHK(launch_adj_theta(q, out, x->st));
+    return IDUGKS_OK;
+}
+
+// canonical [2][nc][nv] (host or device) -> device layout [nc][2][nvp]
+static idugks_status canonical_in(idugks_ctx *x, const double *src, int on_host, double *dst) {
+    const size_t n = (size_t)2 * x->p.nc * x->p.nv;
+    if (on_host) {
+        HIPCHK(hipMemcpyAsync(x->ybuf, src, n * sizeof(double), hipMemcpyHostToDevice, x->st));
+        src = x->ybuf;
+    }
+    HIPCHK(launch_to_dev(x->p, src, dst, x->st));
+    return IDUGKS_OK;
+}
+
+static idugks_status canonical_out(idugks_ctx *x, const double *src, double scale, double *dst, int on_host) {
+    const size_t n = (size_t)2 * x->p.nc * x->p.nv;
+    double *d = on_host ? x->ybuf : dst;
+    HIPCHK(launch_from_dev(x->p, src, d, scale, x->st));
+    if (on_host) HIPCHK(hipMemcpyAsync(dst, x->ybuf, n * sizeof(double), hipMemcpyDeviceToHost, x->st));
+    HIPCHK(hipStreamSynchronize(x->st));
+    return IDUGKS_OK;
+}
+
+idugks_status idugks_vjp(idugks_ctx *x, const double *lam, double *f_bar, double theta_bar[3], int32_t on_host) {
+    idugks_status s = adjoint_check(x);
+    if (s != IDUGKS_OK) return s;
+    if (!lam) return fail(IDUGKS_E_INVALID, "null lam");
+    if ((s = adjoint_forward(x)) != IDUGKS_OK) return s;
+    if ((s = canonical_in(x, lam, on_host, x->lt)) != IDUGKS_OK) return s;
+    if ((s = vjp_core(x, x->lt, -1, x->adjs)) != IDUGKS_OK) return s;
+    if (f_bar && (s = canonical_out(x, x->p.fbar, 1.0, f_bar, on_host)) != IDUGKS_OK) return s;
+    double t[4];
+    HIPCHK(hipMemcpyAsync(t, x->adjs, sizeof t, hipMemcpyDeviceToHost, x->st));
+    HIPCHK(hipStreamSynchronize(x->st));
+    if (theta_bar)
+        for (int a = 0; a < 3; ++a) theta_bar[a] = t[a];
+    return IDUGKS_OK;
+}
+
+idugks_status idugks_objective(idugks_ctx *x, int32_t objective, double *J, double *dJ_df,
+                               double dJ_dtheta[3], int32_t on_host) {
+    idugks_status s = adjoint_check(x);
+    if (s != IDUGKS_OK) return s;
+    if (objective != 0 && objective != 1) return fail(IDUGKS_E_INVALID, "unknown objective");
+    if ((s = adjoint_forward(x)) != IDUGKS_OK) return s;
+    HIPCHK(hipMemsetAsync(x->lt, 0, sizeof(double) * 2 * x->p.nc * x->p.nvp, x->st));
+    if ((s = vjp_core(x, x->lt, objective, x->adjs)) != IDUGKS_OK) return s;
+    if (dJ_df && (s = canonical_out(x, x->p.fbar, 1.0, dJ_df, on_host)) != IDUGKS_OK) return s;
+    double t[4];
+    HIPCHK(hipMemcpyAsync(t, x->adjs, sizeof t, hipMemcpyDeviceToHost, x->st));
+    HIPCHK(hipStreamSynchronize(x->st));
+    if (dJ_dtheta)
+        for (int a = 0; a < 3; ++a) dJ_dtheta[a] = t[a];
+    if (J) *J = t[3];
+    return IDUGKS_OK;
+}
+
+idugks_status idugks_adjoint(idugks_ctx *x, int32_t objective, double tol, int32_t max_iter, double *J,
+                             double grad[3], int32_t *iters, double *res_out, double *lam, int32_t on_host) {
+    idugks_status s = adjoint_check(x);
+    if (s != IDUGKS_OK) return s;
+    if (objective != 0 && objective != 1) return fail(IDUGKS_E_INVALID, "unknown objective");
+    if (!(tol > 0) || max_iter < 1) return fail(IDUGKS_E_INVALID, "bad tolerance or iteration limit");
+    const Params &p = x->p;
+    const size_t nd = (size_t)2 * p.nc * p.nvp;
+    if ((s = adjoint_forward(x)) != IDUGKS_OK) return s;
+    HIPCHK(launch_macro_prep(p, x->st));   // dt_imp of the current state
+    HIPCHK(launch_adj_diag(p, x->st));      // diagonal of the preconditioner
+    // g = dJ/df and dJ/dtheta at fixed f
+    HIPCHK(hipMemsetAsync(x->lt, 0, nd * sizeof(double), x->st));
+    if ((s = vjp_core(x, x->lt, objective, x->adjs + 8)) != IDUGKS_OK) return s;
+    HIPCHK(hipMemcpyAsync(x->gJ, p.fbar, nd * sizeof(double), hipMemcpyDeviceToDevice, x->st));
+    // Fixed-point iteration of the adjoint of one micro LU-SGS iteration with the mass
+    // rescale (closed domains): with y = lt - l_M (f.lt)/M0 and z = P^-T y,
+    //   lt <- y + (dR/df)^T z + g,
+    // whose limit gives the Lagrange multipliers lam = -z of the steady problem and
+    // dJ/dtheta = dJ/dtheta|_f + z^T dR/dtheta.  P is the micro operator of Eq. 26 (current
+    // records, no predictor): its transpose is an ascending and a descending sweep along
+    // the outflow couplings.
+    double r = INFINITY, h[4];
+    int it = 0;
+    const double dotscale = p.closed ? 1.0 : 0.0;
+    for (it = 1; it <= max_iter; ++it) {
+        HIPCHK(launch_dot(p, (const double *)p.f, x->lt, dotscale, x->adjs + 4, x->st));
+        HIPCHK(launch_adj_project(p, x->lt, x->ybuf, x->adjs + 4, x->st));
+        HIPCHK(launch_adj_sweep(p, false, x->sweep, x->st));
+        HIPCHK(launch_adj_sweep(p, true, x->sweep, x->st));
+        if ((s = vjp_core(x, (const double *)p.d1, -1, x->adjs)) != IDUGKS_OK) return s;
+        HIPCHK(launch_adj_update(p, x->lt, x->ybuf, x->gJ, x->adjs + 5, x->st));
+        double nrm[2];
+        HIPCHK(hipMemcpyAsync(nrm, x->adjs + 5, sizeof nrm, hipMemcpyDeviceToHost, x->st));
+        HIPCHK(hipStreamSynchronize(x->st));
+        r = nrm[1] > 0 ? sqrt(nrm[0] / nrm[1]) : 0.0;
+        if (!std::isfinite(r)) return fail(IDUGKS_E_DIVERGED, "adjoint iteration diverged");
+        if (r < tol) break;
+    }
+    double t[12];
+    HIPCHK(hipMemcpyAsync(t, x->adjs, sizeof t, hipMemcpyDeviceToHost, x->st));
+    HIPCHK(hipStreamSynchronize(x->st));
+    for (int a = 0; a < 3; ++a) h[a] = t[8 + a] + t[a];
+    if (grad)
+        for (int a = 0; a < 3; ++a) grad[a] = h[a];
+    if (J) *J = t[11];
+    if (iters) *iters = it > max_iter ? max_iter : it;
+    if (res_out) *res_out = r;
+    if (lam && (s = canonical_out(x, (const double *)p.d1, -1.0, lam, on_host)) != IDUGKS_OK) return s;
+    return r < tol ? IDUGKS_OK : fail(IDUGKS_E_NOT_CONVERGED, "adjoint iteration limit reached");
 }
 
 idugks_status idugks_residual(idugks_ctx *x, double out_l2[4]) {

@@ -104,6 +104,24 @@ struct Params {
     double *sdrho;           // [nc][4] wall ghost density increment per cell side
     double *mh;              // [nc][MH_N] macro: M_W, diagonal, codes, per side nx, ny, S,
                              //                lambda_j, F_n(W_j), W_j
+    // sensitivities (BGK, no limiter, FP64 state; null otherwise)
+    double Kn, wall_u[4], wall_v[4];
+    const double *lam;       // [nc][2][nvp] adjoint weights the VJP is taken with
+    double *fbar;            // [nc][2][nvp] VJP output (d/d phi~)
+    double *agr;             // [nc][6][nvp] per cell the face adjoints gathered where the cell
+                             //   is upwind: direct G, H; sigma-bar x G, y G, x H, y H
+    double *fadj;            // [nf][FA_N] face adjoint record
+    double *cadj;            // [nc][CA_N] cell adjoint record
+    const double *dgw;       // [2][4][nvp] d(wall Maxwellian)/d(u_w), /d(T_w) per wall side
+    const double *dwden;     // [2][nf] d(wden)/d(u_w), /d(T_w) per wall face
+    double *jacc, *jacf;     // [nc][32], [nf][32] record Jacobians d(rho,U,V,RT,c0..c3)/dW
+    double *red;             // [RED_N] partial sums of the fixed-order reductions
 };
+
+// face adjoint record: W-bar (4), rho_w-bar, theta-bar (3: lid speed, wall T, Kn), J part
+enum FaceAdj : int { FA_WB = 0, FA_RHOW = 4, FA_TH = 5, FA_J = 8, FA_N = 9 };
+// cell adjoint record: W-bar (4), theta-bar Kn
+enum CellAdj : int { CA_WB = 0, CA_TH = 4, CA_N = 5 };
+constexpr int RED_N = 4096;
 
 }  // namespace idugks

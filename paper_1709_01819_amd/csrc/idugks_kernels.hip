@@ -903,7 +903,10 @@ DEV void sweep_stage(const StageCol<UPPER> &col, const T (&reg)[SPW_MICRO], T *d
         if (col.k0 + q * kp < cells) d[q * kp * STG] = col.zero ? T(0) : reg[q];
 }
 
-template <class S, bool SHAK, bool UPPER>
+// ADJ: the transposed operator of the adjoint iteration (FP64): the couplings run along
+// the outflow side (xi.n > 0) of the lower / upper neighbours, the right-hand side of the
+// ascending sweep is d1 itself and the descending sweep writes its result to d1.
+template <class S, bool SHAK, bool UPPER, bool ADJ>
 __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
     using T = S;
     extern __shared__ unsigned char lds_raw[];
@@ -975,7 +978,10 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
             const int s = hp(t), i = cur.i, j = s - i;
             const T *m = ((t & 1) ? st1 : st0) + slot * STG;
             T D = m[11], sG, sH;
-            if (!UPPER) {
+            if (!UPPER && ADJ) {
+                sG = cur.aG;
+                sH = cur.aH;
+            } else if (!UPPER) {
                 RecT<T> r;
                 r.U = m[0]; r.V = m[1]; r.c0 = m[2]; r.c1 = m[3]; r.c2c = m[4]; r.c3 = m[5];
                 r.kqx = m[6]; r.kqy = m[7]; r.iRT = m[8]; r.KRT = m[9];
@@ -991,7 +997,19 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
                 const int code = (int)m[SR_N + 12 + sd];
                 if (!(code & SG_DIAG)) continue;
                 const T un = x * m[SR_N + sd] + y * m[SR_N + 4 + sd], Sk = m[SR_N + 8 + sd];
-                if (un > T(0)) {
+                if (ADJ) {
+                    if (un > T(0)) {
+                        D += un * Sk;
+                        if (code & need) {
+                            const int fi = UPPER ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
+                            const T *fp = (code & SG_ADJ) ? f0 + fi * vb
+                                                          : (sd < 2 ? wI + j * vb : wJ + i * vb);
+                            const T cf = un * Sk;
+                            sG += cf * fp[vl];
+                            sH += cf * fp[FR + vl];
+                        }
+                    }
+                } else if (un > T(0)) {
                     D += un * Sk;
                 } else if (un < T(0)) {
                     if (code & need) {
@@ -1018,7 +1036,7 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
             const T iD = T(1) / D;
             const T dG = UPPER ? cur.aG + sG * iD : sG * iD;
             const T dH = UPPER ? cur.aH + sH * iD : sH * iD;
-            if (UPPER) {
+            if (UPPER && !ADJ) {
                 ((S *)p.f)[o] = (S)(sc * cur.bG + dG);
                 ((S *)p.f)[o + p.nvp] = (S)(sc * cur.bH + dH);
             } else {
@@ -1158,6 +1176,525 @@ __global__ void k_fields(Params p, double *out) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Sensitivities: vector-Jacobian product of the steady residual
+//   R_i(v) = M_i(v) - c_i (phi~_i(v) - phi_eq,i(v)),  c_i = 2 Omega_i / (2 tau_i + dt)
+// (Eq. 11-23, BGK, no limiter, FP64 state), with theta = (lid speed, wall T, Kn).  The
+// reverse pass runs the forward chain backwards: Eq. 18 blend and flux of each face,
+// face equilibrium and tau (records), face moments, diffuse-wall density (Eq. 34), upwind
+// reconstruction (Eq. 13-14), least-squares gradient (Eq. 15), phi-bar-plus (Eq. 10, 12),
+// cell equilibrium and tau, cell moments.  The forward values (records, tables, gr) are
+// those of the last flux evaluation at the same state.
+// ---------------------------------------------------------------------------------------
+
+// Forward-mode number with four tangents (derivatives with respect to W).
+struct D4 {
+    double v, d[4];
+};
+DEV D4 dconst(double a) { D4 r; r.v = a; r.d[0] = r.d[1] = r.d[2] = r.d[3] = 0.0; return r; }
+DEV D4 operator+(const D4 &a, const D4 &b) { D4 r; r.v = a.v + b.v; for (int i = 0; i < 4; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
+DEV D4 operator-(const D4 &a, const D4 &b) { D4 r; r.v = a.v - b.v; for (int i = 0; i < 4; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
+DEV D4 operator-(const D4 &a) { D4 r; r.v = -a.v; for (int i = 0; i < 4; ++i) r.d[i] = -a.d[i]; return r; }
+DEV D4 operator*(const D4 &a, const D4 &b) { D4 r; r.v = a.v * b.v; for (int i = 0; i < 4; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i]; return r; }
+DEV D4 operator*(double a, const D4 &b) { D4 r; r.v = a * b.v; for (int i = 0; i < 4; ++i) r.d[i] = a * b.d[i]; return r; }
+DEV D4 operator/(const D4 &a, const D4 &b) {
+    D4 r; r.v = a.v / b.v;
+    for (int i = 0; i < 4; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) / b.v;
+    return r;
+}
+DEV D4 dexp(const D4 &a) { D4 r; r.v = exp(a.v); for (int i = 0; i < 4; ++i) r.d[i] = r.v * a.d[i]; return r; }
+
+DEV void solve4_d(D4 A[4][4], D4 b[4]) {
+    for (int k = 0; k < 4; ++k) {
+        int piv = k;
+        for (int r = k + 1; r < 4; ++r)
+            if (fabs(A[r][k].v) > fabs(A[piv][k].v)) piv = r;
+        if (piv != k) {
+            for (int c = 0; c < 4; ++c) { D4 t = A[k][c]; A[k][c] = A[piv][c]; A[piv][c] = t; }
+            D4 t = b[k]; b[k] = b[piv]; b[piv] = t;
+        }
+        for (int r = k + 1; r < 4; ++r) {
+            const D4 m = A[r][k] / A[k][k];
+            for (int c = k; c < 4; ++c) A[r][c] = A[r][c] - m * A[k][c];
+            b[r] = b[r] - m * b[k];
+        }
+    }
+    for (int k = 3; k >= 0; --k) {
+        D4 s = b[k];
+        for (int c = k + 1; c < 4; ++c) s = s - A[k][c] * b[c];
+        b[k] = s / A[k][k];
+    }
+}
+
+// Jacobian J[m][a] = d p_m / d W_a of the BGK equilibrium record
+// p = (rho, U, V, RT, c0, c1, c2c, c3) from the conserved moments W, by the same steps as
+// build_eq (central basis, factored 1-D moments) in forward-mode arithmetic.  One wave;
+// every lane returns J.
+DEV void record_jacobian(const Params &p, const double W[4], double J[8][4], int lane) {
+    D4 w[4];
+    for (int a = 0; a < 4; ++a) { w[a] = dconst(W[a]); w[a].d[a] = 1.0; }
+    const D4 rho = w[0], U = w[1] / rho, V = w[2] / rho;
+    const D4 RT = (2.0 * (w[3] / rho) - U * U - V * V) / dconst((double)(p.K + 2));
+    const D4 lam = dconst(0.5) / RT, A0 = rho * lam / dconst(M_PI);
+    constexpr int NP = 5;
+    double X[NP * 5], Y[NP * 5];
+    for (int i = 0; i < NP * 5; ++i) X[i] = Y[i] = 0.0;
+    for (int ix = lane; ix < p.nvx; ix += 64) {
+        const D4 cx = dconst(p.x1[ix]) - U;
+        const D4 e = dexp(-(lam * cx * cx));
+        D4 t = p.wx1[ix] * e;
+        for (int k = 0; k < NP; ++k) {
+            X[5 * k] += t.v;
+            for (int i = 0; i < 4; ++i) X[5 * k + 1 + i] += t.d[i];
+            t = t * cx;
+        }
+    }
+    for (int iy = lane; iy < p.nvy; iy += 64) {
+        const D4 cy = dconst(p.y1[iy]) - V;
+        const D4 e = dexp(-(lam * cy * cy));
+        D4 t = p.wy1[iy] * e;
+        for (int k = 0; k < NP; ++k) {
+            Y[5 * k] += t.v;
+            for (int i = 0; i < 4; ++i) Y[5 * k + 1 + i] += t.d[i];
+            t = t * cy;
+        }
+    }
+    wave_sum<NP * 5>(X);
+    wave_sum<NP * 5>(Y);
+    auto get = [&](const double *Z, int k) { D4 r; r.v = Z[5 * k]; for (int i = 0; i < 4; ++i) r.d[i] = Z[5 * k + 1 + i]; return r; };
+    auto m = [&](int a, int b) { return A0 * get(X, a) * get(Y, b); };
+    D4 A[4][4], r[4];
+    A[0][0] = m(0, 0); A[0][1] = m(1, 0); A[0][2] = m(0, 1); A[0][3] = 0.5 * (m(2, 0) + m(0, 2));
+    A[1][1] = m(2, 0); A[1][2] = m(1, 1); A[1][3] = 0.5 * (m(3, 0) + m(1, 2));
+    A[2][2] = m(0, 2); A[2][3] = 0.5 * (m(2, 1) + m(0, 3));
+    A[3][3] = 0.25 * (m(4, 0) + 2.0 * m(2, 2) + m(0, 4));
+    for (int a = 1; a < 4; ++a)
+        for (int b = 0; b < a; ++b) A[a][b] = A[b][a];
+    r[0] = rho - A[0][0];
+    r[1] = -A[0][1];
+    r[2] = -A[0][2];
+    r[3] = rho * RT - A[0][3];
+    solve4_d(A, r);
+    const D4 out[8] = {rho, U, V, RT, dconst(1.0) + r[0], r[1], r[2], 0.5 * r[3]};
+    for (int mm = 0; mm < 8; ++mm)
+        for (int a = 0; a < 4; ++a) J[mm][a] = out[mm].d[a];
+}
+
+// Per velocity: accumulate, for the equilibrium adjoint (eG, eH) of a record r with
+// Maxwellian factor M (= tab[ix] tab[nvx+iy]), the sums S_m = sum_v d(E)/d(p_m) . e-bar
+// (p = rho, U, V, RT, c0, c1, c2c, c3).
+DEV void eq_adjoint_acc(const Rec &r, double x, double y, double M, double eG, double eH, double *S) {
+    const double cx = x - r.U, cy = y - r.V, c2 = cx * cx + cy * cy;
+    const double poly = r.c0 + r.c1 * cx + r.c2c * cy + r.c3 * c2;
+    const double G = M * poly;
+    const double e = eG + r.KRT * eH;       // H = K RT G
+    const double Me = M * e;
+    S[0] += e * G / r.rho;
+    S[1] += Me * (r.iRT * cx * poly - r.c1 - 2.0 * r.c3 * cx);
+    S[2] += Me * (r.iRT * cy * poly - r.c2c - 2.0 * r.c3 * cy);
+    S[3] += Me * poly * (0.5 * c2 * r.iRT - 1.0) * r.iRT + (r.KRT * r.iRT) * eH * G;  // K G = KRT G / RT
+    S[4] += Me;
+    S[5] += Me * cx;
+    S[6] += Me * cy;
+    S[7] += Me * c2;
+}
+
+// W-bar = J^T p-bar with p-bar = S + tau-bar d(tau)/d(rho, RT); W from the record.
+DEV void record_wbar(const Params &p, const Rec &r, const double S[8], double taubar,
+                     double J[8][4], double Wb[4]) {
+    double pb[8];
+    for (int m = 0; m < 8; ++m) pb[m] = S[m];
+    pb[0] += taubar * (-r.tau / r.rho);
+    pb[3] += taubar * r.tau * (p.omega - 1.0) / r.RT;
+    for (int a = 0; a < 4; ++a) {
+        double s = 0.0;
+        for (int m = 0; m < 8; ++m) s += J[m][a] * pb[m];
+        Wb[a] = s;
+    }
+}
+
+DEV void rec_W(const Params &p, const Rec &r, double W[4]) {
+    W[0] = r.rho;
+    W[1] = r.rho * r.U;
+    W[2] = r.rho * r.V;
+    W[3] = 0.5 * r.rho * (r.U * r.U + r.V * r.V + (p.K + 2) * r.RT);
+}
+
+// objective seeds: d J / d phi_k(v) at a wall face seen from its gas side (un = xi.n_out)
+template <int OBJ>
+DEV void objective_seed(const Params &p, const Face &F, double S, double x, double y, double wv,
+                        double un, double &sG, double &sH) {
+    sG = sH = 0.0;
+    if (OBJ == 0 && F.type == FT_WALL && F.wside == 3) {
+        sG = S * wv * x * un;
+    } else if (OBJ == 1 && F.type == FT_WALL) {
+        const double cx = x - p.wall_u[F.wside], cy = y - p.wall_v[F.wside];
+        sG = S * wv * un * 0.5 * (cx * cx + cy * cy);
+        sH = S * wv * un * 0.5;
+    }
+}
+
+// One wave per face: the adjoint of phi_k = alpha phi-bar_k + (1 - alpha) E_k, of the face
+// record (W-bar_k), of the wall density and of theta through the wall Maxwellian.
+template <int OBJ>
+__global__ __launch_bounds__(256) void k_adj_face(Params p) {
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= p.nf) return;
+    const Face F = p.faces[k];
+    double *fa = p.fadj + (size_t)k * FA_N;
+    if (F.type == FT_SELF) {
+        if (lane < FA_N) fa[lane] = 0.0;
+        return;
+    }
+    const CellSide cL = p.cs[4 * F.L + F.sL];
+    const Rec r = p.recf[k];
+    const double *tf = (const double *)p.tabf + (size_t)k * (p.nvx + p.nvy);
+    const double h = p.h, al = r.alpha, S = cL.S, sc = p.scal[SC_SCALE];
+    (void)sc;
+    const double *gL = (const double *)p.gr + (size_t)F.L * 6 * p.nvp;
+    const double *gR = F.type == FT_INTERIOR ? (const double *)p.gr + (size_t)F.R * 6 * p.nvp : gL;
+    const CellSide cR = F.type == FT_INTERIOR ? p.cs[4 * F.R + F.sR] : cL;
+    const double *lL = p.lam + (size_t)F.L * 2 * p.nvp;
+    const double *lR = F.type == FT_INTERIOR ? p.lam + (size_t)F.R * 2 * p.nvp : nullptr;
+    const int ws = F.type == FT_WALL ? F.wside : 0;
+    const double *gw = p.gw + (size_t)ws * p.nvp;
+    const double KRTw = p.wKRT[ws];
+    // pass 1: alpha-bar, the equilibrium sums and the objective value
+    double acc[10];
+    for (int i = 0; i < 10; ++i) acc[i] = 0.0;
+    for (int v = lane; v < p.nv; v += 64) {
+        const double x = p.xi[v], y = p.eta[v], wv = p.w[v];
+        const double un = normal_speed(x, y, cL.nx, cL.ny);
+        const bool mineL = un > 0.0 || (un == 0.0 && cL.tie);
+        double fG, fH;
+        if (mineL) {
+            const double rx = cL.dx - h * x, ry = cL.dy - h * y;
+            fG = gL[v] + gL[p.nvp + v] * rx + gL[2 * p.nvp + v] * ry;
+            fH = gL[3 * p.nvp + v] + gL[4 * p.nvp + v] * rx + gL[5 * p.nvp + v] * ry;
+        } else if (F.type == FT_INTERIOR) {
+            const double rx = cR.dx - h * x, ry = cR.dy - h * y;
+            fG = gR[v] + gR[p.nvp + v] * rx + gR[2 * p.nvp + v] * ry;
+            fH = gR[3 * p.nvp + v] + gR[4 * p.nvp + v] * rx + gR[5 * p.nvp + v] * ry;
+        } else if (F.type == FT_WALL) {
+            fG = r.rw * gw[v];
+            fH = r.rw * KRTw * gw[v];
+        } else {
+            fG = p.ginf[v];
+            fH = p.hinf[v];
+        }
+        const double M = tf[p.vix[v]] * tf[p.nvx + p.viy[v]];
+        const RecT<double> rr = load_rec<double>(r);
+        double eG, eH;
+        eq_eval<double, false>(rr, x, y, M, eG, eH);
+        double sG, sH;
+        objective_seed<OBJ>(p, F, S, x, y, wv, un, sG, sH);
+        const double dlG = lL[v] - (lR ? lR[v] : 0.0), dlH = lL[p.nvp + v] - (lR ? lR[p.nvp + v] : 0.0);
+        const double pbG = -S * un * dlG + sG, pbH = -S * un * dlH + sH;
+        acc[0] += pbG * (fG - eG) + pbH * (fH - eH);
+        eq_adjoint_acc(r, x, y, M, (1.0 - al) * pbG, (1.0 - al) * pbH, acc + 1);
+        acc[9] += sG * (al * fG + (1.0 - al) * eG) + sH * (al * fH + (1.0 - al) * eH);
+    }
+    wave_sum<10>(acc);
+    double J[8][4];
+    for (int mm = 0; mm < 8; ++mm)
+        for (int a = 0; a < 4; ++a) J[mm][a] = p.jacf[(size_t)k * 32 + 4 * mm + a];
+    const double t2h = 2.0 * r.tau + h;
+    const double taubar = acc[0] * 2.0 * h / (t2h * t2h);
+    double Wb[4];
+    record_wbar(p, r, acc + 1, taubar, J, Wb);
+    double th[3] = {0.0, 0.0, taubar * r.tau / p.Kn}, rwb = 0.0;
+    if (OBJ == 1 && F.type == FT_WALL && F.wside == 3) {
+        // J2 depends on the lid speed explicitly through |xi - U_w|^2
+        double a[1] = {0.0};
+        for (int v = lane; v < p.nv; v += 64) {
+            const double x = p.xi[v], y = p.eta[v];
+            const double un = normal_speed(x, y, cL.nx, cL.ny);
+            const bool mineL = un > 0.0;
+            const double fG = mineL ? gL[v] + gL[p.nvp + v] * (cL.dx - h * x) + gL[2 * p.nvp + v] * (cL.dy - h * y)
+                                    : r.rw * gw[v];
+            const double M = tf[p.vix[v]] * tf[p.nvx + p.viy[v]];
+            const RecT<double> rr = load_rec<double>(r);
+            double eG, eH;
+            eq_eval<double, false>(rr, x, y, M, eG, eH);
+            a[0] += S * p.w[v] * un * (-(x - p.wall_u[3])) * (al * fG + (1.0 - al) * eG);
+        }
+        wave_sum<1>(a);
+        th[0] += a[0];
+    }
+    if (F.type == FT_WALL) {
+        // incoming half: phi-bar = rho_w g_w(theta), rho_w = -sum_out w un phi-bar / wden(theta)
+        const double *dgU = p.dgw + (size_t)ws * p.nvp, *dgT = p.dgw + (size_t)(4 + ws) * p.nvp;
+        const double dKT = 0.5 * p.K;  // d(K RT_w)/dT_w
+        double a[3] = {0.0, 0.0, 0.0};
+        for (int v = lane; v < p.nv; v += 64) {
+            const double x = p.xi[v], y = p.eta[v], wv = p.w[v];
+            const double un = normal_speed(x, y, cL.nx, cL.ny);
+            if (un > 0.0) continue;
+            double sG, sH;
+            objective_seed<OBJ>(p, F, S, x, y, wv, un, sG, sH);
+            const double dlG = lL[v], dlH = lL[p.nvp + v];
+            const double pbG = -S * un * dlG + sG, pbH = -S * un * dlH + sH;
+            const double q2 = x * x + y * y;
+            const double bbG = al * pbG + wv * (Wb[0] + x * Wb[1] + y * Wb[2] + 0.5 * q2 * Wb[3]);
+            const double bbH = al * pbH + wv * 0.5 * Wb[3];
+            a[0] += (bbG + bbH * KRTw) * gw[v];
+            a[1] += r.rw * (bbG + bbH * KRTw) * dgU[v];
+            a[2] += r.rw * (bbG * dgT[v] + bbH * (dKT * gw[v] + KRTw * dgT[v]));
+        }
+        wave_sum<3>(a);
+        rwb = a[0];
+        const double drw = -r.rw / p.wden[k];  // d(rho_w)/d(wden)
+        if (ws == 3) th[0] += a[1] + rwb * drw * p.dwden[k];
+        th[1] += a[2] + rwb * drw * p.dwden[p.nf + k];
+    }
+    if (lane == 0) {
+        for (int a = 0; a < 4; ++a) fa[FA_WB + a] = Wb[a];
+        fa[FA_RHOW] = rwb;
+        for (int a = 0; a < 3; ++a) fa[FA_TH + a] = th[a];
+        fa[FA_J] = acc[9];
+    }
+}
+
+// Per cell and velocity: gather, from each face at which the cell is upwind, the adjoint of
+// the reconstructed phi-bar_k into phi-bar-plus-bar (direct part) and sigma-bar.
+template <int OBJ>
+__global__ __launch_bounds__(256) void k_adj_gather(Params p) {
+    const int c = xcd_remap(blockIdx.x, p.nc);
+    const CellSide *cs = p.cs + 4 * c;
+    const double h = p.h;
+    const double *lc = p.lam + (size_t)c * 2 * p.nvp;
+    double *out = p.agr + (size_t)c * 6 * p.nvp;
+    for (int v = threadIdx.x; v < p.nv; v += blockDim.x) {
+        const double x = p.xi[v], y = p.eta[v], wv = p.w[v], q2 = x * x + y * y;
+        double dG = 0.0, dH = 0.0, sxG = 0.0, syG = 0.0, sxH = 0.0, syH = 0.0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int type = cs[s].type;
+            if (type == FT_SELF) continue;
+            const double un = normal_speed(x, y, cs[s].nx, cs[s].ny);
+            if (!(un > 0.0 || (un == 0.0 && cs[s].tie))) continue;
+            const int k = cs[s].face;
+            const double *fa = p.fadj + (size_t)k * FA_N;
+            const double al = p.recf[k].alpha;
+            double lnG = 0.0, lnH = 0.0;
+            if (type == FT_INTERIOR) {
+                const double *ln = p.lam + (size_t)cs[s].nb * 2 * p.nvp;
+                lnG = ln[v];
+                lnH = ln[p.nvp + v];
+            }
+            double sG = 0.0, sH = 0.0;
+            if (type == FT_WALL) objective_seed<OBJ>(p, p.faces[k], cs[s].S, x, y, wv, un, sG, sH);
+            const double pbG = -cs[s].S * un * (lc[v] - lnG) + sG;
+            const double pbH = -cs[s].S * un * (lc[p.nvp + v] - lnH) + sH;
+            double bbG = al * pbG + wv * (fa[0] + x * fa[1] + y * fa[2] + 0.5 * q2 * fa[3]);
+            const double bbH = al * pbH + wv * 0.5 * fa[3];
+            if (type == FT_WALL) bbG += -fa[FA_RHOW] * wv * un / p.wden[k];
+            const double rx = cs[s].dx - h * x, ry = cs[s].dy - h * y;
+            dG += bbG; dH += bbH;
+            sxG += bbG * rx; syG += bbG * ry; sxH += bbH * rx; syH += bbH * ry;
+        }
+        out[v] = dG;
+        out[p.nvp + v] = dH;
+        out[2 * p.nvp + v] = sxG;
+        out[3 * p.nvp + v] = syG;
+        out[4 * p.nvp + v] = sxH;
+        out[5 * p.nvp + v] = syH;
+    }
+}
+
+// Per cell: phi-bar-plus-bar = direct + sum_j a_ji sigma-bar_j - (sum_j a_ij) sigma-bar_i,
+// then the collision term, phi-bar-plus and the cell record in reverse, and the moments.
+__global__ __launch_bounds__(256) void k_adj_cell(Params p) {
+    __shared__ double sh[4 * 11];
+    __shared__ double wb[5];
+    const int c = xcd_remap(blockIdx.x, p.nc);
+    const CellSide *cs = p.cs + 4 * c;
+    const Rec r = p.rec[c];
+    const double *tb = (const double *)p.tab + (size_t)c * (p.nvx + p.nvy);
+    const double sc = p.scal[SC_SCALE];
+    const double t2d = 2.0 * r.tau + p.dt, cc = 2.0 * p.area[c] / t2d;
+    double Ax = 0.0, Ay = 0.0;
+    for (int s = 0; s < 4; ++s)
+        if (cs[s].nb >= 0 && cs[s].nb != c) { Ax += cs[s].ax; Ay += cs[s].ay; }
+    const double *own = p.agr + (size_t)c * 6 * p.nvp;
+    const double *lc = p.lam + (size_t)c * 2 * p.nvp;
+    const double *fc = (const double *)p.f + (size_t)c * 2 * p.nvp;
+    double *fb = p.fbar + (size_t)c * 2 * p.nvp;
+    double acc[11];
+    for (int i = 0; i < 11; ++i) acc[i] = 0.0;
+    const RecT<double> rr = load_rec<double>(r);
+    for (int v = threadIdx.x; v < p.nv; v += blockDim.x) {
+        const double x = p.xi[v], y = p.eta[v];
+        double pG = own[v] - (Ax * own[2 * p.nvp + v] + Ay * own[3 * p.nvp + v]);
+        double pH = own[p.nvp + v] - (Ax * own[4 * p.nvp + v] + Ay * own[5 * p.nvp + v]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int j = cs[s].nb;
+            if (j < 0 || j == c) continue;
+            const CellSide &cj = p.cs[4 * j + (s ^ 1)];
+            const double *oj = p.agr + (size_t)j * 6 * p.nvp;
+            pG += cj.ax * oj[2 * p.nvp + v] + cj.ay * oj[3 * p.nvp + v];
+            pH += cj.ax * oj[4 * p.nvp + v] + cj.ay * oj[5 * p.nvp + v];
+        }
+        const double M = tb[p.vix[v]] * tb[p.nvx + p.viy[v]];
+        double eG, eH;
+        eq_eval<double, false>(rr, x, y, M, eG, eH);
+        const double lG = lc[v], lH = lc[p.nvp + v];
+        const double XG = sc * fc[v], XH = sc * fc[p.nvp + v];
+        fb[v] = -cc * lG + r.ab * pG;
+        fb[p.nvp + v] = -cc * lH + r.ab * pH;
+        acc[0] += -(lG * (XG - eG) + lH * (XH - eH));   // c-bar
+        acc[1] += pG * XG + pH * XH;                     // a-bar
+        acc[2] += pG * eG + pH * eH;                     // b-bar
+        eq_adjoint_acc(r, x, y, M, cc * lG + r.bb * pG, cc * lH + r.bb * pH, acc + 3);
+    }
+    block_sum<11>(acc, sh);
+    {
+        double J[8][4];
+        for (int mm = 0; mm < 8; ++mm)
+            for (int a = 0; a < 4; ++a) J[mm][a] = p.jacc[(size_t)c * 32 + 4 * mm + a];
+        if (threadIdx.x == 0) {
+            const double taubar = acc[0] * (-2.0 * cc / t2d) + acc[1] * 2.0 * (p.dt + p.h) / (t2d * t2d) +
+                                  acc[2] * (-6.0 * p.h) / (t2d * t2d);
+            double Wb[4];
+            record_wbar(p, r, acc + 3, taubar, J, Wb);
+            for (int a = 0; a < 4; ++a) wb[a] = Wb[a];
+            wb[4] = taubar * r.tau / p.Kn;
+        }
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v < p.nv; v += blockDim.x) {
+        const double x = p.xi[v], y = p.eta[v], wv = p.w[v];
+        fb[v] += wv * (wb[0] + x * wb[1] + y * wb[2] + 0.5 * (x * x + y * y) * wb[3]);
+        fb[p.nvp + v] += wv * 0.5 * wb[3];
+    }
+    if (threadIdx.x < CA_N) p.cadj[(size_t)c * CA_N + threadIdx.x] = threadIdx.x < 4 ? wb[threadIdx.x] : wb[4];
+}
+
+// Record Jacobians d p / d W of all cells (which = 0) or faces (1), one wave each; they
+// depend on the state only, so one evaluation serves every product at that state.
+__global__ __launch_bounds__(256) void k_rec_jac(Params p, int which) {
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int n = which ? p.nf : p.nc;
+    if (k >= n) return;
+    double *out = (which ? p.jacf : p.jacc) + (size_t)k * 32;
+    if (which && p.faces[k].type == FT_SELF) {
+        if (lane < 32) out[lane] = 0.0;
+        return;
+    }
+    const Rec r = which ? p.recf[k] : p.rec[k];
+    double W[4], J[8][4];
+    rec_W(p, r, W);
+    record_jacobian(p, W, J, lane);
+    if (lane == 0)
+        for (int mm = 0; mm < 8; ++mm)
+            for (int a = 0; a < 4; ++a) out[4 * mm + a] = J[mm][a];
+}
+
+// theta-bar and J: fixed-order sums of the face and cell parts (one block); out[0..2]
+// theta-bar, out[3] J
+__global__ __launch_bounds__(1024) void k_adj_theta(Params p, double *out) {
+    __shared__ double sh[16 * 4];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < p.nf; k += blockDim.x) {
+        const double *fa = p.fadj + (size_t)k * FA_N;
+        a[0] += fa[FA_TH];
+        a[1] += fa[FA_TH + 1];
+        a[2] += fa[FA_TH + 2];
+        a[3] += fa[FA_J];
+    }
+    for (int c = threadIdx.x; c < p.nc; c += blockDim.x) a[2] += p.cadj[(size_t)c * CA_N + CA_TH];
+    block_sum_store<4>(a, sh, out);
+}
+
+// ---- vectors of the adjoint iteration (FP64, device layout [nc][2][nvp], pad lanes 0) ----
+// partial sums of a.b over blocks (fixed order within a block)
+__global__ __launch_bounds__(256) void k_dot(Params p, const double *a, const double *b, double scale_a, int nblk) {
+    __shared__ double sh[4];
+    double s[1] = {0.0};
+    const size_t n = (size_t)p.nc * 2 * p.nvp;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)nblk * blockDim.x)
+        s[0] += scale_a * a[t] * b[t];
+    block_sum_store<1>(s, sh, p.red + blockIdx.x);
+}
+
+// out[0] = sum of the nblk partials (fixed order)
+__global__ void k_dot_final(Params p, int nblk, double *out) {
+    __shared__ double sh[4];
+    double s[1] = {0.0};
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s[0] += p.red[i];
+    block_sum_store<1>(s, sh, out);
+}
+
+// y = lt - l_M (f*.lt) / M0 (l_M = area w on G; f* = scale f, the stored state times its
+// pending mass scale; dot = f.lt), written to y and to the sweep input d1
+__global__ __launch_bounds__(256) void k_adj_project(Params p, const double *lt, double *y, const double *dot) {
+    const size_t n = (size_t)p.nc * 2 * p.nvp;
+    const double k = dot[0] * p.scal[SC_SCALE] / p.M0;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(t / (2 * (size_t)p.nvp)), r = (int)(t % (2 * (size_t)p.nvp));
+        const int sp = r / p.nvp, v = r % p.nvp;
+        double val = v < p.nv ? lt[t] : 0.0;
+        if (sp == 0 && v < p.nv) val -= p.area[c] * p.w[v] * k;
+        y[t] = val;
+        ((double *)p.d1)[t] = val;
+    }
+}
+
+// lt_new = y + fbar + g; partial sums of |lt_new - lt|^2 and |lt_new|^2 per block
+__global__ __launch_bounds__(256) void k_adj_update(Params p, double *lt, const double *y, const double *g, int nblk) {
+    __shared__ double sh[8];
+    double s[2] = {0.0, 0.0};
+    const size_t n = (size_t)p.nc * 2 * p.nvp;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)nblk * blockDim.x) {
+        const double nw = y[t] + p.fbar[t] + g[t];
+        const double d = nw - lt[t];
+        s[0] += d * d;
+        s[1] += nw * nw;
+        lt[t] = nw;
+    }
+    block_sum_store<2>(s, sh, p.red + 2 * blockIdx.x);
+}
+
+__global__ void k_adj_update_final(Params p, int nblk, double *out) {
+    __shared__ double sh[8];
+    double s[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) { s[0] += p.red[2 * i]; s[1] += p.red[2 * i + 1]; }
+    block_sum_store<2>(s, sh, out);
+}
+
+// srec base of the adjoint sweeps: Omega/dt_imp + c of the current record (no predictor)
+__global__ __launch_bounds__(256) void k_adj_diag(Params p) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= p.nc) return;
+    const double cc = 2.0 * p.area[c] / (2.0 * p.rec[c].tau + p.dt);
+    double *row = p.srec + (size_t)p.hp_pos[c] * SR_N;
+    row[10] = cc;
+    row[11] = p.area[c] / p.dtimp[c] + cc;
+}
+
+// copy between the canonical [2][nc][nv] layout and the device layout
+__global__ void k_to_dev(Params p, const double *src, double *dst) {
+    const size_t n = (size_t)p.nc * 2 * p.nvp;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(t / (2 * (size_t)p.nvp)), r = (int)(t % (2 * (size_t)p.nvp));
+        const int s = r / p.nvp, v = r % p.nvp;
+        dst[t] = v < p.nv ? src[((size_t)s * p.nc + c) * p.nv + v] : 0.0;
+    }
+}
+
+__global__ void k_from_dev(Params p, const double *src, double *dst, double scale) {
+    const size_t n = (size_t)p.nc * p.nv;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < 2 * n; t += (size_t)gridDim.x * blockDim.x) {
+        const int s = (int)(t / n);
+        const size_t r = t % n;
+        const int c = (int)(r / p.nv), v = (int)(r % p.nv);
+        dst[t] = scale * src[((size_t)c * 2 + s) * p.nvp + v];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
 #define DISPATCH_S(fp32, ...) \
@@ -1273,18 +1810,18 @@ SweepShape sweep_shape(int ni, int nj, int nv, size_t s_bytes) {
 hipError_t launch_sweep(const Params &p, bool fp32, bool upper, const SweepShape &sh, hipStream_t st) {
     const dim3 g((p.nv + sh.vb - 1) / sh.vb);
     DISPATCH_S(fp32, {
-        const void *fn = !upper ? (p.model == 1 ? (const void *)k_sweep<S, true, false> : (const void *)k_sweep<S, false, false>)
-                                : (p.model == 1 ? (const void *)k_sweep<S, true, true> : (const void *)k_sweep<S, false, true>);
+        const void *fn = !upper ? (p.model == 1 ? (const void *)k_sweep<S, true, false, false> : (const void *)k_sweep<S, false, false, false>)
+                                : (p.model == 1 ? (const void *)k_sweep<S, true, true, false> : (const void *)k_sweep<S, false, true, false>);
         if (sh.lds > 64 * 1024) {
             hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
             if (e != hipSuccess) return e;
         }
         if (!upper) {
-            if (p.model == 1) hipLaunchKernelGGL((k_sweep<S, true, false>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
-            else hipLaunchKernelGGL((k_sweep<S, false, false>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
+            if (p.model == 1) hipLaunchKernelGGL((k_sweep<S, true, false, false>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
+            else hipLaunchKernelGGL((k_sweep<S, false, false, false>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
         } else {
-            if (p.model == 1) hipLaunchKernelGGL((k_sweep<S, true, true>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
-            else hipLaunchKernelGGL((k_sweep<S, false, true>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
+            if (p.model == 1) hipLaunchKernelGGL((k_sweep<S, true, true, false>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
+            else hipLaunchKernelGGL((k_sweep<S, false, true, false>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
         }
     });
     return hipGetLastError();
@@ -1325,6 +1862,90 @@ hipError_t launch_fill_uniform(const Params &p, bool fp32, const double *eq, hip
 
 hipError_t launch_fields(const Params &p, double *out, hipStream_t st) {
     hipLaunchKernelGGL(k_fields, dim3((p.nc + 255) / 256), dim3(256), 0, st, p, out);
+    return hipGetLastError();
+}
+
+// ---- sensitivities ---------------------------------------------------------------------
+hipError_t launch_adj_face(const Params &p, int obj, hipStream_t st) {
+    const dim3 g((p.nf + 3) / 4);
+    if (obj == 0) hipLaunchKernelGGL((k_adj_face<0>), g, dim3(256), 0, st, p);
+    else if (obj == 1) hipLaunchKernelGGL((k_adj_face<1>), g, dim3(256), 0, st, p);
+    else hipLaunchKernelGGL((k_adj_face<-1>), g, dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_gather(const Params &p, int obj, hipStream_t st) {
+    if (obj == 0) hipLaunchKernelGGL((k_adj_gather<0>), dim3(p.nc), dim3(256), 0, st, p);
+    else if (obj == 1) hipLaunchKernelGGL((k_adj_gather<1>), dim3(p.nc), dim3(256), 0, st, p);
+    else hipLaunchKernelGGL((k_adj_gather<-1>), dim3(p.nc), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_rec_jac(const Params &p, hipStream_t st) {
+    hipLaunchKernelGGL(k_rec_jac, dim3((p.nc + 3) / 4), dim3(256), 0, st, p, 0);
+    hipLaunchKernelGGL(k_rec_jac, dim3((p.nf + 3) / 4), dim3(256), 0, st, p, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_cell(const Params &p, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_cell, dim3(p.nc), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_theta(const Params &p, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_theta, dim3(1), dim3(1024), 0, st, p, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_sweep(const Params &p, bool upper, const SweepShape &sh, hipStream_t st) {
+    const dim3 g((p.nv + sh.vb - 1) / sh.vb);
+    const void *fn = upper ? (const void *)k_sweep<double, false, true, true> : (const void *)k_sweep<double, false, false, true>;
+    if (sh.lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
+        if (e != hipSuccess) return e;
+    }
+    if (upper) hipLaunchKernelGGL((k_sweep<double, false, true, true>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
+    else hipLaunchKernelGGL((k_sweep<double, false, false, true>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_diag(const Params &p, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_diag, dim3((p.nc + 255) / 256), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+static int red_blocks(const Params &p) {
+    const size_t n = (size_t)p.nc * 2 * p.nvp;
+    size_t b = (n + 255) / 256;
+    return (int)(b < RED_N / 2 ? b : RED_N / 2);
+}
+
+hipError_t launch_dot(const Params &p, const double *a, const double *b, double scale_a, double *out, hipStream_t st) {
+    const int nb = red_blocks(p);
+    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(256), 0, st, p, a, b, scale_a, nb);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, p, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_project(const Params &p, const double *lt, double *y, const double *dot, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_project, dim3(2048), dim3(256), 0, st, p, lt, y, dot);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_update(const Params &p, double *lt, const double *y, const double *g, double *out, hipStream_t st) {
+    const int nb = red_blocks(p);
+    hipLaunchKernelGGL(k_adj_update, dim3(nb), dim3(256), 0, st, p, lt, y, g, nb);
+    hipLaunchKernelGGL(k_adj_update_final, dim3(1), dim3(256), 0, st, p, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_dev(const Params &p, const double *src, double *dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_dev, dim3(2048), dim3(256), 0, st, p, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_from_dev(const Params &p, const double *src, double *dst, double scale, hipStream_t st) {
+    hipLaunchKernelGGL(k_from_dev, dim3(2048), dim3(256), 0, st, p, src, dst, scale);
     return hipGetLastError();
 }
 

@@ -37,4 +37,19 @@ hipError_t launch_unpack(const Params &p, bool fp32, const double *src, int sp, 
 hipError_t launch_fill_uniform(const Params &p, bool fp32, const double *eq, hipStream_t st);
 hipError_t launch_fields(const Params &p, double *out, hipStream_t st);
 
+// sensitivities (FP64 state, BGK, no limiter); obj: -1 none, 0 lid x-momentum flux,
+// 1 wall heat flux
+hipError_t launch_rec_jac(const Params &p, hipStream_t st);
+hipError_t launch_adj_face(const Params &p, int obj, hipStream_t st);
+hipError_t launch_adj_gather(const Params &p, int obj, hipStream_t st);
+hipError_t launch_adj_cell(const Params &p, hipStream_t st);
+hipError_t launch_adj_theta(const Params &p, double *out, hipStream_t st);
+hipError_t launch_adj_sweep(const Params &p, bool upper, const SweepShape &sh, hipStream_t st);
+hipError_t launch_adj_diag(const Params &p, hipStream_t st);
+hipError_t launch_dot(const Params &p, const double *a, const double *b, double scale_a, double *out, hipStream_t st);
+hipError_t launch_adj_project(const Params &p, const double *lt, double *y, const double *dot, hipStream_t st);
+hipError_t launch_adj_update(const Params &p, double *lt, const double *y, const double *g, double *out, hipStream_t st);
+hipError_t launch_to_dev(const Params &p, const double *src, double *dst, hipStream_t st);
+hipError_t launch_from_dev(const Params &p, const double *src, double *dst, double scale, hipStream_t st);
+
 }  // namespace idugks

@@ -114,6 +114,38 @@ class Solver:
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(2, self.nc, self.nv)
         self._check(self._lib.idugks_set_state(self._h, C.c_void_p(f.ctypes.data), 1))
 
+    # sensitivities (BGK, no limiter, FP64): theta = (lid speed, wall temperature, Kn)
+    def vjp(self, lam):
+        """(lam^T dR/df, lam^T dR/dtheta) at the current state; lam [2, nc, nv]."""
+        lam = np.ascontiguousarray(lam, dtype=np.float64).reshape(2, self.nc, self.nv)
+        fb = np.zeros((2, self.nc, self.nv))
+        tb = np.zeros(3)
+        self._check(self._lib.idugks_vjp(self._h, C.c_void_p(lam.ctypes.data),
+                                         C.c_void_p(fb.ctypes.data), _dp(tb), 1))
+        return fb, tb
+
+    def objective(self, which):
+        """(J, dJ/df, dJ/dtheta at fixed f); which 0: lid x-momentum flux, 1: wall heat flux."""
+        J = np.zeros(1)
+        g = np.zeros((2, self.nc, self.nv))
+        t = np.zeros(3)
+        self._check(self._lib.idugks_objective(self._h, which, _dp(J), C.c_void_p(g.ctypes.data),
+                                               _dp(t), 1))
+        return float(J[0]), g, t
+
+    def adjoint(self, which, tol=1e-10, max_iter=10000, want_lam=False):
+        """Steady sensitivity at the current (converged) state:
+        (J, dJ/dtheta, iterations, last relative change, multipliers or None)."""
+        J = np.zeros(1)
+        grad = np.zeros(3)
+        it = C.c_int32(0)
+        res = np.zeros(1)
+        lam = np.zeros((2, self.nc, self.nv)) if want_lam else None
+        self._check(self._lib.idugks_adjoint(self._h, which, tol, max_iter, _dp(J), _dp(grad),
+                                             C.byref(it), _dp(res),
+                                             C.c_void_p(lam.ctypes.data) if want_lam else None, 1))
+        return float(J[0]), grad, it.value, float(res[0]), lam
+
     def kernel_names(self):
         n = self._lib.idugks_num_kernels()
         return [self._lib.idugks_kernel_name(k).decode() for k in range(n)]
