@@ -175,7 +175,7 @@ idugks_status validate(const idugks_config *c) {
     if (c->struct_size != sizeof(idugks_config)) return fail(IDUGKS_E_INVALID, "struct_size mismatch");
     if (c->ni < 1 || c->nj < 1) return fail(IDUGKS_E_INVALID, "mesh needs ni, nj >= 1");
     if (std::min(c->ni, c->nj) > 280 || macro_shape(c->ni, c->nj).lds > 150 * 1024 ||
-        macro_shape(c->ni, c->nj).threads > 768 || sweep_shape(c->ni, c->nj, 1, 8).vb == 0)
+        macro_shape(c->ni, c->nj).threads > 1024 || sweep_shape(c->ni, c->nj, 1, 8).vb == 0)
         return fail(IDUGKS_E_INVALID, "mesh too large for the LDS-resident sweep fronts");
     if (!c->xn || !c->yn) return fail(IDUGKS_E_INVALID, "missing node coordinates");
     if (c->nvx < 2 || c->nvy < 2) return fail(IDUGKS_E_INVALID, "need nv >= 2 per direction");
@@ -504,7 +504,7 @@ idugks_status build(const idugks_config *c, Built &b) {
         for (int s = 0; s < 4; ++s) {
             const CellSide &q = b.cs[(size_t)4 * cidx + s];
             double *g = &b.sgeo[(size_t)b.hp_pos[cidx] * SG_N];
-            g[s] = q.nx; g[4 + s] = q.ny; g[8 + s] = q.S;
+            g[s] = q.nx * q.S; g[4 + s] = q.ny * q.S; g[8 + s] = q.S;  // xi.n S = xi nxS + eta nyS
             int code = 0;
             if (q.type != FT_SELF) {
                 code |= SG_DIAG;

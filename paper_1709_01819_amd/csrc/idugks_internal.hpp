@@ -62,7 +62,10 @@ struct Rec {
     double rw;               // wall faces: density of the reflected Maxwellian
 };
 
-constexpr int SG_N = 16, SR_N = 12, MH_N = 57;
+constexpr int SG_N = 16, SR_N = 12;
+// macro row: M_W (dW* after the forward sweep) [4], 1/D, packed side codes, then per side
+// nx, ny, S, lambda_j, W_j [4]
+constexpr int MH_SIDE = 6, MH_SN = 8, MH_N = MH_SIDE + 4 * MH_SN, MH_CODE_BITS = 5;
 
 // Static per-cell geometry of the micro and macro sweeps (built on the host).
 // code bits: SG_DIAG the side counts in the diagonal (not self-periodic), SG_LOWER /
@@ -99,11 +102,10 @@ struct Params {
     // that the cells of one hyperplane are contiguous and can be staged into LDS at once
     const int *hp_off;       // [nh+1] first position of each hyperplane
     const int *hp_pos;       // [nc] position of each cell
-    const double *sgeo;      // [nc][SG_N] nx[4], ny[4], S[4], code[4] (static)
+    const double *sgeo;      // [nc][SG_N] nx S[4], ny S[4], S[4], code[4] (static)
     double *srec;            // [nc][SR_N] U, V, c0, c1, c2c, c3, kqx, kqy, iRT, KRT, cst, base
     double *sdrho;           // [nc][4] wall ghost density increment per cell side
-    double *mh;              // [nc][MH_N] macro: M_W, diagonal, codes, per side nx, ny, S,
-                             //                lambda_j, F_n(W_j), W_j
+    double *mh;              // [nc][MH_N] macro rows in hyperplane order
     // sensitivities (BGK, no limiter, FP64 state; null otherwise)
     double Kn, wall_u[4], wall_v[4];
     const double *lam;       // [nc][2][nvp] adjoint weights the VJP is taken with

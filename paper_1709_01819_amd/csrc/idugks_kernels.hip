@@ -610,20 +610,20 @@ DEV void euler_flux_n(const double W[4], double nx, double ny, double ik2, doubl
 
 // Everything of Eq. 30-31 that does not depend on the increments, all cells in parallel:
 // implicit time step, inverse diagonal (a wall face carries its whole lambda S: mirrored
-// ghost), and per cell side with a neighbour j the neighbour's lambda_j and F_n(W_j).
-// Rows are stored in i+j hyperplane order: M_W, 1/D, codes, per side nx, ny, S, lambda_j,
-// F_n(W_j), W_j.
+// ghost), and per cell side with a neighbour j the neighbour's lambda_j and W_j (the
+// sweep recomputes F_n(W_j): a shorter row stages faster).  Rows are stored in i+j
+// hyperplane order: M_W, 1/D, packed side codes, per side nx, ny, S, lambda_j, W_j.
 __global__ __launch_bounds__(256) void k_macro_prep(Params p) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= p.nc) return;
     const CellSide *cs = p.cs + 4 * c;
     double *m = p.mh + (size_t)p.hp_pos[c] * MH_N;
     const double U = p.rec[c].U, V = p.rec[c].V, C = sqrt(p.gam * p.rec[c].RT);
-    const double ik2 = 1.0 / (p.K + 2);
     double ls = 0.0, lw = 0.0;
+    int codes = 0;
     for (int s = 0; s < 4; ++s) {
-        m[5 + s] = p.sgeo[(size_t)p.hp_pos[c] * SG_N + 12 + s];  // code
-        double *ms = m + 9 + 12 * s;
+        codes |= (int)p.sgeo[(size_t)p.hp_pos[c] * SG_N + 12 + s] << (MH_CODE_BITS * s);
+        double *ms = m + MH_SIDE + MH_SN * s;
         ms[0] = cs[s].nx; ms[1] = cs[s].ny; ms[2] = cs[s].S;
         if (cs[s].type == FT_SELF) continue;
         const double l = (fabs(U * cs[s].nx + V * cs[s].ny) + C) * cs[s].S;
@@ -633,17 +633,13 @@ __global__ __launch_bounds__(256) void k_macro_prep(Params p) {
         if (j < 0) continue;
         const double *Wj = p.Wc + (size_t)j * 4;
         ms[3] = fabs((Wj[1] * cs[s].nx + Wj[2] * cs[s].ny) / Wj[0]) + sqrt(p.gam * p.rec[j].RT);
-        double F0[4];
-        euler_flux_n(Wj, cs[s].nx, cs[s].ny, ik2, F0);
-        for (int a = 0; a < 4; ++a) {
-            ms[4 + a] = F0[a];
-            ms[8 + a] = Wj[a];
-        }
+        for (int a = 0; a < 4; ++a) ms[4 + a] = Wj[a];
     }
     const double dti = p.cfl_imp * p.area[c] / ls;
     p.dtimp[c] = dti;
     for (int a = 0; a < 4; ++a) m[a] = p.MW[(size_t)c * 4 + a];
     m[4] = 1.0 / (p.area[c] / dti + 0.5 * ls + 0.5 * lw);
+    m[5] = (double)codes;
 }
 
 // All data exchanged inside the sweep kernels goes through LDS, so their barrier orders
@@ -661,32 +657,40 @@ DEV void hp_bounds(int s, int ni, int nj, int &lo, int &hi) {
 
 // Both sweep kernels split their block into compute waves and staging waves.  The
 // staging waves copy the per-cell rows of hyperplane t+1 (contiguous in hyperplane order)
-// from HBM into one of two LDS buffers during step t, having issued the loads SDEPTH (or
-// MDEPTH) steps earlier; the compute waves read only LDS for per-cell data.  A wave's loads complete in
-// order, so keeping these copies out of the compute waves lets the compute waves' own
-// prefetches run ahead without waiting for them.
-constexpr int SPW = 16;    // staged values per staging lane and hyperplane (macro sweep)
+// from HBM into one of two LDS buffers during step t, having issued the loads a fixed
+// number of steps earlier (SDEPTH in the micro sweeps, MD in the macro sweep); the compute
+// waves read only LDS for per-cell data.  A wave's loads complete in order, so keeping
+// these copies out of the compute waves lets the compute waves' own prefetches run ahead
+// without waiting for them.
 constexpr int SDEPTH = 4;  // hyperplanes of staging loads in flight (micro sweeps)
-constexpr int MDEPTH = 3;  // the same for the macro sweep (its rows are longer)
+static_assert(SG_WALL < 1 << MH_CODE_BITS, "side codes must fit their field of the macro row");
+// a staging wave reads up to 64 x 16 values past the first row of a hyperplane, the last of
+// which starts at row nc - 1: the min(ni, nj) + 32 spare rows of the staged arrays cover it
+static_assert(33 * MH_N >= 64 * 16, "macro staging reads past the spare rows");
 
-template <class T>
-DEV void stage_store(const T (&reg)[SPW], T *dst, int n, int sl, int nsl) {
+template <int N>
+DEV void stage_store(const double (&reg)[N], double *dst, int n, int sl, int nsl) {
 #pragma unroll
-    for (int q = 0; q < SPW; ++q) {
+    for (int q = 0; q < N; ++q) {
         const int e = sl + q * nsl;
         if (e < n) dst[e] = reg[q];
     }
 }
 
 // Macro LU-SGS sweeps (Eq. 29-31) over i+j hyperplanes in one block.  Waves below nct
-// compute, one lane per cell of a hyperplane:
+// compute, LPC lanes per cell of a hyperplane, each taking the sides q, q + LPC, ...:
 //   r -= 1/2 S (F_n(W_j + dW_j) - F_n(W_j) - lambda_j dW_j)
-// over the lower (forward) or upper (backward) neighbours.  LDS holds the previous
-// hyperplane's increments (fronts), those of the cells next to a periodic seam (wI:
-// column i = 0 / ni-1, wJ: row j = 0 / nj-1, the only non-adjacent neighbours) and the
-// staged rows of the current and the next hyperplane.  The forward sweep writes dW* into
-// the first four values of each cell's row, which the backward sweep stages back.
-__global__ __launch_bounds__(768) void k_macro_sweep(Params p, int nct) {
+// over the lower (forward) or upper (backward) neighbours; the lanes of a cell sum their
+// parts in a fixed order by shuffles and lane q finishes the components q, q + LPC, ....
+// LDS holds the previous hyperplane's increments (fronts), those of the cells next to a
+// periodic seam (wI: column i = 0 / ni-1, wJ: row j = 0 / nj-1, the only non-adjacent
+// neighbours) and the staged rows of the current and the next hyperplane.  The forward
+// sweep writes dW* into the first four values of each cell's row, which the backward
+// sweep stages back.  The staging waves keep MD hyperplanes of SPWM values per lane in
+// flight: the row is short enough that one CU's load latency, not its bandwidth, bounds
+// the step, so the depth matters more than the lane count.
+template <int LPC, int SPWM, int MD>
+__global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
     extern __shared__ double lds[];
     const int ni = p.ni, nj = p.nj, nh = ni + nj - 1, L = ni < nj ? ni : nj;
     double *fr0 = lds, *fr1 = lds + 4 * ni, *wI = lds + 8 * ni, *wJ = wI + 4 * nj;
@@ -699,14 +703,14 @@ __global__ __launch_bounds__(768) void k_macro_sweep(Params p, int nct) {
     // hyperplane in each direction, plus the block-wide one between the directions.
     if ((int)threadIdx.x >= nct) {
         const int sl = (int)threadIdx.x - nct, nsl = (int)blockDim.x - nct;
-        // register set k holds the row values of a hyperplane t with t % MDEPTH == k; the
-        // loads of hyperplane t+1 are issued MDEPTH steps before it is staged
-        double reg[MDEPTH][SPW];
+        // register set k holds the row values of a hyperplane t with t % MD == k; the
+        // loads of hyperplane t+1 are issued MD steps before it is staged
+        double reg[MD][SPWM];
         // rows past the hyperplane are read (spare rows at the end of mh) but never staged
-        auto issue = [&](double (&rg)[SPW], int h) {
+        auto issue = [&](double (&rg)[SPWM], int h) {
             const double *src = p.mh + (size_t)hpo[h] * MH_N + sl;
 #pragma unroll
-            for (int q = 0; q < SPW; ++q) rg[q] = src[q * nsl];
+            for (int q = 0; q < SPWM; ++q) rg[q] = src[q * nsl];
         };
         for (int dir = 0; dir < 2; ++dir) {
             const bool upper = dir == 1;
@@ -716,23 +720,23 @@ __global__ __launch_bounds__(768) void k_macro_sweep(Params p, int nct) {
             issue(reg[0], hcl(0));
             stage_store(reg[0], st0, cells(0) * MH_N, sl, nsl);
 #pragma unroll
-            for (int d = 1; d <= MDEPTH; ++d) issue(reg[d % MDEPTH], hcl(d));
+            for (int d = 1; d <= MD; ++d) issue(reg[d % MD], hcl(d));
             lds_barrier();
             int t0 = 0;
-            for (; t0 + MDEPTH <= nh; t0 += MDEPTH) {
+            for (; t0 + MD <= nh; t0 += MD) {
 #pragma unroll
-                for (int d = 0; d < MDEPTH; ++d) {
+                for (int d = 0; d < MD; ++d) {
                     const int t = t0 + d;
-                    if (t + 1 < nh) stage_store(reg[(d + 1) % MDEPTH], (t + 1) & 1 ? st1 : st0, cells(t + 1) * MH_N, sl, nsl);
-                    issue(reg[(d + 1) % MDEPTH], hcl(t + 1 + MDEPTH));
+                    if (t + 1 < nh) stage_store(reg[(d + 1) % MD], (t + 1) & 1 ? st1 : st0, cells(t + 1) * MH_N, sl, nsl);
+                    issue(reg[(d + 1) % MD], hcl(t + 1 + MD));
                     lds_barrier();
                 }
             }
 #pragma unroll
-            for (int d = 0; d < MDEPTH - 1; ++d) {
+            for (int d = 0; d < MD - 1; ++d) {
                 const int t = t0 + d;
                 if (t < nh) {
-                    if (t + 1 < nh) stage_store(reg[(d + 1) % MDEPTH], (t + 1) & 1 ? st1 : st0, cells(t + 1) * MH_N, sl, nsl);
+                    if (t + 1 < nh) stage_store(reg[(d + 1) % MD], (t + 1) & 1 ? st1 : st0, cells(t + 1) * MH_N, sl, nsl);
                     lds_barrier();
                 }
             }
@@ -740,6 +744,8 @@ __global__ __launch_bounds__(768) void k_macro_sweep(Params p, int nct) {
         }
         return;
     }
+    constexpr int NS = 4 / LPC;  // sides (and components) per lane
+    const int k = (int)threadIdx.x / LPC, q = (int)threadIdx.x % LPC;
     for (int dir = 0; dir < 2; ++dir) {
         const bool upper = dir == 1;
         const int need = upper ? SG_UPPER : SG_LOWER;
@@ -748,56 +754,64 @@ __global__ __launch_bounds__(768) void k_macro_sweep(Params p, int nct) {
             const int s = upper ? nh - 1 - t : t;
             int lo, hi;
             hp_bounds(s, ni, nj, lo, hi);
-            const int k = threadIdx.x, i = lo + k;
-            if (i <= hi) {
-                const int j = s - i, c = i + j * ni;
-                const double *m = (t & 1 ? st1 : st0) + (size_t)k * MH_N;
-                // the whole staged row in one batch of LDS reads (no read waits on a write)
-                double mr[5], ms[4][12];
-                int code[4];
+            const int i = lo + k;
+            const bool live = i <= hi;
+            const int j = s - i;
+            const double *m = (t & 1 ? st1 : st0) + (size_t)(live ? k : 0) * MH_N;
+            // this lane's side values, then the neighbours' increments, in two LDS batches
+            const int codes = (int)m[5];
+            double ms[NS][MH_SN], mr[NS];
 #pragma unroll
-                for (int a = 0; a < 5; ++a) mr[a] = m[a];
+            for (int u = 0; u < NS; ++u) {
+                mr[u] = m[q + u * LPC];
 #pragma unroll
-                for (int sd = 0; sd < 4; ++sd) {
-                    code[sd] = (int)m[5 + sd];
+                for (int e = 0; e < MH_SN; ++e) ms[u][e] = m[MH_SIDE + MH_SN * (q + u * LPC) + e];
+            }
+            const double iD = m[4];
+            bool cpl[NS];
+            double dW[NS][4];
 #pragma unroll
-                    for (int e = 0; e < 12; ++e) ms[sd][e] = m[9 + 12 * sd + e];
-                }
-                // the neighbours' increments, again in one batch (unused sides read fr0)
-                double dW[4][4];
+            for (int u = 0; u < NS; ++u) {
+                const int sd = q + u * LPC, code = (codes >> (MH_CODE_BITS * sd)) & ((1 << MH_CODE_BITS) - 1);
+                cpl[u] = live && (code & need);
+                const int fi = upper ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
+                const double *src = !cpl[u] ? fr0 : (code & SG_ADJ) ? fr0 + 4 * fi : (sd < 2 ? wI + 4 * j : wJ + 4 * i);
 #pragma unroll
-                for (int sd = 0; sd < 4; ++sd) {
-                    const int fi = upper ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
-                    const double *src = !(code[sd] & need) ? fr0
-                                        : (code[sd] & SG_ADJ) ? fr0 + 4 * fi
-                                        : (sd < 2 ? wI + 4 * j : wJ + 4 * i);
+                for (int a = 0; a < 4; ++a) dW[u][a] = src[a];
+            }
+            double r[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) dW[sd][a] = src[a];
-                }
-                double r[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int u = 0; u < NS; ++u) {
+                if (!cpl[u]) continue;
+                double Wn[4], F0[4], F1[4];
 #pragma unroll
-                for (int sd = 0; sd < 4; ++sd) {
-                    if (!(code[sd] & need)) continue;
-                    double Wn[4], F1[4];
+                for (int a = 0; a < 4; ++a) Wn[a] = ms[u][4 + a] + dW[u][a];
+                euler_flux_n(&ms[u][4], ms[u][0], ms[u][1], ik2, F0);
+                euler_flux_n(Wn, ms[u][0], ms[u][1], ik2, F1);
+                const double hS = 0.5 * ms[u][2];
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) Wn[a] = ms[sd][8 + a] + dW[sd][a];
-                    euler_flux_n(Wn, ms[sd][0], ms[sd][1], ik2, F1);
-                    const double hS = 0.5 * ms[sd][2];
+                for (int a = 0; a < 4; ++a) r[a] += hS * (F1[a] - F0[a] - ms[u][3] * dW[u][a]);
+            }
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) r[a] += hS * (F1[a] - ms[sd][4 + a] - ms[sd][3] * dW[sd][a]);
-                }
-                double d[4];
+            for (int a = 0; a < 4; ++a) {
+                if (LPC >= 2) r[a] += __shfl_xor(r[a], 1, 64);
+                if (LPC >= 4) r[a] += __shfl_xor(r[a], 2, 64);
+            }
+            if (live) {
 #pragma unroll
-                for (int a = 0; a < 4; ++a)  // forward: dW* = (M_W - r)/D; backward: dW = dW* - r/D
-                    d[a] = upper ? mr[a] - r[a] * mr[4] : (mr[a] - r[a]) * mr[4];
-                double *row = p.mh + (size_t)(hpo[s] + k) * MH_N;
+                for (int u = 0; u < NS; ++u) {
+                    const int a = q + u * LPC;
+                    double ra = r[0];
 #pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    if (upper) p.dW[(size_t)c * 4 + a] = d[a];
-                    else row[a] = d[a];
-                    fr1[4 * i + a] = d[a];
-                    if (i == (upper ? ni - 1 : 0)) wI[4 * j + a] = d[a];
-                    if (j == (upper ? nj - 1 : 0)) wJ[4 * i + a] = d[a];
+                    for (int b = 1; b < 4; ++b)
+                        if (a == b) ra = r[b];
+                    // forward dW* = (M_W - r)/D, backward dW = dW* - r/D
+                    const double d = upper ? mr[u] - ra * iD : (mr[u] - ra) * iD;
+                    if (upper) p.dW[(size_t)(i + j * ni) * 4 + a] = d;
+                    else p.mh[(size_t)(hpo[s] + k) * MH_N + a] = d;
+                    fr1[4 * i + a] = d;
+                    if (i == (upper ? ni - 1 : 0)) wI[4 * j + a] = d;
+                    if (j == (upper ? nj - 1 : 0)) wJ[4 * i + a] = d;
                 }
             }
             lds_barrier();
@@ -818,8 +832,8 @@ __global__ __launch_bounds__(768) void k_macro_sweep(Params p, int nct) {
 // compute lane keeps the HBM loads of its next RING items (one per hyperplane) in flight
 // in fixed registers.
 // ---------------------------------------------------------------------------------------
-constexpr int STG = 28;  // staged values per cell: record (12), nx ny S (12), codes (4)
-constexpr int RING = 4;
+constexpr int STG = 24;  // staged values per cell: record (12), nx S (4), ny S (4), codes (4)
+constexpr int RING = 3;
 
 template <class S>
 struct SweepItem {
@@ -876,7 +890,8 @@ struct StageCol {
         stride = 0;
         zero = true;
         if (k0 >= kp) return;  // idle lane
-        if (r >= SR_N) { base = p.sgeo + (r - SR_N); stride = SG_N; zero = false; }
+        if (r >= SR_N + 8) { base = p.sgeo + 12 + (r - SR_N - 8); stride = SG_N; zero = false; }
+        else if (r >= SR_N) { base = p.sgeo + (r - SR_N); stride = SG_N; zero = false; }
         else if (!UPPER || r >= 10) { base = p.srec + r; stride = SR_N; zero = false; }
         else if (r < 4) { base = p.sdrho + r; stride = 4; zero = false; }
     }
@@ -977,56 +992,65 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
         if (cur.i >= 0) {
             const int s = hp(t), i = cur.i, j = s - i;
             const T *m = ((t & 1) ? st1 : st0) + slot * STG;
-            T D = m[11], sG, sH;
+            // the staged row and the coupled neighbours' increments in two batches of LDS
+            // reads, so that no read waits behind a branch
+            T mr[STG];
+#pragma unroll
+            for (int e = 0; e < STG; ++e) mr[e] = m[e];
+            int code[4];
+            T fg[4], fh[4];
+#pragma unroll
+            for (int sd = 0; sd < 4; ++sd) {
+                code[sd] = (int)mr[SR_N + 8 + sd];
+                const int fi = UPPER ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
+                // fronts of this step: f0 (adjacent hyperplane) or wI / wJ; uncoupled sides
+                // read f0[vl] and discard it
+                const T *fp = !(code[sd] & need) ? f0
+                              : (code[sd] & SG_ADJ) ? f0 + fi * vb
+                              : (sd < 2 ? wI + j * vb : wJ + i * vb);
+                fg[sd] = fp[vl];
+                fh[sd] = fp[FR + vl];
+            }
+            T D = mr[11], sG, sH;
             if (!UPPER && ADJ) {
                 sG = cur.aG;
                 sH = cur.aH;
             } else if (!UPPER) {
                 RecT<T> r;
-                r.U = m[0]; r.V = m[1]; r.c0 = m[2]; r.c1 = m[3]; r.c2c = m[4]; r.c3 = m[5];
-                r.kqx = m[6]; r.kqy = m[7]; r.iRT = m[8]; r.KRT = m[9];
+                r.U = mr[0]; r.V = mr[1]; r.c0 = mr[2]; r.c1 = mr[3]; r.c2c = mr[4]; r.c3 = mr[5];
+                r.kqx = mr[6]; r.kqy = mr[7]; r.iRT = mr[8]; r.KRT = mr[9];
                 T eG, eH;
                 eq_eval<T, SHAK>(r, x, y, cur.e1 * cur.e2, eG, eH);
-                sG = cur.aG - m[10] * (sc * cur.bG - eG);
-                sH = cur.aH - m[10] * (sc * cur.bH - eH);
+                sG = cur.aG - mr[10] * (sc * cur.bG - eG);
+                sH = cur.aH - mr[10] * (sc * cur.bH - eH);
             } else {
                 sG = sH = T(0);
             }
 #pragma unroll
             for (int sd = 0; sd < 4; ++sd) {
-                const int code = (int)m[SR_N + 12 + sd];
-                if (!(code & SG_DIAG)) continue;
-                const T un = x * m[SR_N + sd] + y * m[SR_N + 4 + sd], Sk = m[SR_N + 8 + sd];
+                if (!(code[sd] & SG_DIAG)) continue;
+                const T unS = x * mr[SR_N + sd] + y * mr[SR_N + 4 + sd];  // (xi.n) S
                 if (ADJ) {
-                    if (un > T(0)) {
-                        D += un * Sk;
-                        if (code & need) {
-                            const int fi = UPPER ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
-                            const T *fp = (code & SG_ADJ) ? f0 + fi * vb
-                                                          : (sd < 2 ? wI + j * vb : wJ + i * vb);
-                            const T cf = un * Sk;
-                            sG += cf * fp[vl];
-                            sH += cf * fp[FR + vl];
+                    if (unS > T(0)) {
+                        D += unS;
+                        if (code[sd] & need) {
+                            sG += unS * fg[sd];
+                            sH += unS * fh[sd];
                         }
                     }
-                } else if (un > T(0)) {
-                    D += un * Sk;
-                } else if (un < T(0)) {
-                    if (code & need) {
-                        const int fi = UPPER ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
-                        // fronts of this step: f0 (adjacent hyperplane) or wI / wJ
-                        const T *fp = (code & SG_ADJ) ? f0 + fi * vb
-                                                      : (sd < 2 ? wI + j * vb : wJ + i * vb);
-                        const T cf = -un * Sk;
-                        sG += cf * fp[vl];
-                        sH += cf * fp[FR + vl];
-                    } else if (UPPER && (code & SG_WALL)) {
-                        const int ws = (code >> 8) & 3;
+                } else if (unS > T(0)) {
+                    D += unS;
+                } else if (unS < T(0)) {
+                    if (code[sd] & need) {
+                        sG -= unS * fg[sd];
+                        sH -= unS * fh[sd];
+                    } else if (UPPER && (code[sd] & SG_WALL)) {
+                        const int ws = (code[sd] >> 8) & 3;
                         T g = T(0), kk = T(0);
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
                             if (q == ws) { g = gwv[q]; kk = kw[q]; }
-                        const T gw = g * m[sd] * (-un * Sk);
+                        const T gw = -g * mr[sd] * unS;
                         sG += gw;
                         sH += gw * kk;
                     }
@@ -1759,14 +1783,47 @@ hipError_t launch_flux(const Params &p, bool fp32, hipStream_t st) {
 
 static int round64(int n) { return (n + 63) / 64 * 64; }
 
+// Lanes per cell: 4 if they leave room in 1024 lanes for the staging waves at 16 values
+// per lane, else 2; then the fewest values per staging lane (the deepest prefetch: 32
+// registers hold MD x SPWM values) that still fit.  Meshes too wide for that are
+// rejected at init (their LDS would not fit either).
 MacroShape macro_shape(int ni, int nj) {
     const int L = ni < nj ? ni : nj, nh = ni + nj - 1;
-    MacroShape m;
-    m.nct = round64(L);
-    const int nsw = (L * MH_N + 64 * SPW - 1) / (64 * SPW);
-    m.threads = m.nct + 64 * nsw;
+    auto waves = [&](int spw) { return (L * MH_N + 64 * spw - 1) / (64 * spw); };
+    MacroShape m{};
+    for (int lpc = 4; lpc >= 2; lpc /= 2) {
+        m.lpc = lpc;
+        m.nct = round64(lpc * L);
+        if (m.nct + 64 * waves(16) <= 1024) break;
+    }
+    for (int spw = 4; spw <= 16; spw *= 2) {
+        m.spw = spw;
+        m.threads = m.nct + 64 * waves(spw);
+        if (m.threads <= 1024) break;
+    }
     m.lds = (size_t)(12 * ni + 4 * nj + 2 * L * MH_N) * sizeof(double) + (size_t)(nh + 1) * sizeof(int);
     return m;
+}
+
+template <int LPC, int SPWM>
+static hipError_t launch_macro_t(const Params &p, const MacroShape &m, hipStream_t st) {
+    constexpr int MD = 32 / SPWM;
+    const void *fn = (const void *)k_macro_sweep<LPC, SPWM, MD>;
+    if (m.lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)m.lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_macro_sweep<LPC, SPWM, MD>), dim3(1), dim3(m.threads), m.lds, st, p, m.nct);
+    return hipGetLastError();
+}
+
+template <int LPC>
+static hipError_t launch_macro_l(const Params &p, const MacroShape &m, hipStream_t st) {
+    switch (m.spw) {
+    case 4: return launch_macro_t<LPC, 4>(p, m, st);
+    case 8: return launch_macro_t<LPC, 8>(p, m, st);
+    default: return launch_macro_t<LPC, 16>(p, m, st);
+    }
 }
 
 hipError_t launch_macro_prep(const Params &p, hipStream_t st) {
@@ -1775,14 +1832,8 @@ hipError_t launch_macro_prep(const Params &p, hipStream_t st) {
 }
 
 hipError_t launch_macro(const Params &p, hipStream_t st) {
-    hipError_t e = hipSuccess;
     const MacroShape m = macro_shape(p.ni, p.nj);
-    if (m.lds > 64 * 1024) {
-        e = hipFuncSetAttribute((const void *)k_macro_sweep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)m.lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_macro_sweep, dim3(1), dim3(m.threads), m.lds, st, p, m.nct);
-    return hipGetLastError();
+    return m.lpc == 4 ? launch_macro_l<4>(p, m, st) : launch_macro_l<2>(p, m, st);
 }
 
 // Velocities per sweep block: the largest slice (at most 16) that fits one block of at

@@ -16,6 +16,7 @@ hipError_t launch_face_records(const Params &p, bool fp32, hipStream_t st);
 hipError_t launch_flux(const Params &p, bool fp32, hipStream_t st);
 // Launch shapes of the hyperplane sweeps: block = nct compute lanes + staging waves.
 struct MacroShape {
+    int lpc, spw;  // compute lanes per cell, staged values per staging lane
     int nct, threads;
     size_t lds;
 };
