@@ -180,6 +180,12 @@ idugks_status validate(const idugks_config *c) {
     if (!c->xn || !c->yn) return fail(IDUGKS_E_INVALID, "missing node coordinates");
     if (c->nvx < 2 || c->nvy < 2) return fail(IDUGKS_E_INVALID, "need nv >= 2 per direction");
     if (c->nvx > 4096 || c->nvy > 4096) return fail(IDUGKS_E_INVALID, "velocity grid too large");
+    {
+        // the sweeps index the state [nc][2][nvp] with 32-bit element offsets
+        const int64_t nv = (int64_t)c->nvx * c->nvy, nvp = (nv + VPAD - 1) / VPAD * VPAD;
+        if ((int64_t)c->ni * c->nj * 2 * nvp >= ((int64_t)1 << 31))
+            return fail(IDUGKS_E_INVALID, "state too large (nc x 2 x padded nv must stay below 2^31)");
+    }
     if (!(c->Kn > 0)) return fail(IDUGKS_E_INVALID, "Kn must be positive");
     if (!(c->Pr > 0)) return fail(IDUGKS_E_INVALID, "Pr must be positive");
     if (c->K < 0) return fail(IDUGKS_E_INVALID, "K must be >= 0");
@@ -504,14 +510,16 @@ idugks_status build(const idugks_config *c, Built &b) {
         for (int s = 0; s < 4; ++s) {
             const CellSide &q = b.cs[(size_t)4 * cidx + s];
             double *g = &b.sgeo[(size_t)b.hp_pos[cidx] * SG_N];
-            g[s] = q.nx * q.S; g[4 + s] = q.ny * q.S; g[8 + s] = q.S;  // xi.n S = xi nxS + eta nyS
             int code = 0;
             if (q.type != FT_SELF) {
                 code |= SG_DIAG;
                 if (q.nb >= 0) code |= (q.nb < cidx ? SG_LOWER : SG_UPPER) | (q.hp_adj ? SG_ADJ : 0);
-                if (q.type == FT_WALL) code |= SG_WALL | (q.wside << 8);
             }
-            g[12 + s] = code;
+            const bool flux = code & SG_DIAG;
+            g[s] = flux ? q.nx * q.S : 0.0;  // xi.n S = xi nxS + eta nyS
+            g[4 + s] = flux ? q.ny * q.S : 0.0;
+            g[8 + s] = (code & SG_LOWER) ? 1.0 : 0.0;
+            g[12 + s] = (code & SG_UPPER) ? 1.0 : 0.0;
         }
     // physical time step
     double hmin = 1e300, smax = 0.0;

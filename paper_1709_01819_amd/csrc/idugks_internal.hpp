@@ -67,11 +67,14 @@ constexpr int SG_N = 16, SR_N = 12;
 // nx, ny, S, lambda_j, W_j [4]
 constexpr int MH_SIDE = 6, MH_SN = 8, MH_N = MH_SIDE + 4 * MH_SN, MH_CODE_BITS = 5;
 
-// Static per-cell geometry of the micro and macro sweeps (built on the host).
-// code bits: SG_DIAG the side counts in the diagonal (not self-periodic), SG_LOWER /
-// SG_UPPER the neighbour has a lower / higher index, SG_ADJ the neighbour is on an adjacent
-// i+j hyperplane (else it sits across a periodic seam), SG_WALL wall side.
-enum SweepCode : int { SG_DIAG = 1, SG_LOWER = 2, SG_UPPER = 4, SG_ADJ = 8, SG_WALL = 16 };
+// Static per-cell data of the micro sweeps (built on the host), per cell side: nx S and
+// ny S (0 on a self-periodic side, which has no flux) and the coupling weights of the
+// forward and the backward sweep (1 if the neighbour has a lower / higher index, else 0).
+// Side code bits (the host builds them for these weights, the macro prep for its rows):
+// SG_DIAG the side counts in the diagonal (not self-periodic), SG_LOWER / SG_UPPER the
+// neighbour has a lower / higher index, SG_ADJ the neighbour is on an adjacent i+j
+// hyperplane (else it sits across a periodic seam).
+enum SweepCode : int { SG_DIAG = 1, SG_LOWER = 2, SG_UPPER = 4, SG_ADJ = 8 };
 // Scalars kept on the device (FP64).
 enum Scalar : int { SC_SCALE = 0, SC_RES = 1, SC_MASS = 2, SC_FLAG = 3, SC_NUM = 8 };
 
@@ -102,7 +105,7 @@ struct Params {
     // that the cells of one hyperplane are contiguous and can be staged into LDS at once
     const int *hp_off;       // [nh+1] first position of each hyperplane
     const int *hp_pos;       // [nc] position of each cell
-    const double *sgeo;      // [nc][SG_N] nx S[4], ny S[4], S[4], code[4] (static)
+    const double *sgeo;      // [nc][SG_N] nx S[4], ny S[4], w_lower[4], w_upper[4] (static)
     double *srec;            // [nc][SR_N] U, V, c0, c1, c2c, c3, kqx, kqy, iRT, KRT, cst, base
     double *sdrho;           // [nc][4] wall ghost density increment per cell side
     double *mh;              // [nc][MH_N] macro rows in hyperplane order

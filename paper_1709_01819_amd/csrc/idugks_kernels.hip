@@ -622,7 +622,8 @@ __global__ __launch_bounds__(256) void k_macro_prep(Params p) {
     double ls = 0.0, lw = 0.0;
     int codes = 0;
     for (int s = 0; s < 4; ++s) {
-        codes |= (int)p.sgeo[(size_t)p.hp_pos[c] * SG_N + 12 + s] << (MH_CODE_BITS * s);
+        if (cs[s].type != FT_SELF && cs[s].nb >= 0)
+            codes |= ((cs[s].nb < c ? SG_LOWER : SG_UPPER) | (cs[s].hp_adj ? SG_ADJ : 0)) << (MH_CODE_BITS * s);
         double *ms = m + MH_SIDE + MH_SN * s;
         ms[0] = cs[s].nx; ms[1] = cs[s].ny; ms[2] = cs[s].S;
         if (cs[s].type == FT_SELF) continue;
@@ -663,7 +664,7 @@ DEV void hp_bounds(int s, int ni, int nj, int &lo, int &hi) {
 // these copies out of the compute waves lets the compute waves' own prefetches run ahead
 // without waiting for them.
 constexpr int SDEPTH = 4;  // hyperplanes of staging loads in flight (micro sweeps)
-static_assert(SG_WALL < 1 << MH_CODE_BITS, "side codes must fit their field of the macro row");
+static_assert(SG_ADJ < 1 << MH_CODE_BITS, "side codes must fit their field of the macro row");
 // a staging wave reads up to 64 x 16 values past the first row of a hyperplane, the last of
 // which starts at row nc - 1: the min(ni, nj) + 32 spare rows of the staged arrays cover it
 static_assert(33 * MH_N >= 64 * 16, "macro staging reads past the spare rows");
@@ -837,44 +838,17 @@ constexpr int RING = 3;
 
 template <class S>
 struct SweepItem {
-    int i;                        // cell column, -1 if the lane has no cell at this step
     S aG, aH, bG, bH, e1, e2;     // forward: M, phi~ (G, H), factored Maxwellian;
                                   // backward: increment, phi~
 };
 
-// the item of hyperplane h for this lane; every lane issues the same loads (lanes without
-// a cell read cell 0, velocity 0)
-template <class S, bool UPPER>
-DEV void sweep_load(const Params &p, SweepItem<S> &it, int h, int nh, int slot, int v, bool vok,
-                    int ix, int iy) {
-    int c = 0, i = -1;
-    if (vok && h >= 0 && h < nh) {
-        int lo, hi;
-        hp_bounds(h, p.ni, p.nj, lo, hi);
-        if (lo + slot <= hi) {
-            i = lo + slot;
-            c = i + (h - i) * p.ni;
-        }
-    }
-    it.i = i;
-    const size_t o = (size_t)c * 2 * p.nvp + (i >= 0 ? v : 0);
-    it.aG = ((const S *)p.d1)[o];
-    it.aH = ((const S *)p.d1)[o + p.nvp];
-    it.bG = ((const S *)p.f)[o];
-    it.bH = ((const S *)p.f)[o + p.nvp];
-    if (!UPPER) {
-        const S *tb = (const S *)p.tabs + (size_t)c * (p.nvx + p.nvy);
-        it.e1 = tb[i >= 0 ? ix : 0];
-        it.e2 = tb[p.nvx + (i >= 0 ? iy : 0)];
-    }
-}
-
 // Staging of the micro sweeps: staging lane sl copies column r = sl % STG of the staged
 // rows of cells k = sl / STG + q * KP (KP = cells per pass, q < SPW_MICRO) of a
-// hyperplane.  Columns: forward sweep record (12) + geometry (16); the backward sweep
-// replaces the equilibrium part of the record by the wall ghost increments of the 4
-// sides.  Each lane reads one source column with a fixed stride: one load per value and
-// no divergence between the lanes of a wave.
+// hyperplane.  Columns of the forward sweep: record (12), nx S (4), ny S (4), forward
+// coupling weights (4).  The backward sweep stages the wall ghost density increments of
+// the 4 sides (0 on every side that is not a wall) in place of the equilibrium part of the
+// record, and its own coupling weights.  Each lane reads one source column with a fixed
+// stride: one load per value and no divergence between the lanes of a wave.
 constexpr int SPW_MICRO = 8;
 
 template <bool UPPER>
@@ -890,10 +864,13 @@ struct StageCol {
         stride = 0;
         zero = true;
         if (k0 >= kp) return;  // idle lane
-        if (r >= SR_N + 8) { base = p.sgeo + 12 + (r - SR_N - 8); stride = SG_N; zero = false; }
-        else if (r >= SR_N) { base = p.sgeo + (r - SR_N); stride = SG_N; zero = false; }
-        else if (!UPPER || r >= 10) { base = p.srec + r; stride = SR_N; zero = false; }
-        else if (r < 4) { base = p.sdrho + r; stride = 4; zero = false; }
+        zero = false;
+        stride = SG_N;
+        if (r >= SR_N + 8) base = p.sgeo + (UPPER ? 12 : 8) + (r - SR_N - 8);  // coupling weights
+        else if (r >= SR_N) base = p.sgeo + (r - SR_N);                      // nx S, ny S
+        else if (!UPPER || r >= 10) { base = p.srec + r; stride = SR_N; }
+        else if (r < 4) { base = p.sdrho + r; stride = 4; }
+        else { base = p.srec; stride = 0; zero = true; }
     }
 };
 
@@ -926,11 +903,15 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
     using T = S;
     extern __shared__ unsigned char lds_raw[];
     const int ni = p.ni, nj = p.nj, nh = ni + nj - 1, L = ni < nj ? ni : nj;
-    const int FR = (3 * ni + nj) * vb;   // one species' fronts
-    T *f0 = (T *)lds_raw, *f1 = f0 + ni * vb, *wI = f1 + ni * vb, *wJ = wI + nj * vb;
+    // one species' fronts: [pad][f0][pad][f1][pad][wI][wJ], the pads (vb values) taking the
+    // reads of the columns -1 and ni of lanes on the hyperplane's first and last cell
+    const int FR = (3 * ni + nj + 3) * vb;
+    T *f0 = (T *)lds_raw + vb, *f1 = f0 + (ni + 1) * vb, *wI = f1 + (ni + 1) * vb, *wJ = wI + nj * vb;
     T *st0 = (T *)lds_raw + 2 * FR, *st1 = st0 + L * STG;
     int *hpo = (int *)(st1 + L * STG);
     for (int h = threadIdx.x; h <= nh; h += blockDim.x) hpo[h] = p.hp_off[h];
+    // every front value is finite from the start: uncoupled sides multiply theirs by 0
+    for (int e = threadIdx.x; e < 2 * FR; e += blockDim.x) ((T *)lds_raw)[e] = T(0);
     __syncthreads();
     auto hp = [&](int t) { return UPPER ? nh - 1 - t : t; };
     // Both roles run one barrier after the prologue and one per hyperplane.
@@ -966,50 +947,82 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
         }
         return;
     }
+    // Compute lanes.  On hyperplane h (cells i = lo..hi, j = h - i) the lane of slot k has the
+    // cell i = lo + k if k <= hi - lo.  Its ring loads take i = lo + min(k, hi - lo) (lanes
+    // past the hyperplane's end load its last cell and discard it, so every load stays in
+    // bounds): the cell index is the one of (hi, h - hi) plus max(hi - lo - k, 0) (ni - 1),
+    // a per-hyperplane scalar plus a lane constant under a max, and so are its offsets in
+    // the state and the tables.  (Velocities past nv lie in the padding of the velocity
+    // arrays; those lanes compute but store nothing.)
     const int vl = threadIdx.x % vb, slot = threadIdx.x / vb;
     const int v = xcd_remap(blockIdx.x, gridDim.x) * vb + vl;
     const bool vok = slot < L && v < p.nv;
-    const int vv = vok ? v : 0;
-    const T x = (T)p.xi[vv], y = (T)p.eta[vv];
-    const int ix = p.vix[vv], iy = p.viy[vv];
+    const int kk = slot < L ? slot : L - 1;
+    const int nv2 = 2 * p.nvp, ntb = p.nvx + p.nvy;
+    const int kc = kk * (ni - 1) * nv2, kt = kk * (ni - 1) * ntb, ks = slot * vb;
+    const T x = (T)p.xi[v], y = (T)p.eta[v];
+    const int ix = p.vix[v], iy = p.viy[v];
     const T sc = (T)p.scal[SC_SCALE];
     const int need = UPPER ? SG_UPPER : SG_LOWER;
     T gwv[4] = {T(0), T(0), T(0), T(0)}, kw[4] = {T(0), T(0), T(0), T(0)};
-    if (UPPER) {
+    if (UPPER && !ADJ) {
 #pragma unroll
-        for (int ws = 0; ws < 4; ++ws) {
-            gwv[ws] = (T)p.gw[(size_t)ws * p.nvp + vv];
-            kw[ws] = (T)p.wKRT[ws];
+        for (int sd = 0; sd < 4; ++sd) {
+            gwv[sd] = (T)p.gw[(size_t)sd * p.nvp + v];
+            kw[sd] = (T)p.wKRT[sd];
         }
     }
+    auto state_off = [&](int h, int lo, int hi) {
+        return (hi + (h - hi) * ni) * nv2 + max((hi - lo) * (ni - 1) * nv2 - kc, 0) + v;
+    };
+    auto load = [&](SweepItem<S> &it, int t) {
+        const int h = hp(t < nh ? t : nh - 1);
+        int lo, hi;
+        hp_bounds(h, ni, nj, lo, hi);
+        const unsigned o = state_off(h, lo, hi);
+        const S *a = (const S *)p.d1 + o;
+        it.aG = a[0];
+        it.aH = a[p.nvp];
+        if (!ADJ) {
+            const S *b = (const S *)p.f + o;
+            it.bG = b[0];
+            it.bH = b[p.nvp];
+        }
+        if (!UPPER && !ADJ) {
+            const unsigned ot = (hi + (h - hi) * ni) * ntb + max((hi - lo) * (ni - 1) * ntb - kt, 0);
+            const S *tb = (const S *)p.tabs + ot;
+            it.e1 = tb[ix];
+            it.e2 = tb[p.nvx + iy];
+        }
+    };
     SweepItem<S> ring[RING];
 #pragma unroll
-    for (int d = 0; d < RING; ++d) sweep_load<S, UPPER>(p, ring[d], hp(d), nh, slot, v, vok, ix, iy);
+    for (int d = 0; d < RING; ++d) load(ring[d], d);
     lds_barrier();
     // One step: the hyperplane t with ring slot d.  Full groups of RING steps are unrolled
     // without guards, so that the waits for a slot's loads are exact; the tail is guarded.
     auto step = [&](const int t, SweepItem<S> &cur) {
-        if (cur.i >= 0) {
-            const int s = hp(t), i = cur.i, j = s - i;
+        const int h = hp(t);
+        int lo, hi;
+        hp_bounds(h, ni, nj, lo, hi);
+        if (slot <= hi - lo) {
+            const int fi = lo * vb + ks + vl, fj = (h - lo) * vb - ks + vl;  // i vb + vl, j vb + vl
             const T *m = ((t & 1) ? st1 : st0) + slot * STG;
-            // the staged row and the coupled neighbours' increments in two batches of LDS
-            // reads, so that no read waits behind a branch
+            // The staged row, then the one neighbour increment each side can couple to in
+            // this direction (sides i-, i+, j-, j+): forward f0[i-1], wI[j], f0[i], wJ[i];
+            // backward wI[j], f0[i+1], wJ[i], f0[i] (the neighbours across a periodic seam
+            // sit in wI / wJ), all read in one batch.
             T mr[STG];
 #pragma unroll
             for (int e = 0; e < STG; ++e) mr[e] = m[e];
-            int code[4];
+            const T *sp[4];
+            if (UPPER) { sp[0] = wI + fj; sp[1] = f0 + fi + vb; sp[2] = wJ + fi; sp[3] = f0 + fi; }
+            else { sp[0] = f0 + fi - vb; sp[1] = wI + fj; sp[2] = f0 + fi; sp[3] = wJ + fi; }
             T fg[4], fh[4];
 #pragma unroll
             for (int sd = 0; sd < 4; ++sd) {
-                code[sd] = (int)mr[SR_N + 8 + sd];
-                const int fi = UPPER ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
-                // fronts of this step: f0 (adjacent hyperplane) or wI / wJ; uncoupled sides
-                // read f0[vl] and discard it
-                const T *fp = !(code[sd] & need) ? f0
-                              : (code[sd] & SG_ADJ) ? f0 + fi * vb
-                              : (sd < 2 ? wI + j * vb : wJ + i * vb);
-                fg[sd] = fp[vl];
-                fh[sd] = fp[FR + vl];
+                fg[sd] = sp[sd][0];
+                fh[sd] = sp[sd][FR];
             }
             T D = mr[11], sG, sH;
             if (!UPPER && ADJ) {
@@ -1026,55 +1039,56 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
             } else {
                 sG = sH = T(0);
             }
+            // per side, by weights instead of branches: outflow (xi.n > 0) adds to the
+            // diagonal; inflow from a coupled neighbour adds its increment, inflow through a
+            // wall (backward sweep) the ghost's; the transposed operator couples along the
+            // outflow instead.  A weight of 0 adds an exact 0 (all fronts are finite).
 #pragma unroll
             for (int sd = 0; sd < 4; ++sd) {
-                if (!(code[sd] & SG_DIAG)) continue;
                 const T unS = x * mr[SR_N + sd] + y * mr[SR_N + 4 + sd];  // (xi.n) S
+                const T uo = fmax(unS, T(0)), ui = fmin(unS, T(0));
+                D += uo;
+                const T uc = (ADJ ? uo : ui) * mr[SR_N + 8 + sd];
                 if (ADJ) {
-                    if (unS > T(0)) {
-                        D += unS;
-                        if (code[sd] & need) {
-                            sG += unS * fg[sd];
-                            sH += unS * fh[sd];
-                        }
-                    }
-                } else if (unS > T(0)) {
-                    D += unS;
-                } else if (unS < T(0)) {
-                    if (code[sd] & need) {
-                        sG -= unS * fg[sd];
-                        sH -= unS * fh[sd];
-                    } else if (UPPER && (code[sd] & SG_WALL)) {
-                        const int ws = (code[sd] >> 8) & 3;
-                        T g = T(0), kk = T(0);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            if (q == ws) { g = gwv[q]; kk = kw[q]; }
-                        const T gw = -g * mr[sd] * unS;
-                        sG += gw;
-                        sH += gw * kk;
-                    }
+                    sG += uc * fg[sd];
+                    sH += uc * fh[sd];
+                } else {
+                    sG -= uc * fg[sd];
+                    sH -= uc * fh[sd];
+                }
+                if (UPPER && !ADJ) {  // the ghost density increment is 0 off the walls
+                    const T gw = -gwv[sd] * mr[sd] * ui;
+                    sG += gw;
+                    sH += gw * kw[sd];
                 }
             }
-            const size_t o = (size_t)(i + j * ni) * 2 * p.nvp + v;
             const T iD = T(1) / D;
             const T dG = UPPER ? cur.aG + sG * iD : sG * iD;
             const T dH = UPPER ? cur.aH + sH * iD : sH * iD;
-            if (UPPER && !ADJ) {
-                ((S *)p.f)[o] = (S)(sc * cur.bG + dG);
-                ((S *)p.f)[o + p.nvp] = (S)(sc * cur.bH + dH);
-            } else {
-                ((S *)p.d1)[o] = (S)dG;
-                ((S *)p.d1)[o + p.nvp] = (S)dH;
+            if (vok) {
+                const unsigned o = state_off(h, lo, hi);
+                if (UPPER && !ADJ) {
+                    ((S *)p.f)[o] = (S)(sc * cur.bG + dG);
+                    ((S *)p.f)[o + p.nvp] = (S)(sc * cur.bH + dH);
+                } else {
+                    ((S *)p.d1)[o] = (S)dG;
+                    ((S *)p.d1)[o + p.nvp] = (S)dH;
+                }
+                f1[fi] = dG;
+                f1[FR + fi] = dH;
+                // the seam copies: a cell off the seam column / row writes its f1 value again
+                const int i = lo + slot, j = h - i;
+                T *qI = i == (UPPER ? ni - 1 : 0) ? wI + fj : f1 + fi;
+                T *qJ = j == (UPPER ? nj - 1 : 0) ? wJ + fi : f1 + fi;
+                qI[0] = dG;
+                qI[FR] = dH;
+                qJ[0] = dG;
+                qJ[FR] = dH;
             }
-            f1[i * vb + vl] = dG;
-            f1[FR + i * vb + vl] = dH;
-            if (i == (UPPER ? ni - 1 : 0)) { wI[j * vb + vl] = dG; wI[FR + j * vb + vl] = dH; }
-            if (j == (UPPER ? nj - 1 : 0)) { wJ[i * vb + vl] = dG; wJ[FR + i * vb + vl] = dH; }
         }
         // the slot's loads were issued RING steps ago; it is refilled only after use, so
         // the new loads land in the same registers (no copies that would wait on them)
-        sweep_load<S, UPPER>(p, cur, hp(t + RING), nh, slot, v, vok, ix, iy);
+        load(cur, t + RING);
     };
     int t0 = 0;
     for (; t0 + RING <= nh; t0 += RING) {
@@ -1850,7 +1864,7 @@ SweepShape sweep_shape(int ni, int nj, int nv, size_t s_bytes) {
         c.vb = vb;
         c.nct = round64(vb * L);
         c.threads = c.nct + 64 * nsw;
-        c.lds = ((size_t)2 * (3 * ni + nj) * vb + (size_t)2 * L * STG) * s_bytes + (size_t)(nh + 1) * sizeof(int);
+        c.lds = ((size_t)2 * (3 * ni + nj + 3) * vb + (size_t)2 * L * STG) * s_bytes + (size_t)(nh + 1) * sizeof(int);
         if (c.threads > 1024 || c.lds > 150 * 1024) continue;
         best = c;
         if ((nv + vb - 1) / vb >= 192) break;
