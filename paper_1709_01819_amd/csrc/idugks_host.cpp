@@ -472,11 +472,9 @@ idugks_status build(const idugks_config *c, Built &b) {
                     q.ndx = b.xc[q.nb] + shx - b.xc[cidx];
                     q.ndy = b.yc[q.nb] + shy - b.yc[cidx];
                     q.tie = (F.type == FT_INTERIOR && F.R == cidx && F.sR == s) ? 1 : 0;
-                    q.hp_adj = abs((ni2 + nj2) - (i + j)) == 1 ? 1 : 0;
                 } else {
                     q.nb = -1;
                     q.tie = F.type == FT_FAR ? 1 : 0;
-                    q.hp_adj = 0;
                 }
             }
             // least-squares weights (Eq. 15) over the neighbours (periodic images included)
@@ -513,7 +511,7 @@ idugks_status build(const idugks_config *c, Built &b) {
             int code = 0;
             if (q.type != FT_SELF) {
                 code |= SG_DIAG;
-                if (q.nb >= 0) code |= (q.nb < cidx ? SG_LOWER : SG_UPPER) | (q.hp_adj ? SG_ADJ : 0);
+                if (q.nb >= 0) code |= q.nb < cidx ? SG_LOWER : SG_UPPER;
             }
             const bool flux = code & SG_DIAG;
             g[s] = flux ? q.nx * q.S : 0.0;  // xi.n S = xi nxS + eta nyS

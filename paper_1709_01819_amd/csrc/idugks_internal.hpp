@@ -31,8 +31,7 @@ struct CellSide {
     int type;      // FaceType
     int tie;       // 1 if this cell is upwind for xi.n_out == 0 (R end of interior, far field)
     int wside;     // boundary side (0..3) of wall / far-field faces
-    int hp_adj;    // 1 if nb is on the adjacent i+j hyperplane (not a periodic wrap)
-    int pad0, pad1;
+    int pad0, pad1, pad2;
     double nx, ny; // outward unit normal
     double S;      // face length
     double dx, dy; // face midpoint (own frame) minus own centroid
@@ -65,16 +64,18 @@ struct Rec {
 constexpr int SG_N = 16, SR_N = 12;
 // macro row: M_W (dW* after the forward sweep) [4], 1/D, packed side codes, then per side
 // nx, ny, S, lambda_j, W_j [4]
-constexpr int MH_SIDE = 6, MH_SN = 8, MH_N = MH_SIDE + 4 * MH_SN, MH_CODE_BITS = 5;
+constexpr int MH_SIDE = 6, MH_SN = 8, MH_N = MH_SIDE + 4 * MH_SN, MH_CODE_BITS = 4;
 
 // Static per-cell data of the micro sweeps (built on the host), per cell side: nx S and
 // ny S (0 on a self-periodic side, which has no flux) and the coupling weights of the
 // forward and the backward sweep (1 if the neighbour has a lower / higher index, else 0).
 // Side code bits (the host builds them for these weights, the macro prep for its rows):
 // SG_DIAG the side counts in the diagonal (not self-periodic), SG_LOWER / SG_UPPER the
-// neighbour has a lower / higher index, SG_ADJ the neighbour is on an adjacent i+j
-// hyperplane (else it sits across a periodic seam).
-enum SweepCode : int { SG_DIAG = 1, SG_LOWER = 2, SG_UPPER = 4, SG_ADJ = 8 };
+// neighbour has a lower / higher index.  With periodic directions of 1 or at least 3
+// cells, a side couples in one sweep direction only and to one place: sides i- and j- in
+// the forward sweep to the adjacent hyperplane, i+ and j+ to the copy kept at a periodic
+// seam; the other way round in the backward sweep.
+enum SweepCode : int { SG_DIAG = 1, SG_LOWER = 2, SG_UPPER = 4 };
 // Scalars kept on the device (FP64).
 enum Scalar : int { SC_SCALE = 0, SC_RES = 1, SC_MASS = 2, SC_FLAG = 3, SC_NUM = 8 };
 

@@ -623,7 +623,7 @@ __global__ __launch_bounds__(256) void k_macro_prep(Params p) {
     int codes = 0;
     for (int s = 0; s < 4; ++s) {
         if (cs[s].type != FT_SELF && cs[s].nb >= 0)
-            codes |= ((cs[s].nb < c ? SG_LOWER : SG_UPPER) | (cs[s].hp_adj ? SG_ADJ : 0)) << (MH_CODE_BITS * s);
+            codes |= (cs[s].nb < c ? SG_LOWER : SG_UPPER) << (MH_CODE_BITS * s);
         double *ms = m + MH_SIDE + MH_SN * s;
         ms[0] = cs[s].nx; ms[1] = cs[s].ny; ms[2] = cs[s].S;
         if (cs[s].type == FT_SELF) continue;
@@ -664,10 +664,20 @@ DEV void hp_bounds(int s, int ni, int nj, int &lo, int &hi) {
 // these copies out of the compute waves lets the compute waves' own prefetches run ahead
 // without waiting for them.
 constexpr int SDEPTH = 4;  // hyperplanes of staging loads in flight (micro sweeps)
-static_assert(SG_ADJ < 1 << MH_CODE_BITS, "side codes must fit their field of the macro row");
+static_assert(SG_UPPER < 1 << MH_CODE_BITS, "side codes must fit their field of the macro row");
 // a staging wave reads up to 64 x 16 values past the first row of a hyperplane, the last of
 // which starts at row nc - 1: the min(ni, nj) + 32 spare rows of the staged arrays cover it
 static_assert(33 * MH_N >= 64 * 16, "macro staging reads past the spare rows");
+
+// x of the lane (lane ^ 1) or (lane ^ 2) of the same quad: a DPP quad permutation
+// (CTRL 0xB1 = [1,0,3,2], 0x4E = [2,3,0,1]), two 32-bit moves in registers
+template <int CTRL>
+DEV double quad_swap(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 template <int N>
 DEV void stage_store(const double (&reg)[N], double *dst, int n, int sl, int nsl) {
@@ -679,13 +689,16 @@ DEV void stage_store(const double (&reg)[N], double *dst, int n, int sl, int nsl
 }
 
 // Macro LU-SGS sweeps (Eq. 29-31) over i+j hyperplanes in one block.  Waves below nct
-// compute, LPC lanes per cell of a hyperplane, each taking the sides q, q + LPC, ...:
+// compute, LPC lanes per cell of a hyperplane, lane q taking the sides q NS .. q NS + NS - 1
+// (NS = 4 / LPC: with two lanes, one has the i sides and the other the j sides, so each
+// has one coupled side per direction in the interior):
 //   r -= 1/2 S (F_n(W_j + dW_j) - F_n(W_j) - lambda_j dW_j)
 // over the lower (forward) or upper (backward) neighbours; the lanes of a cell sum their
-// parts in a fixed order by shuffles and lane q finishes the components q, q + LPC, ....
-// LDS holds the previous hyperplane's increments (fronts), those of the cells next to a
-// periodic seam (wI: column i = 0 / ni-1, wJ: row j = 0 / nj-1, the only non-adjacent
-// neighbours) and the staged rows of the current and the next hyperplane.  The forward
+// parts in a fixed order by quad permutations and lane q finishes the components q,
+// q + LPC, ....  LDS holds the previous hyperplane's increments (fronts, with a padding
+// cell at each end), those of the cells next to a periodic seam (wI: column i = 0 / ni-1,
+// wJ: row j = 0 / nj-1, the only non-adjacent neighbours) and the staged rows of the
+// current and the next hyperplane.  The forward
 // sweep writes dW* into the first four values of each cell's row, which the backward
 // sweep stages back.  The staging waves keep MD hyperplanes of SPWM values per lane in
 // flight: the row is short enough that one CU's load latency, not its bandwidth, bounds
@@ -694,10 +707,11 @@ template <int LPC, int SPWM, int MD>
 __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
     extern __shared__ double lds[];
     const int ni = p.ni, nj = p.nj, nh = ni + nj - 1, L = ni < nj ? ni : nj;
-    double *fr0 = lds, *fr1 = lds + 4 * ni, *wI = lds + 8 * ni, *wJ = wI + 4 * nj;
+    double *fr0 = lds + 4, *fr1 = fr0 + 4 * (ni + 1), *wI = fr1 + 4 * (ni + 1), *wJ = wI + 4 * nj;
     double *st0 = wJ + 4 * ni, *st1 = st0 + (size_t)L * MH_N;
     int *hpo = (int *)(st1 + (size_t)L * MH_N);
     for (int h = threadIdx.x; h <= nh; h += blockDim.x) hpo[h] = p.hp_off[h];
+    for (int e = threadIdx.x; e < 12 * ni + 4 * nj + 12; e += blockDim.x) lds[e] = 0.0;
     __syncthreads();
     const double ik2 = 1.0 / (p.K + 2);
     // Both roles run the same number of barriers: one after the prologue and one per
@@ -755,35 +769,32 @@ __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
             const int s = upper ? nh - 1 - t : t;
             int lo, hi;
             hp_bounds(s, ni, nj, lo, hi);
-            const int i = lo + k;
-            const bool live = i <= hi;
-            const int j = s - i;
+            // idle lanes (past the hyperplane's end) read the data of its first cell
+            const bool live = lo + k <= hi;
+            const int i = live ? lo + k : lo, j = s - i;
             const double *m = (t & 1 ? st1 : st0) + (size_t)(live ? k : 0) * MH_N;
-            // this lane's side values, then the neighbours' increments, in two LDS batches
+            // this lane's side values and the one neighbour increment each of its sides can
+            // couple to in this direction (sides i-, i+, j-, j+): forward fr0[i-1], wI[j],
+            // fr0[i], wJ[i]; backward wI[j], fr0[i+1], wJ[i], fr0[i]; one batch of LDS reads
             const int codes = (int)m[5];
-            double ms[NS][MH_SN], mr[NS];
+            double ms[NS][MH_SN], mr[NS], dW[NS][4];
 #pragma unroll
             for (int u = 0; u < NS; ++u) {
-                mr[u] = m[q + u * LPC];
+                const int sd = q * NS + u;
+                mr[u] = m[sd];
 #pragma unroll
-                for (int e = 0; e < MH_SN; ++e) ms[u][e] = m[MH_SIDE + MH_SN * (q + u * LPC) + e];
-            }
-            const double iD = m[4];
-            bool cpl[NS];
-            double dW[NS][4];
-#pragma unroll
-            for (int u = 0; u < NS; ++u) {
-                const int sd = q + u * LPC, code = (codes >> (MH_CODE_BITS * sd)) & ((1 << MH_CODE_BITS) - 1);
-                cpl[u] = live && (code & need);
-                const int fi = upper ? (sd == 1 ? i + 1 : i) : (sd == 0 ? i - 1 : i);
-                const double *src = !cpl[u] ? fr0 : (code & SG_ADJ) ? fr0 + 4 * fi : (sd < 2 ? wI + 4 * j : wJ + 4 * i);
+                for (int e = 0; e < MH_SN; ++e) ms[u][e] = m[MH_SIDE + MH_SN * sd + e];
+                const double *src = upper ? (sd == 0 ? wI + 4 * j : sd == 1 ? fr0 + 4 * (i + 1) : sd == 2 ? wJ + 4 * i : fr0 + 4 * i)
+                                          : (sd == 0 ? fr0 + 4 * (i - 1) : sd == 1 ? wI + 4 * j : sd == 2 ? fr0 + 4 * i : wJ + 4 * i);
 #pragma unroll
                 for (int a = 0; a < 4; ++a) dW[u][a] = src[a];
             }
+            const double iD = m[4];
             double r[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int u = 0; u < NS; ++u) {
-                if (!cpl[u]) continue;
+                const int sd = q * NS + u;
+                if (!(live && ((codes >> (MH_CODE_BITS * sd)) & need))) continue;
                 double Wn[4], F0[4], F1[4];
 #pragma unroll
                 for (int a = 0; a < 4; ++a) Wn[a] = ms[u][4 + a] + dW[u][a];
@@ -795,8 +806,8 @@ __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
             }
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
-                if (LPC >= 2) r[a] += __shfl_xor(r[a], 1, 64);
-                if (LPC >= 4) r[a] += __shfl_xor(r[a], 2, 64);
+                if (LPC >= 2) r[a] += quad_swap<0xB1>(r[a]);
+                if (LPC >= 4) r[a] += quad_swap<0x4E>(r[a]);
             }
             if (live) {
 #pragma unroll
@@ -1797,25 +1808,24 @@ hipError_t launch_flux(const Params &p, bool fp32, hipStream_t st) {
 
 static int round64(int n) { return (n + 63) / 64 * 64; }
 
-// Lanes per cell: 4 if they leave room in 1024 lanes for the staging waves at 16 values
-// per lane, else 2; then the fewest values per staging lane (the deepest prefetch: 32
-// registers hold MD x SPWM values) that still fit.  Meshes too wide for that are
-// rejected at init (their LDS would not fit either).
+// The deepest staging prefetch first (fewest values per staging lane: 32 registers hold
+// MD x SPWM values), then the most lanes per cell (4 or 2), that fit 1024 lanes.  Meshes
+// too wide for that are rejected at init (their LDS would not fit either).
 MacroShape macro_shape(int ni, int nj) {
     const int L = ni < nj ? ni : nj, nh = ni + nj - 1;
     auto waves = [&](int spw) { return (L * MH_N + 64 * spw - 1) / (64 * spw); };
     MacroShape m{};
-    for (int lpc = 4; lpc >= 2; lpc /= 2) {
-        m.lpc = lpc;
-        m.nct = round64(lpc * L);
-        if (m.nct + 64 * waves(16) <= 1024) break;
-    }
     for (int spw = 4; spw <= 16; spw *= 2) {
-        m.spw = spw;
-        m.threads = m.nct + 64 * waves(spw);
+        for (int lpc = 4; lpc >= 2; lpc /= 2) {
+            m.lpc = lpc;
+            m.spw = spw;
+            m.nct = round64(lpc * L);
+            m.threads = m.nct + 64 * waves(spw);
+            if (m.threads <= 1024) break;
+        }
         if (m.threads <= 1024) break;
     }
-    m.lds = (size_t)(12 * ni + 4 * nj + 2 * L * MH_N) * sizeof(double) + (size_t)(nh + 1) * sizeof(int);
+    m.lds = (size_t)(12 * ni + 4 * nj + 12 + 2 * L * MH_N) * sizeof(double) + (size_t)(nh + 1) * sizeof(int);
     return m;
 }
 
