@@ -606,7 +606,7 @@ enum Region {
     R_CS, R_FACES, R_WALLF, R_AREA, R_XI, R_ETA, R_W, R_X1, R_WX1, R_Y1, R_WY1, R_VIX, R_VIY,
     R_GW, R_WKRT, R_GINF, R_HINF, R_WDEN, R_BHALF, R_F, R_D1, R_TAB, R_TABS, R_TABF, R_REC,
     R_RECS, R_RECF, R_PART, R_RAW, R_WC, R_MW, R_DW, R_DWD, R_DTIMP, R_RHOOLD, R_DRHO, R_SCAL,
-    R_STAGE, R_HPOFF, R_HPPOS, R_SGEO, R_SREC, R_SDRHO, R_MH, R_GR,
+    R_STAGE, R_HPOFF, R_HPPOS, R_SGEO, R_SREC, R_SDRHO, R_MH, R_GR, R_MWC,
     // sensitivities (empty unless BGK, no limiter, FP64)
     R_LT, R_GJ, R_FBAR, R_YBUF, R_AGR, R_FADJ, R_CADJ, R_DGW, R_DWDEN, R_JACC, R_JACF, R_RED,
     R_ADJS, R_COUNT
@@ -626,6 +626,7 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
     // rows of the hyperplane-ordered sweep arrays: the staging waves read whole passes past
     // the last cell of a hyperplane, so these arrays carry min(ni, nj) + 32 spare rows
     const size_t ncs = (size_t)nc + std::min(c->ni, c->nj) + 32;
+    const int nv = c->nvx * c->nvy, nch = (nv + vel_chunk(nv) - 1) / vel_chunk(nv);
     const size_t adj = adjoint_capable(c) ? 1 : 0;
     const size_t sizes[R_COUNT] = {
         sizeof(CellSide) * 4 * (size_t)nc, sizeof(Face) * (size_t)nf, sizeof(int) * (size_t)std::max(nwall, 1),
@@ -638,7 +639,7 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
         8 * 4 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nf, 8 * SC_NUM,
         8 * (size_t)std::max(nc, 2) * nvp, sizeof(int) * (size_t)(nc + 2), sizeof(int) * (size_t)nc,
         8 * (size_t)SG_N * ncs, 8 * (size_t)SR_N * ncs, 8 * 4 * (size_t)ncs, 8 * (size_t)MH_N * ncs,
-        S * 6 * (size_t)nc * nvp,
+        S * 6 * (size_t)nc * nvp, nch > 1 ? 8 * (size_t)nc * nch * 4 : 0,
         adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 2 * (size_t)nc * nvp,
         adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 6 * (size_t)nc * nvp, adj * 8 * (size_t)FA_N * nf,
         adj * 8 * (size_t)CA_N * nc, adj * 8 * 8 * (size_t)nvp, adj * 8 * 2 * (size_t)nf,
@@ -803,6 +804,7 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     Params &p = x->p;
     memset(&p, 0, sizeof p);
     p.ni = b.ni; p.nj = b.nj; p.nc = b.nc; p.nf = b.nf; p.nv = b.nv; p.nvp = b.nvp;
+    p.vch = vel_chunk(b.nv); p.nch = (b.nv + p.vch - 1) / p.vch;
     p.nvx = b.nvx; p.nvy = b.nvy; p.K = cfg->K; p.model = cfg->model; p.limiter = cfg->limiter;
     p.closed = b.closed; p.nm = cfg->model == IDUGKS_SHAKHOV ? NM_SHAKHOV : NM_BGK; p.nwall = b.nwall;
     p.dt = b.dt; p.h = 0.5 * b.dt; p.Pr = cfg->Pr; p.mu_ref = cfg->Kn / sqrt(M_PI);
@@ -825,6 +827,7 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     p.hp_off = (const int *)R(R_HPOFF); p.hp_pos = (const int *)R(R_HPPOS);
     p.sgeo = (const double *)R(R_SGEO); p.srec = (double *)R(R_SREC); p.sdrho = (double *)R(R_SDRHO);
     p.mh = (double *)R(R_MH); p.gr = R(R_GR);
+    p.MWc = (double *)R(R_MWC);
     x->stage = (double *)R(R_STAGE);
     p.Kn = cfg->Kn;
     for (int s4 = 0; s4 < 4; ++s4) { p.wall_u[s4] = cfg->wall_u[s4]; p.wall_v[s4] = cfg->wall_v[s4]; }

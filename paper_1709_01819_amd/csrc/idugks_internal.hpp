@@ -61,6 +61,12 @@ struct Rec {
     double rw;               // wall faces: density of the reflected Maxwellian
 };
 
+// Velocities per block of the flux kernel: all of them up to 4096, else chunks of 2048,
+// blocks ordered chunk by chunk, so that a cell's upwind neighbours are read while their
+// slice of the reconstruction is still in L2.  (The face-partial kernel takes all
+// velocities per block: its 4 x NM sums per block would cost more than the reuse saves.)
+inline int vel_chunk(int nv) { return nv <= 4096 ? nv : 2048; }
+
 constexpr int SG_N = 16, SR_N = 12;
 // macro row: M_W (dW* after the forward sweep) [4], 1/D, packed side codes, then per side
 // nx, ny, S, lambda_j, W_j [4]
@@ -81,6 +87,7 @@ enum Scalar : int { SC_SCALE = 0, SC_RES = 1, SC_MASS = 2, SC_FLAG = 3, SC_NUM =
 
 struct Params {
     int ni, nj, nc, nf, nv, nvp, nvx, nvy, K, model, limiter, closed, nm, nwall;
+    int vch, nch;            // velocities per chunk of the flux kernel, chunks
     double dt, h, Pr, mu_ref, omega, cfl_imp, M0, gam;
     // velocity set
     const double *xi, *eta, *w;
@@ -102,6 +109,7 @@ struct Params {
     void *gr;                // [nc][6][nvp] phi-bar-plus and its limited gradient (G: b, gx, gy; H: b, gx, gy)
     Rec *rec, *recs, *recf;
     double *part, *raw, *Wc, *MW, *dW, *DWd, *dtimp, *rho_old, *drho, *scal;
+    double *MWc;             // [nc][nch][4] per-chunk sums of MW (nch > 1)
     // per-cell data of the sweeps stored in i+j hyperplane order (position hp_pos[c]), so
     // that the cells of one hyperplane are contiguous and can be staged into LDS at once
     const int *hp_off;       // [nh+1] first position of each hyperplane

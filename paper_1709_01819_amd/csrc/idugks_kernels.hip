@@ -82,6 +82,27 @@ DEV void block_sum_store(double (&a)[N], double *sh, double *out) {
     }
 }
 
+// Block of a velocity-chunked per-cell kernel: ncp = nc rounded up to a multiple of 8
+// blocks per chunk of vch velocities, chunk by chunk, so that XCD x takes a contiguous
+// range of cells of every chunk.  False for the padding blocks.
+DEV bool chunk_block(const Params &p, int vch, int &c, int &v0, int &v1) {
+    const int ncp = (p.nc + 7) & ~7, ch = blockIdx.x / ncp;
+    c = xcd_remap(blockIdx.x - ch * ncp, ncp);
+    v0 = ch * vch;
+    v1 = min(p.nv, v0 + vch);
+    return c < p.nc;
+}
+
+// dst[c][m] = sum over the chunks k (in order) of src[c][k][m], m < n
+__global__ __launch_bounds__(256) void k_combine(const double *src, double *dst, int nc, int nch, int n) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nc * n) return;
+    const int c = e / n, m = e - c * n;
+    double s = 0.0;
+    for (int k = 0; k < nch; ++k) s += src[((size_t)c * nch + k) * n + m];
+    dst[e] = s;
+}
+
 template <class T>
 struct RecT {
     T U, V, c0, c1, c2c, c3, kqx, kqy, iRT, KRT, ab, bb;
@@ -436,13 +457,14 @@ __global__ __launch_bounds__(256) void k_partials(Params p) {
     using T = S;
     constexpr int NM = SHAK ? NM_SHAKHOV : NM_BGK;
     __shared__ double sh[4 * 4 * NM];
-    const int c = xcd_remap(blockIdx.x, p.nc);
+    int c, v0, v1;
+    if (!chunk_block(p, p.nv, c, v0, v1)) return;
     const CellSide *cs = p.cs + 4 * c;
     const T sc = (T)p.scal[SC_SCALE], h = (T)p.h;
     double acc[4 * NM];
 #pragma unroll
     for (int m = 0; m < 4 * NM; ++m) acc[m] = 0.0;
-    for (int v = threadIdx.x; v < p.nv; v += blockDim.x) {
+    for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
         const int ix = p.vix[v], iy = p.viy[v];
         const T x = (T)p.xi[v], y = (T)p.eta[v];
         T bG, bH, gxG, gyG, gxH, gyH;
@@ -517,13 +539,14 @@ template <class S, bool SHAK, bool LIM>
 __global__ __launch_bounds__(256) void k_flux(Params p) {
     using T = S;
     __shared__ double sh[4 * 4];
-    const int c = xcd_remap(blockIdx.x, p.nc);
+    int c, v0, v1;
+    if (!chunk_block(p, p.vch, c, v0, v1)) return;
     const CellSide *cs = p.cs + 4 * c;
     const T h = (T)p.h;
     const int TW = p.nvx + p.nvy;
     S *MG = (S *)p.d1 + ((size_t)c * 2) * p.nvp, *MH = MG + p.nvp;
     double mw[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int v = threadIdx.x; v < p.nv; v += blockDim.x) {
+    for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
         const int ix = p.vix[v], iy = p.viy[v];
         const T x = (T)p.xi[v], y = (T)p.eta[v];
         const S *gr = (const S *)p.gr + (size_t)c * 6 * p.nvp + v;
@@ -578,7 +601,7 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
         mw[2] += wv * dy * dG;
         mw[3] += 0.5 * wv * ((dx * dx + dy * dy) * dG + (double)accH);
     }
-    block_sum_store<4>(mw, sh, p.MW + (size_t)c * 4);
+    block_sum_store<4>(mw, sh, p.nch > 1 ? p.MWc + ((size_t)c * p.nch + v0 / p.vch) * 4 : p.MW + (size_t)c * 4);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1771,14 +1794,22 @@ hipError_t launch_records(const Params &p, bool fp32, int which, hipStream_t st)
     return hipGetLastError();
 }
 
+static dim3 chunk_grid(const Params &p, int nch) { return dim3(((p.nc + 7) & ~7) * nch); }
+
+static hipError_t combine(const double *src, double *dst, const Params &p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_combine, dim3((p.nc * n + 255) / 256), dim3(256), 0, st, src, dst, p.nc, p.nch, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_partials(const Params &p, bool fp32, hipStream_t st) {
+    const dim3 g = chunk_grid(p, 1);
     DISPATCH_S(fp32, {
         if (p.model == 1) {
-            if (p.limiter) hipLaunchKernelGGL((k_partials<S, true, true>), dim3(p.nc), dim3(256), 0, st, p);
-            else hipLaunchKernelGGL((k_partials<S, true, false>), dim3(p.nc), dim3(256), 0, st, p);
+            if (p.limiter) hipLaunchKernelGGL((k_partials<S, true, true>), g, dim3(256), 0, st, p);
+            else hipLaunchKernelGGL((k_partials<S, true, false>), g, dim3(256), 0, st, p);
         } else {
-            if (p.limiter) hipLaunchKernelGGL((k_partials<S, false, true>), dim3(p.nc), dim3(256), 0, st, p);
-            else hipLaunchKernelGGL((k_partials<S, false, false>), dim3(p.nc), dim3(256), 0, st, p);
+            if (p.limiter) hipLaunchKernelGGL((k_partials<S, false, true>), g, dim3(256), 0, st, p);
+            else hipLaunchKernelGGL((k_partials<S, false, false>), g, dim3(256), 0, st, p);
         }
     });
     return hipGetLastError();
@@ -1794,15 +1825,17 @@ hipError_t launch_face_records(const Params &p, bool fp32, hipStream_t st) {
 }
 
 hipError_t launch_flux(const Params &p, bool fp32, hipStream_t st) {
+    const dim3 g = chunk_grid(p, p.nch);
     DISPATCH_S(fp32, {
         if (p.model == 1) {
-            if (p.limiter) hipLaunchKernelGGL((k_flux<S, true, true>), dim3(p.nc), dim3(256), 0, st, p);
-            else hipLaunchKernelGGL((k_flux<S, true, false>), dim3(p.nc), dim3(256), 0, st, p);
+            if (p.limiter) hipLaunchKernelGGL((k_flux<S, true, true>), g, dim3(256), 0, st, p);
+            else hipLaunchKernelGGL((k_flux<S, true, false>), g, dim3(256), 0, st, p);
         } else {
-            if (p.limiter) hipLaunchKernelGGL((k_flux<S, false, true>), dim3(p.nc), dim3(256), 0, st, p);
-            else hipLaunchKernelGGL((k_flux<S, false, false>), dim3(p.nc), dim3(256), 0, st, p);
+            if (p.limiter) hipLaunchKernelGGL((k_flux<S, false, true>), g, dim3(256), 0, st, p);
+            else hipLaunchKernelGGL((k_flux<S, false, false>), g, dim3(256), 0, st, p);
         }
     });
+    if (p.nch > 1) return combine(p.MWc, p.MW, p, 4, st);
     return hipGetLastError();
 }
 

@@ -45,6 +45,12 @@ CASES = {
     "cylinder_limiter": lambda: wl.cylinder(ni=8, nj=12, rmax=6.0, nv=16, vmax=12.0, Kn=0.1,
                                             precision=wl.FP64),
     "periodic_box": lambda: wl.periodic_box(n=5, nv=8),
+    # 65^2 = 4225 velocities: the flux kernel splits them into chunks of 2048, 2048 and 129
+    # and combines the per-chunk macroscopic residuals
+    "cavity_shakhov_chunked": lambda: wl.cavity(n=6, stretch=None, nv=65, quad=wl.NEWTON_COTES,
+                                                vmax=4.0, Kn=1.0, model=wl.SHAKHOV, Pr=2 / 3, K=1),
+    "cylinder_chunked": lambda: wl.cylinder(ni=6, nj=8, rmax=6.0, nv=65, vmax=12.0, Kn=0.1,
+                                            precision=wl.FP64),
 }
 
 
