@@ -606,7 +606,7 @@ enum Region {
     R_CS, R_FACES, R_WALLF, R_AREA, R_XI, R_ETA, R_W, R_X1, R_WX1, R_Y1, R_WY1, R_VIX, R_VIY,
     R_GW, R_WKRT, R_GINF, R_HINF, R_WDEN, R_BHALF, R_F, R_D1, R_TAB, R_TABS, R_TABF, R_REC,
     R_RECS, R_RECF, R_PART, R_RAW, R_WC, R_MW, R_DW, R_DWD, R_DTIMP, R_RHOOLD, R_DRHO, R_SCAL,
-    R_STAGE, R_HPOFF, R_HPPOS, R_SGEO, R_SREC, R_SDRHO, R_MH, R_GR, R_MWC,
+    R_STAGE, R_HPOFF, R_HPPOS, R_SGEO, R_SREC, R_SDRHO, R_MH, R_FV, R_MWC, R_RECT, R_RECFT,
     // sensitivities (empty unless BGK, no limiter, FP64)
     R_LT, R_GJ, R_FBAR, R_YBUF, R_AGR, R_FADJ, R_CADJ, R_DGW, R_DWDEN, R_JACC, R_JACF, R_RED,
     R_ADJS, R_COUNT
@@ -639,7 +639,8 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
         8 * 4 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nf, 8 * SC_NUM,
         8 * (size_t)std::max(nc, 2) * nvp, sizeof(int) * (size_t)(nc + 2), sizeof(int) * (size_t)nc,
         8 * (size_t)SG_N * ncs, 8 * (size_t)SR_N * ncs, 8 * 4 * (size_t)ncs, 8 * (size_t)MH_N * ncs,
-        S * 6 * (size_t)nc * nvp, nch > 1 ? 8 * (size_t)nc * nch * 4 : 0,
+        S * 2 * (size_t)nf * nvp, nch > 1 ? 8 * (size_t)nc * nch * 4 : 0,
+        S * RT_N * (size_t)nc, S * RT_N * (size_t)nf,
         adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 2 * (size_t)nc * nvp,
         adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 6 * (size_t)nc * nvp, adj * 8 * (size_t)FA_N * nf,
         adj * 8 * (size_t)CA_N * nc, adj * 8 * 8 * (size_t)nvp, adj * 8 * 2 * (size_t)nf,
@@ -826,7 +827,7 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     p.scal = (double *)R(R_SCAL);
     p.hp_off = (const int *)R(R_HPOFF); p.hp_pos = (const int *)R(R_HPPOS);
     p.sgeo = (const double *)R(R_SGEO); p.srec = (double *)R(R_SREC); p.sdrho = (double *)R(R_SDRHO);
-    p.mh = (double *)R(R_MH); p.gr = R(R_GR);
+    p.mh = (double *)R(R_MH); p.fv = R(R_FV); p.recT = R(R_RECT); p.recfT = R(R_RECFT);
     p.MWc = (double *)R(R_MWC);
     x->stage = (double *)R(R_STAGE);
     p.Kn = cfg->Kn;

@@ -67,6 +67,11 @@ struct Rec {
 // velocities per block: its 4 x NM sums per block would cost more than the reuse saves.)
 inline int vel_chunk(int nv) { return nv <= 4096 ? nv : 2048; }
 
+// Records in the state precision, per cell (current step) and per face: U, V, c0, c1, c2c,
+// c3, kqx, kqy, iRT, KRT, ab, bb, alpha, rw (two spare), read in the per-velocity loops
+// with scalar loads and no conversions.
+constexpr int RT_N = 16;
+
 constexpr int SG_N = 16, SR_N = 12;
 // macro row: M_W (dW* after the forward sweep) [4], 1/D, packed side codes, then per side
 // nx, ny, S, lambda_j, W_j [4]
@@ -106,7 +111,10 @@ struct Params {
     const double *bhalf;     // [nf][NM] moments of the incoming half of the ghost distribution
     // state and work (S-typed arrays as void*)
     void *f, *d1, *tab, *tabs, *tabf;
-    void *gr;                // [nc][6][nvp] phi-bar-plus and its limited gradient (G: b, gx, gy; H: b, gx, gy)
+    void *recT, *recfT;      // [nc][RT_N], [nf][RT_N] records in the state precision
+    void *fv;                // [nf][2][nvp] reconstructed phi-bar at each face (Eq. 13-14, from the
+                             // upwind cell; written by the face-partial kernel for every
+                             // velocity whose upwind side is a cell)
     Rec *rec, *recs, *recf;
     double *part, *raw, *Wc, *MW, *dW, *DWd, *dtimp, *rho_old, *drho, *scal;
     double *MWc;             // [nc][nch][4] per-chunk sums of MW (nch > 1)

@@ -215,7 +215,7 @@ DEV void solve4(double A[4][4], double b[4]) {
 // P = c.q, projected out of the conserved moments with the same A.
 template <class S, bool SHAK>
 DEV void build_eq(const Params &p, double rho, double U, double V, double RT, double tau,
-                  double qx, double qy, Rec *out, S *tab, int lane) {
+                  double qx, double qy, Rec *out, S *tab, int lane, S *outT = nullptr) {
     constexpr int NP = SHAK ? 6 : 5;
     const double lam = 0.5 / RT, A0 = rho * lam / M_PI;
     double X[NP], Y[NP];
@@ -288,7 +288,22 @@ DEV void build_eq(const Params &p, double rho, double U, double V, double RT, do
         o.alpha = 2.0 * tau / (2.0 * tau + p.h);
         o.rw = 0.0;
         *out = o;
+        if (outT) {
+            const double v[14] = {o.U, o.V, o.c0, o.c1, o.c2c, o.c3, o.kqx, o.kqy,
+                                  o.iRT, o.KRT, o.ab, o.bb, o.alpha, o.rw};
+            for (int i = 0; i < 14; ++i) outT[i] = (S)v[i];
+        }
     }
+}
+
+// A record in the state precision; i is uniform over the wave (scalar loads)
+template <class S>
+DEV RecT<S> load_recT(const void *base, int i) {
+    const S *r = (const S *)base + (size_t)__builtin_amdgcn_readfirstlane(i) * RT_N;
+    RecT<S> o;
+    o.U = r[0]; o.V = r[1]; o.c0 = r[2]; o.c1 = r[3]; o.c2c = r[4]; o.c3 = r[5];
+    o.kqx = r[6]; o.kqy = r[7]; o.iRT = r[8]; o.KRT = r[9]; o.ab = r[10]; o.bb = r[11];
+    return o;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -378,7 +393,8 @@ __global__ __launch_bounds__(256) void k_records(Params p, int which) {
     }
     Rec *out = which == 0 ? p.rec + c : p.recs + c;
     S *tab = (S *)(which == 0 ? p.tab : p.tabs) + (size_t)c * TW;
-    build_eq<S, SHAK>(p, rho, U, V, RT, tau, qx, qy, out, tab, lane);
+    build_eq<S, SHAK>(p, rho, U, V, RT, tau, qx, qy, out, tab, lane,
+                      which == 0 ? (S *)p.recT + (size_t)c * RT_N : nullptr);
     if (which == 1 && lane == 0) {
         const Rec r = *out;  // written by this lane
         double *o = p.srec + (size_t)p.hp_pos[c] * SR_N;
@@ -394,7 +410,7 @@ __global__ __launch_bounds__(256) void k_records(Params p, int which) {
 // ---------------------------------------------------------------------------------------
 template <class S, class T, bool SHAK>
 DEV void barplus(const Params &p, int j, int v, int ix, int iy, T x, T y, T sc, T &bG, T &bH) {
-    const RecT<T> r = load_rec<T>(p.rec[j]);
+    const RecT<T> r = load_recT<S>(p.recT, j);
     const S *tb = (const S *)p.tab + (size_t)j * (p.nvx + p.nvy);
     const T E = (T)tb[ix] * (T)tb[p.nvx + iy];
     T eG, eH;
@@ -469,9 +485,6 @@ __global__ __launch_bounds__(256) void k_partials(Params p) {
         const T x = (T)p.xi[v], y = (T)p.eta[v];
         T bG, bH, gxG, gyG, gxH, gyH;
         recon_cell<S, T, SHAK, LIM>(p, c, v, ix, iy, x, y, sc, bG, bH, gxG, gyG, gxH, gyH);
-        S *gr = (S *)p.gr + (size_t)c * 6 * p.nvp + v;
-        gr[0] = (S)bG; gr[p.nvp] = (S)gxG; gr[2 * p.nvp] = (S)gyG;
-        gr[3 * p.nvp] = (S)bH; gr[4 * p.nvp] = (S)gxH; gr[5 * p.nvp] = (S)gyH;
         const double wv = p.w[v];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -480,6 +493,9 @@ __global__ __launch_bounds__(256) void k_partials(Params p) {
             if (!(un > 0.0 || (un == 0.0 && cs[s].tie))) continue;
             const T rx = (T)cs[s].dx - h * x, ry = (T)cs[s].dy - h * y;
             const T G = bG + gxG * rx + gyG * ry, H = bH + gxH * rx + gyH * ry;
+            S *fv = (S *)p.fv + (size_t)cs[s].face * 2 * p.nvp + v;
+            fv[0] = (S)G;
+            fv[p.nvp] = (S)H;
             double a[NM];
 #pragma unroll
             for (int m = 0; m < NM; ++m) a[m] = 0.0;
@@ -528,30 +544,29 @@ __global__ __launch_bounds__(256) void k_face_records(Params p) {
         qy = t2 * qby / (t2 + p.h * p.Pr);
     }
     S *tab = (S *)p.tabf + (size_t)k * (p.nvx + p.nvy);
-    build_eq<S, SHAK>(p, rho, U, V, RT, tau, qx, qy, p.recf + k, tab, lane);
-    if (lane == 0) p.recf[k].rw = rw;
+    build_eq<S, SHAK>(p, rho, U, V, RT, tau, qx, qy, p.recf + k, tab, lane, (S *)p.recfT + (size_t)k * RT_N);
+    if (lane == 0) {
+        p.recf[k].rw = rw;
+        ((S *)p.recfT)[(size_t)k * RT_N + 13] = (S)rw;
+    }
 }
 
 // ---------------------------------------------------------------------------------------
 // flux: M_i(v) = -sum_k S (xi.n_out) phi_k (Eq. 18, 19, 23) and M_W = sum w psi M (Eq. 27)
 // ---------------------------------------------------------------------------------------
-template <class S, bool SHAK, bool LIM>
+template <class S, bool SHAK>
 __global__ __launch_bounds__(256) void k_flux(Params p) {
     using T = S;
     __shared__ double sh[4 * 4];
     int c, v0, v1;
     if (!chunk_block(p, p.vch, c, v0, v1)) return;
     const CellSide *cs = p.cs + 4 * c;
-    const T h = (T)p.h;
     const int TW = p.nvx + p.nvy;
     S *MG = (S *)p.d1 + ((size_t)c * 2) * p.nvp, *MH = MG + p.nvp;
     double mw[4] = {0.0, 0.0, 0.0, 0.0};
     for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
         const int ix = p.vix[v], iy = p.viy[v];
         const T x = (T)p.xi[v], y = (T)p.eta[v];
-        const S *gr = (const S *)p.gr + (size_t)c * 6 * p.nvp + v;
-        const T bG = gr[0], gxG = gr[p.nvp], gyG = gr[2 * p.nvp];
-        const T bH = gr[3 * p.nvp], gxH = gr[4 * p.nvp], gyH = gr[5 * p.nvp];
         T accG = T(0), accH = T(0);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -562,20 +577,12 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
             const bool mine = und > 0.0 || (und == 0.0 && cs[s].tie);
             const T un = (T)und;
             T fG, fH;
-            if (mine) {
-                const T rx = (T)cs[s].dx - h * x, ry = (T)cs[s].dy - h * y;
-                fG = bG + gxG * rx + gyG * ry;
-                fH = bH + gxH * rx + gyH * ry;
-            } else if (type == FT_INTERIOR) {
-                const S *ng = (const S *)p.gr + (size_t)cs[s].nb * 6 * p.nvp + v;
-                const T nG = ng[0], ngxG = ng[p.nvp], ngyG = ng[2 * p.nvp];
-                const T nH = ng[3 * p.nvp], ngxH = ng[4 * p.nvp], ngyH = ng[5 * p.nvp];
-                const T rx = (T)(cs[s].dx - cs[s].ndx) - h * x;
-                const T ry = (T)(cs[s].dy - cs[s].ndy) - h * y;
-                fG = nG + ngxG * rx + ngyG * ry;
-                fH = nH + ngxH * rx + ngyH * ry;
+            if (mine || type == FT_INTERIOR) {  // reconstructed by the upwind cell
+                const S *fv = (const S *)p.fv + (size_t)k * 2 * p.nvp + v;
+                fG = fv[0];
+                fH = fv[p.nvp];
             } else if (type == FT_WALL) {
-                const T rw = (T)p.recf[k].rw;
+                const T rw = ((const S *)p.recfT)[(size_t)k * RT_N + 13];
                 const T g = (T)p.gw[(size_t)cs[s].wside * p.nvp + v];
                 fG = rw * g;
                 fH = rw * (T)p.wKRT[cs[s].wside] * g;
@@ -583,11 +590,11 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
                 fG = (T)p.ginf[v];
                 fH = (T)p.hinf[v];
             }
-            const RecT<T> rf = load_rec<T>(p.recf[k]);
+            const RecT<T> rf = load_recT<S>(p.recfT, k);
             const S *tf = (const S *)p.tabf + (size_t)k * TW;
             T eG, eH;
             eq_eval<T, SHAK>(rf, x, y, (T)tf[ix] * (T)tf[p.nvx + iy], eG, eH);
-            const T al = (T)p.recf[k].alpha;
+            const T al = ((const S *)p.recfT)[(size_t)__builtin_amdgcn_readfirstlane(k) * RT_N + 12];
             const T pG = al * fG + (T(1) - al) * eG, pH = al * fH + (T(1) - al) * eH;
             const T fl = (T)cs[s].S * un;
             accG -= fl * pG;
@@ -1423,9 +1430,7 @@ __global__ __launch_bounds__(256) void k_adj_face(Params p) {
     const double *tf = (const double *)p.tabf + (size_t)k * (p.nvx + p.nvy);
     const double h = p.h, al = r.alpha, S = cL.S, sc = p.scal[SC_SCALE];
     (void)sc;
-    const double *gL = (const double *)p.gr + (size_t)F.L * 6 * p.nvp;
-    const double *gR = F.type == FT_INTERIOR ? (const double *)p.gr + (size_t)F.R * 6 * p.nvp : gL;
-    const CellSide cR = F.type == FT_INTERIOR ? p.cs[4 * F.R + F.sR] : cL;
+    const double *fvG = (const double *)p.fv + (size_t)k * 2 * p.nvp, *fvH = fvG + p.nvp;
     const double *lL = p.lam + (size_t)F.L * 2 * p.nvp;
     const double *lR = F.type == FT_INTERIOR ? p.lam + (size_t)F.R * 2 * p.nvp : nullptr;
     const int ws = F.type == FT_WALL ? F.wside : 0;
@@ -1439,14 +1444,9 @@ __global__ __launch_bounds__(256) void k_adj_face(Params p) {
         const double un = normal_speed(x, y, cL.nx, cL.ny);
         const bool mineL = un > 0.0 || (un == 0.0 && cL.tie);
         double fG, fH;
-        if (mineL) {
-            const double rx = cL.dx - h * x, ry = cL.dy - h * y;
-            fG = gL[v] + gL[p.nvp + v] * rx + gL[2 * p.nvp + v] * ry;
-            fH = gL[3 * p.nvp + v] + gL[4 * p.nvp + v] * rx + gL[5 * p.nvp + v] * ry;
-        } else if (F.type == FT_INTERIOR) {
-            const double rx = cR.dx - h * x, ry = cR.dy - h * y;
-            fG = gR[v] + gR[p.nvp + v] * rx + gR[2 * p.nvp + v] * ry;
-            fH = gR[3 * p.nvp + v] + gR[4 * p.nvp + v] * rx + gR[5 * p.nvp + v] * ry;
+        if (mineL || F.type == FT_INTERIOR) {  // reconstructed by the upwind cell
+            fG = fvG[v];
+            fH = fvH[v];
         } else if (F.type == FT_WALL) {
             fG = r.rw * gw[v];
             fH = r.rw * KRTw * gw[v];
@@ -1482,8 +1482,7 @@ __global__ __launch_bounds__(256) void k_adj_face(Params p) {
             const double x = p.xi[v], y = p.eta[v];
             const double un = normal_speed(x, y, cL.nx, cL.ny);
             const bool mineL = un > 0.0;
-            const double fG = mineL ? gL[v] + gL[p.nvp + v] * (cL.dx - h * x) + gL[2 * p.nvp + v] * (cL.dy - h * y)
-                                    : r.rw * gw[v];
+            const double fG = mineL ? fvG[v] : r.rw * gw[v];
             const double M = tf[p.vix[v]] * tf[p.nvx + p.viy[v]];
             const RecT<double> rr = load_rec<double>(r);
             double eG, eH;
@@ -1827,13 +1826,8 @@ hipError_t launch_face_records(const Params &p, bool fp32, hipStream_t st) {
 hipError_t launch_flux(const Params &p, bool fp32, hipStream_t st) {
     const dim3 g = chunk_grid(p, p.nch);
     DISPATCH_S(fp32, {
-        if (p.model == 1) {
-            if (p.limiter) hipLaunchKernelGGL((k_flux<S, true, true>), g, dim3(256), 0, st, p);
-            else hipLaunchKernelGGL((k_flux<S, true, false>), g, dim3(256), 0, st, p);
-        } else {
-            if (p.limiter) hipLaunchKernelGGL((k_flux<S, false, true>), g, dim3(256), 0, st, p);
-            else hipLaunchKernelGGL((k_flux<S, false, false>), g, dim3(256), 0, st, p);
-        }
+        if (p.model == 1) hipLaunchKernelGGL((k_flux<S, true>), g, dim3(256), 0, st, p);
+        else hipLaunchKernelGGL((k_flux<S, false>), g, dim3(256), 0, st, p);
     });
     if (p.nch > 1) return combine(p.MWc, p.MW, p, 4, st);
     return hipGetLastError();
