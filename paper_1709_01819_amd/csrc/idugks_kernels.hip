@@ -877,10 +877,10 @@ __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
 constexpr int STG = 24;  // staged values per cell: record (12), nx S (4), ny S (4), codes (4)
 constexpr int RING = 3;
 
-template <class S>
+template <class S, int VPL>
 struct SweepItem {
-    S aG, aH, bG, bH, e1, e2;     // forward: M, phi~ (G, H), factored Maxwellian;
-                                  // backward: increment, phi~
+    S aG[VPL], aH[VPL], bG[VPL], bH[VPL];  // forward: M, phi~ (G, H); backward: increment, phi~
+    S e1[VPL], e2[VPL];                    // forward: factored Maxwellian
 };
 
 // Staging of the micro sweeps: staging lane sl copies column r = sl % STG of the staged
@@ -939,15 +939,19 @@ DEV void sweep_stage(const StageCol<UPPER> &col, const T (&reg)[SPW_MICRO], T *d
 // ADJ: the transposed operator of the adjoint iteration (FP64): the couplings run along
 // the outflow side (xi.n > 0) of the lower / upper neighbours, the right-hand side of the
 // ascending sweep is d1 itself and the descending sweep writes its result to d1.
-template <class S, bool SHAK, bool UPPER, bool ADJ>
+// VPL: velocities per compute lane (the block's slice has W = vb VPL velocities; lane
+// (slot, vl) takes the columns vl, vl + vb, ...): the staged row, the coupling weights
+// and all per-hyperplane arithmetic are shared by them, and their chains are independent.
+template <class S, bool SHAK, bool UPPER, bool ADJ, int VPL>
 __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
     using T = S;
     extern __shared__ unsigned char lds_raw[];
     const int ni = p.ni, nj = p.nj, nh = ni + nj - 1, L = ni < nj ? ni : nj;
-    // one species' fronts: [pad][f0][pad][f1][pad][wI][wJ], the pads (vb values) taking the
+    const int W = vb * VPL;
+    // one species' fronts: [pad][f0][pad][f1][pad][wI][wJ], the pads (W values) taking the
     // reads of the columns -1 and ni of lanes on the hyperplane's first and last cell
-    const int FR = (3 * ni + nj + 3) * vb;
-    T *f0 = (T *)lds_raw + vb, *f1 = f0 + (ni + 1) * vb, *wI = f1 + (ni + 1) * vb, *wJ = wI + nj * vb;
+    const int FR = (3 * ni + nj + 3) * W;
+    T *f0 = (T *)lds_raw + W, *f1 = f0 + (ni + 1) * W, *wI = f1 + (ni + 1) * W, *wJ = wI + nj * W;
     T *st0 = (T *)lds_raw + 2 * FR, *st1 = st0 + L * STG;
     int *hpo = (int *)(st1 + L * STG);
     for (int h = threadIdx.x; h <= nh; h += blockDim.x) hpo[h] = p.hp_off[h];
@@ -996,58 +1000,72 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
     // the state and the tables.  (Velocities past nv lie in the padding of the velocity
     // arrays; those lanes compute but store nothing.)
     const int vl = threadIdx.x % vb, slot = threadIdx.x / vb;
-    const int v = xcd_remap(blockIdx.x, gridDim.x) * vb + vl;
-    const bool vok = slot < L && v < p.nv;
+    const int v = xcd_remap(blockIdx.x, gridDim.x) * W + vl;  // velocity u: v + u vb
     const int kk = slot < L ? slot : L - 1;
     const int nv2 = 2 * p.nvp, ntb = p.nvx + p.nvy;
-    const int kc = kk * (ni - 1) * nv2, kt = kk * (ni - 1) * ntb, ks = slot * vb;
-    const T x = (T)p.xi[v], y = (T)p.eta[v];
-    const int ix = p.vix[v], iy = p.viy[v];
+    const int kc = kk * (ni - 1) * nv2, kt = kk * (ni - 1) * ntb, ks = slot * W;
+    bool vok[VPL];
+    T x[VPL], y[VPL];
+    int ix[VPL], iy[VPL];
+#pragma unroll
+    for (int u = 0; u < VPL; ++u) {
+        const int vu = v + u * vb;
+        vok[u] = slot < L && vu < p.nv;
+        x[u] = (T)p.xi[vu];
+        y[u] = (T)p.eta[vu];
+        ix[u] = p.vix[vu];
+        iy[u] = p.viy[vu];
+    }
     const T sc = (T)p.scal[SC_SCALE];
-    const int need = UPPER ? SG_UPPER : SG_LOWER;
-    T gwv[4] = {T(0), T(0), T(0), T(0)}, kw[4] = {T(0), T(0), T(0), T(0)};
+    T gwv[VPL][4] = {}, kw[4] = {T(0), T(0), T(0), T(0)};
     if (UPPER && !ADJ) {
 #pragma unroll
         for (int sd = 0; sd < 4; ++sd) {
-            gwv[sd] = (T)p.gw[(size_t)sd * p.nvp + v];
             kw[sd] = (T)p.wKRT[sd];
+#pragma unroll
+            for (int u = 0; u < VPL; ++u) gwv[u][sd] = (T)p.gw[(size_t)sd * p.nvp + v + u * vb];
         }
     }
     auto state_off = [&](int h, int lo, int hi) {
         return (hi + (h - hi) * ni) * nv2 + max((hi - lo) * (ni - 1) * nv2 - kc, 0) + v;
     };
-    auto load = [&](SweepItem<S> &it, int t) {
+    auto load = [&](SweepItem<S, VPL> &it, int t) {
         const int h = hp(t < nh ? t : nh - 1);
         int lo, hi;
         hp_bounds(h, ni, nj, lo, hi);
         const unsigned o = state_off(h, lo, hi);
-        const S *a = (const S *)p.d1 + o;
-        it.aG = a[0];
-        it.aH = a[p.nvp];
-        if (!ADJ) {
-            const S *b = (const S *)p.f + o;
-            it.bG = b[0];
-            it.bH = b[p.nvp];
+        const S *a = (const S *)p.d1 + o, *b = (const S *)p.f + o;
+#pragma unroll
+        for (int u = 0; u < VPL; ++u) {
+            it.aG[u] = a[u * vb];
+            it.aH[u] = a[p.nvp + u * vb];
+            if (!ADJ) {
+                it.bG[u] = b[u * vb];
+                it.bH[u] = b[p.nvp + u * vb];
+            }
         }
         if (!UPPER && !ADJ) {
             const unsigned ot = (hi + (h - hi) * ni) * ntb + max((hi - lo) * (ni - 1) * ntb - kt, 0);
             const S *tb = (const S *)p.tabs + ot;
-            it.e1 = tb[ix];
-            it.e2 = tb[p.nvx + iy];
+#pragma unroll
+            for (int u = 0; u < VPL; ++u) {
+                it.e1[u] = tb[ix[u]];
+                it.e2[u] = tb[p.nvx + iy[u]];
+            }
         }
     };
-    SweepItem<S> ring[RING];
+    SweepItem<S, VPL> ring[RING];
 #pragma unroll
     for (int d = 0; d < RING; ++d) load(ring[d], d);
     lds_barrier();
     // One step: the hyperplane t with ring slot d.  Full groups of RING steps are unrolled
     // without guards, so that the waits for a slot's loads are exact; the tail is guarded.
-    auto step = [&](const int t, SweepItem<S> &cur) {
+    auto step = [&](const int t, SweepItem<S, VPL> &cur) {
         const int h = hp(t);
         int lo, hi;
         hp_bounds(h, ni, nj, lo, hi);
         if (slot <= hi - lo) {
-            const int fi = lo * vb + ks + vl, fj = (h - lo) * vb - ks + vl;  // i vb + vl, j vb + vl
+            const int fi = lo * W + ks + vl, fj = (h - lo) * W - ks + vl;  // i W + vl, j W + vl
             const T *m = ((t & 1) ? st1 : st0) + slot * STG;
             // The staged row, then the one neighbour increment each side can couple to in
             // this direction (sides i-, i+, j-, j+): forward f0[i-1], wI[j], f0[i], wJ[i];
@@ -1057,74 +1075,86 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
 #pragma unroll
             for (int e = 0; e < STG; ++e) mr[e] = m[e];
             const T *sp[4];
-            if (UPPER) { sp[0] = wI + fj; sp[1] = f0 + fi + vb; sp[2] = wJ + fi; sp[3] = f0 + fi; }
-            else { sp[0] = f0 + fi - vb; sp[1] = wI + fj; sp[2] = f0 + fi; sp[3] = wJ + fi; }
-            T fg[4], fh[4];
+            if (UPPER) { sp[0] = wI + fj; sp[1] = f0 + fi + W; sp[2] = wJ + fi; sp[3] = f0 + fi; }
+            else { sp[0] = f0 + fi - W; sp[1] = wI + fj; sp[2] = f0 + fi; sp[3] = wJ + fi; }
+            T fg[VPL][4], fh[VPL][4];
 #pragma unroll
-            for (int sd = 0; sd < 4; ++sd) {
-                fg[sd] = sp[sd][0];
-                fh[sd] = sp[sd][FR];
-            }
-            T D = mr[11], sG, sH;
-            if (!UPPER && ADJ) {
-                sG = cur.aG;
-                sH = cur.aH;
-            } else if (!UPPER) {
-                RecT<T> r;
+            for (int u = 0; u < VPL; ++u)
+#pragma unroll
+                for (int sd = 0; sd < 4; ++sd) {
+                    fg[u][sd] = sp[sd][u * vb];
+                    fh[u][sd] = sp[sd][FR + u * vb];
+                }
+            RecT<T> r;
+            if (!UPPER && !ADJ) {
                 r.U = mr[0]; r.V = mr[1]; r.c0 = mr[2]; r.c1 = mr[3]; r.c2c = mr[4]; r.c3 = mr[5];
                 r.kqx = mr[6]; r.kqy = mr[7]; r.iRT = mr[8]; r.KRT = mr[9];
-                T eG, eH;
-                eq_eval<T, SHAK>(r, x, y, cur.e1 * cur.e2, eG, eH);
-                sG = cur.aG - mr[10] * (sc * cur.bG - eG);
-                sH = cur.aH - mr[10] * (sc * cur.bH - eH);
-            } else {
-                sG = sH = T(0);
             }
-            // per side, by weights instead of branches: outflow (xi.n > 0) adds to the
-            // diagonal; inflow from a coupled neighbour adds its increment, inflow through a
-            // wall (backward sweep) the ghost's; the transposed operator couples along the
-            // outflow instead.  A weight of 0 adds an exact 0 (all fronts are finite).
+            T dG[VPL], dH[VPL];
 #pragma unroll
-            for (int sd = 0; sd < 4; ++sd) {
-                const T unS = x * mr[SR_N + sd] + y * mr[SR_N + 4 + sd];  // (xi.n) S
-                const T uo = fmax(unS, T(0)), ui = fmin(unS, T(0));
-                D += uo;
-                const T uc = (ADJ ? uo : ui) * mr[SR_N + 8 + sd];
-                if (ADJ) {
-                    sG += uc * fg[sd];
-                    sH += uc * fh[sd];
+            for (int u = 0; u < VPL; ++u) {
+                T D = mr[11], sG, sH;
+                if (!UPPER && ADJ) {
+                    sG = cur.aG[u];
+                    sH = cur.aH[u];
+                } else if (!UPPER) {
+                    T eG, eH;
+                    eq_eval<T, SHAK>(r, x[u], y[u], cur.e1[u] * cur.e2[u], eG, eH);
+                    sG = cur.aG[u] - mr[10] * (sc * cur.bG[u] - eG);
+                    sH = cur.aH[u] - mr[10] * (sc * cur.bH[u] - eH);
                 } else {
-                    sG -= uc * fg[sd];
-                    sH -= uc * fh[sd];
+                    sG = sH = T(0);
                 }
-                if (UPPER && !ADJ) {  // the ghost density increment is 0 off the walls
-                    const T gw = -gwv[sd] * mr[sd] * ui;
-                    sG += gw;
-                    sH += gw * kw[sd];
+                // per side, by weights instead of branches: outflow (xi.n > 0) adds to the
+                // diagonal; inflow from a coupled neighbour adds its increment, inflow
+                // through a wall (backward sweep) the ghost's; the transposed operator
+                // couples along the outflow instead.  A weight of 0 adds an exact 0 (all
+                // fronts are finite).
+#pragma unroll
+                for (int sd = 0; sd < 4; ++sd) {
+                    const T unS = x[u] * mr[SR_N + sd] + y[u] * mr[SR_N + 4 + sd];  // (xi.n) S
+                    const T uo = fmax(unS, T(0)), ui = fmin(unS, T(0));
+                    D += uo;
+                    const T uc = (ADJ ? uo : ui) * mr[SR_N + 8 + sd];
+                    if (ADJ) {
+                        sG += uc * fg[u][sd];
+                        sH += uc * fh[u][sd];
+                    } else {
+                        sG -= uc * fg[u][sd];
+                        sH -= uc * fh[u][sd];
+                    }
+                    if (UPPER && !ADJ) {  // the ghost density increment is 0 off the walls
+                        const T gw = -gwv[u][sd] * mr[sd] * ui;
+                        sG += gw;
+                        sH += gw * kw[sd];
+                    }
                 }
+                const T iD = T(1) / D;
+                dG[u] = UPPER ? cur.aG[u] + sG * iD : sG * iD;
+                dH[u] = UPPER ? cur.aH[u] + sH * iD : sH * iD;
             }
-            const T iD = T(1) / D;
-            const T dG = UPPER ? cur.aG + sG * iD : sG * iD;
-            const T dH = UPPER ? cur.aH + sH * iD : sH * iD;
-            if (vok) {
-                const unsigned o = state_off(h, lo, hi);
+            const unsigned o = state_off(h, lo, hi);
+            const int i = lo + slot, j = h - i;
+#pragma unroll
+            for (int u = 0; u < VPL; ++u) {
+                if (!vok[u]) continue;
                 if (UPPER && !ADJ) {
-                    ((S *)p.f)[o] = (S)(sc * cur.bG + dG);
-                    ((S *)p.f)[o + p.nvp] = (S)(sc * cur.bH + dH);
+                    ((S *)p.f)[o + u * vb] = (S)(sc * cur.bG[u] + dG[u]);
+                    ((S *)p.f)[o + p.nvp + u * vb] = (S)(sc * cur.bH[u] + dH[u]);
                 } else {
-                    ((S *)p.d1)[o] = (S)dG;
-                    ((S *)p.d1)[o + p.nvp] = (S)dH;
+                    ((S *)p.d1)[o + u * vb] = (S)dG[u];
+                    ((S *)p.d1)[o + p.nvp + u * vb] = (S)dH[u];
                 }
-                f1[fi] = dG;
-                f1[FR + fi] = dH;
+                const int fu = fi + u * vb;
+                f1[fu] = dG[u];
+                f1[FR + fu] = dH[u];
                 // the seam copies: a cell off the seam column / row writes its f1 value again
-                const int i = lo + slot, j = h - i;
-                T *qI = i == (UPPER ? ni - 1 : 0) ? wI + fj : f1 + fi;
-                T *qJ = j == (UPPER ? nj - 1 : 0) ? wJ + fi : f1 + fi;
-                qI[0] = dG;
-                qI[FR] = dH;
-                qJ[0] = dG;
-                qJ[FR] = dH;
+                T *qI = i == (UPPER ? ni - 1 : 0) ? wI + fj + u * vb : f1 + fu;
+                T *qJ = j == (UPPER ? nj - 1 : 0) ? wJ + fu : f1 + fu;
+                qI[0] = dG[u];
+                qI[FR] = dH[u];
+                qJ[0] = dG[u];
+                qJ[FR] = dH[u];
             }
         }
         // the slot's loads were issued RING steps ago; it is refilled only after use, so
@@ -1895,38 +1925,60 @@ SweepShape sweep_shape(int ni, int nj, int nv, size_t s_bytes) {
     // staging waves: KP = 64 nsw / STG cells per pass, SPW_MICRO passes must cover L cells
     int nsw = 1;
     while ((64 * nsw / STG) * SPW_MICRO < L) ++nsw;
-    SweepShape best{0, 0, 0, 0};
+    auto lds_of = [&](int w) {
+        return ((size_t)2 * (3 * ni + nj + 3) * w + (size_t)2 * L * STG) * s_bytes + (size_t)(nh + 1) * sizeof(int);
+    };
+    SweepShape best{0, 0, 0, 0, 0};
     for (int vb = 16; vb >= 1; vb /= 2) {
         SweepShape c;
         c.vb = vb;
+        c.vpl = 1;
         c.nct = round64(vb * L);
         c.threads = c.nct + 64 * nsw;
-        c.lds = ((size_t)2 * (3 * ni + nj + 3) * vb + (size_t)2 * L * STG) * s_bytes + (size_t)(nh + 1) * sizeof(int);
+        c.lds = lds_of(vb);
         if (c.threads > 1024 || c.lds > 150 * 1024) continue;
         best = c;
         if ((nv + vb - 1) / vb >= 192) break;
     }
+    // FP32 with slices to spare: two velocities per lane halve the slices, and each staged
+    // row serves twice the velocities
+    if (best.vb && s_bytes == 4) {
+        SweepShape c = best;
+        c.vpl = 2;
+        c.lds = lds_of(2 * c.vb);
+        if (c.lds <= 150 * 1024 && (nv + 2 * c.vb - 1) / (2 * c.vb) >= 1024) best = c;
+    }
     return best;
 }
 
-hipError_t launch_sweep(const Params &p, bool fp32, bool upper, const SweepShape &sh, hipStream_t st) {
-    const dim3 g((p.nv + sh.vb - 1) / sh.vb);
-    DISPATCH_S(fp32, {
-        const void *fn = !upper ? (p.model == 1 ? (const void *)k_sweep<S, true, false, false> : (const void *)k_sweep<S, false, false, false>)
-                                : (p.model == 1 ? (const void *)k_sweep<S, true, true, false> : (const void *)k_sweep<S, false, true, false>);
-        if (sh.lds > 64 * 1024) {
-            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
-            if (e != hipSuccess) return e;
-        }
-        if (!upper) {
-            if (p.model == 1) hipLaunchKernelGGL((k_sweep<S, true, false, false>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
-            else hipLaunchKernelGGL((k_sweep<S, false, false, false>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
-        } else {
-            if (p.model == 1) hipLaunchKernelGGL((k_sweep<S, true, true, false>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
-            else hipLaunchKernelGGL((k_sweep<S, false, true, false>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
-        }
-    });
+template <class S, bool SHAK, bool UPPER, bool ADJ, int VPL>
+static hipError_t sweep_launch(const Params &p, const SweepShape &sh, hipStream_t st) {
+    const void *fn = (const void *)k_sweep<S, SHAK, UPPER, ADJ, VPL>;
+    if (sh.lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
+        if (e != hipSuccess) return e;
+    }
+    const dim3 g((p.nv + sh.vb * VPL - 1) / (sh.vb * VPL));
+    hipLaunchKernelGGL((k_sweep<S, SHAK, UPPER, ADJ, VPL>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
     return hipGetLastError();
+}
+
+// two velocities per lane exist for the FP32 state only
+template <class S, bool SHAK, bool UPPER>
+static hipError_t sweep_launch_v(const Params &p, const SweepShape &sh, hipStream_t st) {
+    if constexpr (sizeof(S) == 4) {
+        if (sh.vpl == 2) return sweep_launch<S, SHAK, UPPER, false, 2>(p, sh, st);
+    }
+    return sweep_launch<S, SHAK, UPPER, false, 1>(p, sh, st);
+}
+
+hipError_t launch_sweep(const Params &p, bool fp32, bool upper, const SweepShape &sh, hipStream_t st) {
+    if (!fp32 && sh.vpl != 1) return hipErrorInvalidValue;
+    DISPATCH_S(fp32, {
+        if (p.model == 1) return upper ? sweep_launch_v<S, true, true>(p, sh, st) : sweep_launch_v<S, true, false>(p, sh, st);
+        return upper ? sweep_launch_v<S, false, true>(p, sh, st) : sweep_launch_v<S, false, false>(p, sh, st);
+    });
+    return hipSuccess;
 }
 
 hipError_t launch_wall_ghost(const Params &p, bool fp32, hipStream_t st) {
@@ -2000,15 +2052,9 @@ hipError_t launch_adj_theta(const Params &p, double *out, hipStream_t st) {
 }
 
 hipError_t launch_adj_sweep(const Params &p, bool upper, const SweepShape &sh, hipStream_t st) {
-    const dim3 g((p.nv + sh.vb - 1) / sh.vb);
-    const void *fn = upper ? (const void *)k_sweep<double, false, true, true> : (const void *)k_sweep<double, false, false, true>;
-    if (sh.lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
-        if (e != hipSuccess) return e;
-    }
-    if (upper) hipLaunchKernelGGL((k_sweep<double, false, true, true>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
-    else hipLaunchKernelGGL((k_sweep<double, false, false, true>), g, dim3(sh.threads), sh.lds, st, p, sh.vb, sh.nct);
-    return hipGetLastError();
+    if (sh.vpl != 1) return hipErrorInvalidValue;  // the sensitivities run on the FP64 state
+    return upper ? sweep_launch<double, false, true, true, 1>(p, sh, st)
+                 : sweep_launch<double, false, false, true, 1>(p, sh, st);
 }
 
 hipError_t launch_adj_diag(const Params &p, hipStream_t st) {

@@ -21,8 +21,8 @@ struct MacroShape {
     size_t lds;
 };
 struct SweepShape {
-    int vb, nct, threads;  // vb = 0: no shape fits
-    size_t lds;
+    int vb, vpl, nct, threads;  // velocity columns per slot and velocities per lane;
+    size_t lds;                 // vb = 0: no shape fits
 };
 MacroShape macro_shape(int ni, int nj);
 SweepShape sweep_shape(int ni, int nj, int nv, size_t s_bytes);

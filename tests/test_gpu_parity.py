@@ -163,9 +163,17 @@ def test_c2_fp32_mixed_converged_fields(c2_oracle_converged):
     assert max(errs) <= 1e-5
 
 
-@pytest.mark.parametrize("name", ["cavity_tanh", "cavity_shakhov_nc", "cylinder_limiter"])
+# 181^2 velocities on 5 x 4 cells: the FP32 sweeps take two velocities per lane (1024
+# slices of 2 x 16, the last one ragged)
+FP32_CASES = dict(CASES, cavity_shakhov_vpl2=lambda: wl.cavity(
+    n=5, nj=4, stretch=None, nv=181, quad=wl.NEWTON_COTES, vmax=4.0, Kn=1.0, model=wl.SHAKHOV,
+    Pr=2 / 3, K=1))
+
+
+@pytest.mark.parametrize("name", ["cavity_tanh", "cavity_shakhov_nc", "cylinder_limiter",
+                                  "cavity_shakhov_vpl2"])
 def test_fp32_mixed_step_close_to_fp64_oracle(name):
-    cfg = CASES[name]()
+    cfg = FP32_CASES[name]()
     cfg["precision"] = wl.FP32_MIXED
     o, g = _pair(cfg, seed=8)
     o.implicit_step(2)
