@@ -605,7 +605,7 @@ idugks_status build(const idugks_config *c, Built &b) {
 enum Region {
     R_CS, R_FACES, R_WALLF, R_AREA, R_XI, R_ETA, R_W, R_X1, R_WX1, R_Y1, R_WY1, R_VIX, R_VIY,
     R_GW, R_WKRT, R_GINF, R_HINF, R_WDEN, R_BHALF, R_F, R_D1, R_TAB, R_TABS, R_TABF, R_REC,
-    R_RECS, R_RECF, R_PART, R_RAW, R_WC, R_MW, R_DW, R_DWD, R_DTIMP, R_RHOOLD, R_DRHO, R_SCAL,
+    R_RECS, R_RECF, R_FIELDS, R_RAW, R_WC, R_MW, R_DW, R_DWD, R_DTIMP, R_RHOOLD, R_DRHO, R_SCAL,
     R_STAGE, R_HPOFF, R_HPPOS, R_SGEO, R_SREC, R_SDRHO, R_MH, R_FV, R_MWC, R_RECT, R_RECFT,
     // sensitivities (empty unless BGK, no limiter, FP64)
     R_LT, R_GJ, R_FBAR, R_YBUF, R_AGR, R_FADJ, R_CADJ, R_DGW, R_DWDEN, R_JACC, R_JACF, R_RED,
@@ -635,7 +635,7 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
         8 * 4 * (size_t)nvp, 8 * 4, 8 * (size_t)nvp, 8 * (size_t)nvp, 8 * (size_t)nf, 8 * (size_t)nf * NM_MAX,
         S * 2 * (size_t)nc * nvp, S * 2 * (size_t)nc * nvp, S * (size_t)nc * TW, S * (size_t)nc * TW,
         S * (size_t)nf * TW, sizeof(Rec) * (size_t)nc, sizeof(Rec) * (size_t)nc, sizeof(Rec) * (size_t)nf,
-        8 * (size_t)nc * 4 * NM_MAX, 8 * (size_t)nc * NM_MAX, 8 * 4 * (size_t)nc, 8 * 4 * (size_t)nc,
+        8 * (size_t)nc * 8, 8 * (size_t)nc * NM_MAX, 8 * 4 * (size_t)nc, 8 * 4 * (size_t)nc,
         8 * 4 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nc, 8 * (size_t)nf, 8 * SC_NUM,
         8 * (size_t)std::max(nc, 2) * nvp, sizeof(int) * (size_t)(nc + 2), sizeof(int) * (size_t)nc,
         8 * (size_t)SG_N * ncs, 8 * (size_t)SR_N * ncs, 8 * 4 * (size_t)ncs, 8 * (size_t)MH_N * ncs,
@@ -821,7 +821,7 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     p.wden = (const double *)R(R_WDEN); p.bhalf = (const double *)R(R_BHALF);
     p.f = R(R_F); p.d1 = R(R_D1); p.tab = R(R_TAB); p.tabs = R(R_TABS); p.tabf = R(R_TABF);
     p.rec = (Rec *)R(R_REC); p.recs = (Rec *)R(R_RECS); p.recf = (Rec *)R(R_RECF);
-    p.part = (double *)R(R_PART); p.raw = (double *)R(R_RAW); p.Wc = (double *)R(R_WC);
+    p.fields = (double *)R(R_FIELDS); p.raw = (double *)R(R_RAW); p.Wc = (double *)R(R_WC);
     p.MW = (double *)R(R_MW); p.dW = (double *)R(R_DW); p.DWd = (double *)R(R_DWD);
     p.dtimp = (double *)R(R_DTIMP); p.rho_old = (double *)R(R_RHOOLD); p.drho = (double *)R(R_DRHO);
     p.scal = (double *)R(R_SCAL);
@@ -1173,8 +1173,8 @@ idugks_status idugks_residual(idugks_ctx *x, double out_l2[4]) {
 idugks_status idugks_moments(idugks_ctx *x, double *out, int32_t out_on_host) {
     if (!x || !out) return fail(IDUGKS_E_INVALID, "null argument");
     HIPCHK(launch_raw(x->p, x->fp32, NM_MAX, x->st));
-    HIPCHK(launch_fields(x->p, x->p.part, x->st));
-    return copy_out(x, out, x->p.part, sizeof(double) * 8 * x->p.nc, out_on_host);
+    HIPCHK(launch_fields(x->p, x->p.fields, x->st));
+    return copy_out(x, out, x->p.fields, sizeof(double) * 8 * x->p.nc, out_on_host);
 }
 
 idugks_status idugks_get_state(idugks_ctx *x, double *f, int32_t on_host) {

@@ -116,7 +116,8 @@ struct Params {
                              // upwind cell; written by the face-partial kernel for every
                              // velocity whose upwind side is a cell)
     Rec *rec, *recs, *recf;
-    double *part, *raw, *Wc, *MW, *dW, *DWd, *dtimp, *rho_old, *drho, *scal;
+    double *fields;          // [nc][8] cell fields returned by idugks_moments
+    double *raw, *Wc, *MW, *dW, *DWd, *dtimp, *rho_old, *drho, *scal;
     double *MWc;             // [nc][nch][4] per-chunk sums of MW (nch > 1)
     // per-cell data of the sweeps stored in i+j hyperplane order (position hp_pos[c]), so
     // that the cells of one hyperplane are contiguous and can be staged into LDS at once

@@ -139,7 +139,7 @@ DEV const S *rowp(const Params &p, const void *a, int c, int s) {
 
 // Raw moments of a pair at one velocity, accumulated in double.
 template <int NM>
-DEV void acc_moments(double (&a)[NM], double w, double x, double y, double G, double H) {
+DEV void acc_moments(double *a, double w, double x, double y, double G, double H) {
     const double wG = w * G, wH = w * H, q2 = x * x + y * y;
     a[0] += wG;
     a[1] += wG * x;
@@ -465,46 +465,33 @@ DEV void recon_cell(const Params &p, int j, int v, int ix, int iy, T x, T y, T s
 }
 
 // ---------------------------------------------------------------------------------------
-// partial face moments: each cell reduces, for each of its faces, the moments of the
-// reconstructed phi-bar over the velocities for which it is the upwind cell
+// face values: per (cell, velocity) the reconstruction of phi-bar-plus (value, limited
+// gradient), then at each face the cell is upwind of, the reconstructed phi-bar stored
+// for the face-record and flux kernels
 // ---------------------------------------------------------------------------------------
 template <class S, bool SHAK, bool LIM>
 __global__ __launch_bounds__(256) void k_partials(Params p) {
     using T = S;
-    constexpr int NM = SHAK ? NM_SHAKHOV : NM_BGK;
-    __shared__ double sh[4 * 4 * NM];
     int c, v0, v1;
     if (!chunk_block(p, p.nv, c, v0, v1)) return;
     const CellSide *cs = p.cs + 4 * c;
     const T sc = (T)p.scal[SC_SCALE], h = (T)p.h;
-    double acc[4 * NM];
-#pragma unroll
-    for (int m = 0; m < 4 * NM; ++m) acc[m] = 0.0;
     for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
         const int ix = p.vix[v], iy = p.viy[v];
         const T x = (T)p.xi[v], y = (T)p.eta[v];
         T bG, bH, gxG, gyG, gxH, gyH;
         recon_cell<S, T, SHAK, LIM>(p, c, v, ix, iy, x, y, sc, bG, bH, gxG, gyG, gxH, gyH);
-        const double wv = p.w[v];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             if (cs[s].type == FT_SELF) continue;
             const double un = normal_speed(p.xi[v], p.eta[v], cs[s].nx, cs[s].ny);
             if (!(un > 0.0 || (un == 0.0 && cs[s].tie))) continue;
             const T rx = (T)cs[s].dx - h * x, ry = (T)cs[s].dy - h * y;
-            const T G = bG + gxG * rx + gyG * ry, H = bH + gxH * rx + gyH * ry;
             S *fv = (S *)p.fv + (size_t)cs[s].face * 2 * p.nvp + v;
-            fv[0] = (S)G;
-            fv[p.nvp] = (S)H;
-            double a[NM];
-#pragma unroll
-            for (int m = 0; m < NM; ++m) a[m] = 0.0;
-            acc_moments<NM>(a, wv, (double)x, (double)y, (double)G, (double)H);
-#pragma unroll
-            for (int m = 0; m < NM; ++m) acc[s * NM + m] += a[m];
+            fv[0] = (S)(bG + gxG * rx + gyG * ry);
+            fv[p.nvp] = (S)(bH + gxH * rx + gyH * ry);
         }
     }
-    block_sum_store<4 * NM>(acc, sh, p.part + (size_t)c * 4 * NM);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -519,14 +506,24 @@ __global__ __launch_bounds__(256) void k_face_records(Params p) {
     if (k >= p.nf) return;
     const Face F = p.faces[k];
     if (F.type == FT_SELF) return;
+    // moments of the stored face values: every velocity at an interior face, the outflow
+    // half (the interior cell upwind) at a boundary face
+    const CellSide cL = p.cs[4 * F.L + F.sL];
+    const S *fvG = (const S *)p.fv + (size_t)k * 2 * p.nvp, *fvH = fvG + p.nvp;
     double m[NM];
-    const double *a = p.part + ((size_t)F.L * 4 + F.sL) * NM;
-    for (int i = 0; i < NM; ++i) m[i] = a[i];
+    for (int i = 0; i < NM; ++i) m[i] = 0.0;
+    for (int v = lane; v < p.nv; v += 64) {
+        bool use = true;
+        if (F.type != FT_INTERIOR) {
+            const double un = normal_speed(p.xi[v], p.eta[v], cL.nx, cL.ny);
+            use = un > 0.0 || (un == 0.0 && cL.tie);
+        }
+        // (the inflow half of a boundary face is never written: skip it, do not weight it)
+        if (use) acc_moments<NM>(m, p.w[v], p.xi[v], p.eta[v], (double)fvG[v], (double)fvH[v]);
+    }
+    wave_sum<NM>(m);
     double rw = 0.0;
-    if (F.type == FT_INTERIOR) {
-        const double *b = p.part + ((size_t)F.R * 4 + F.sR) * NM;
-        for (int i = 0; i < NM; ++i) m[i] += b[i];
-    } else {
+    if (F.type != FT_INTERIOR) {
         const double *b = p.bhalf + (size_t)k * NM_MAX;
         if (F.type == FT_WALL) rw = -(F.nx * m[1] + F.ny * m[2]) / p.wden[k];
         const double sc = F.type == FT_WALL ? rw : 1.0;
