@@ -808,7 +808,7 @@ __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
 #pragma unroll
             for (int u = 0; u < NS; ++u) {
                 const int sd = q * NS + u;
-                mr[u] = m[sd];
+                mr[u] = m[q + u * LPC];  // component q + u LPC, which this lane finishes
 #pragma unroll
                 for (int e = 0; e < MH_SN; ++e) ms[u][e] = m[MH_SIDE + MH_SN * sd + e];
                 const double *src = upper ? (sd == 0 ? wI + 4 * j : sd == 1 ? fr0 + 4 * (i + 1) : sd == 2 ? wJ + 4 * i : fr0 + 4 * i)
