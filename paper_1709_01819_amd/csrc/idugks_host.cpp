@@ -1028,7 +1028,8 @@ static idugks_status adjoint_check(idugks_ctx *x) {
     return IDUGKS_OK;
 }
 
-// Forward values the reverse pass reads: records, gr, face records, flux, record Jacobians.
+// Forward values the reverse pass reads: records, face values and records, flux, record
+// Jacobians.
 static idugks_status adjoint_forward(idugks_ctx *x) {
     idugks_status s = flux_pipeline(x);
     if (s != IDUGKS_OK) return s;

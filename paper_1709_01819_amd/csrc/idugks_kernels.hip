@@ -3,8 +3,8 @@
 // Paper: Pan, Zhong & Zhuo, arXiv:1709.01819.  One implicit iteration is
 //   records    cell equilibrium records from the conserved moments (Eq. 2, 4, 20)
 //   partials   phi-bar-plus (Eq. 10, 12), least-squares gradient and limiter (Eq. 14-17),
-//              upwind reconstruction at the faces (Eq. 11, 13) reduced to partial moments
-//   face rec   face moments, wall density, face equilibrium (moments of phi-bar, Eq. 18)
+//              upwind reconstruction at the faces (Eq. 11, 13), stored per face and velocity
+//   face rec   face moments of the stored values, wall density, face equilibrium (Eq. 18)
 //   flux       interface distribution (Eq. 18), flux (Eq. 19), M_i(v) (Eq. 23), M_W (Eq. 27)
 //   macro      predicted macroscopic LU-SGS (Eq. 28-31) on i+j hyperplanes
 //   records*   predicted equilibrium
@@ -867,11 +867,11 @@ __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
 // in its L2); compute lane = (cell of the hyperplane, velocity of the slice), handling
 // both species (they share the diagonal and the couplings).  LDS holds the increments of
 // the previous hyperplane and of the cells next to a periodic seam, and the staged
-// per-cell data (record, diagonal, geometry) of the current and next hyperplane.  Each
-// compute lane keeps the HBM loads of its next RING items (one per hyperplane) in flight
-// in fixed registers.
+// per-cell data (record, geometry, coupling weights) of the current and next hyperplane.
+// Each compute lane keeps the HBM loads of its next RING items (one per hyperplane) in
+// flight in fixed registers.
 // ---------------------------------------------------------------------------------------
-constexpr int STG = 24;  // staged values per cell: record (12), nx S (4), ny S (4), codes (4)
+constexpr int STG = 24;  // staged values per cell: record (12), nx S (4), ny S (4), weights (4)
 constexpr int RING = 3;
 
 template <class S, int VPL>
@@ -1288,8 +1288,8 @@ __global__ void k_fields(Params p, double *out) {
 // reverse pass runs the forward chain backwards: Eq. 18 blend and flux of each face,
 // face equilibrium and tau (records), face moments, diffuse-wall density (Eq. 34), upwind
 // reconstruction (Eq. 13-14), least-squares gradient (Eq. 15), phi-bar-plus (Eq. 10, 12),
-// cell equilibrium and tau, cell moments.  The forward values (records, tables, gr) are
-// those of the last flux evaluation at the same state.
+// cell equilibrium and tau, cell moments.  The forward values (records, tables, face
+// values) are those of the last flux evaluation at the same state.
 // ---------------------------------------------------------------------------------------
 
 // Forward-mode number with four tangents (derivatives with respect to W).
