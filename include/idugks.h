@@ -191,6 +191,11 @@ const char *idugks_kernel_name(int32_t k);
 idugks_status idugks_profile(idugks_ctx *ctx, int32_t mode, int32_t nsteps, double *ms,
                              int64_t *counts);
 
+/* As idugks_profile, but events bracket only the kernels k with bit k of kernel_mask set
+   (each event pair adds a few microseconds to a step; the others run as in idugks_step). */
+idugks_status idugks_profile_mask(idugks_ctx *ctx, int32_t mode, int32_t nsteps, uint32_t kernel_mask,
+                                  double *ms, int64_t *counts);
+
 /* Thread-local message of the last failure. */
 const char *idugks_last_error(void);
 

@@ -72,6 +72,7 @@ _SIGS = {
     "idugks_num_kernels": (C.c_int32, []),
     "idugks_kernel_name": (C.c_char_p, [C.c_int32]),
     "idugks_profile": (C.c_int, [_P, C.c_int32, C.c_int32, _D, C.POINTER(C.c_int64)]),
+    "idugks_profile_mask": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint32, _D, C.POINTER(C.c_int64)]),
     "idugks_last_error": (C.c_char_p, []),
     "idugks_destroy": (None, [_P]),
 }
@@ -91,6 +92,11 @@ def load_library():
     if not os.path.exists(_LIB_PATH):
         raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
                            "`python -m paper_1709_01819_amd.build` (no fallback exists)")
+    # The workspace and stream come from PyTorch, so the library must bind to the HIP
+    # runtime PyTorch loads (same soname).  Importing torch first makes the dynamic linker
+    # resolve the library's libamdhip64.so.7 to that one; loaded the other way round, the
+    # process holds two HIP runtimes and the library's one sees no device.
+    import torch  # noqa: F401
     lib = C.CDLL(_LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)

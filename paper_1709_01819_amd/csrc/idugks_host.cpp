@@ -166,6 +166,7 @@ struct idugks_ctx {
     size_t ev_used;
     double ms[KID_COUNT];
     int64_t cnt[KID_COUNT];
+    uint32_t prof_mask;  // kernels timed while prof is set (bit k: kernel k)
 };
 
 namespace {
@@ -656,7 +657,8 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
 template <class F>
 idugks_status timed(idugks_ctx *x, int kid, F &&launch) {
     size_t slot = 0;
-    if (x->prof) {
+    const bool rec = x->prof && ((x->prof_mask >> kid) & 1u);
+    if (rec) {
         slot = x->ev_used++;
         while (x->evs.size() < 2 * x->ev_used) {
             hipEvent_t e;
@@ -670,7 +672,7 @@ idugks_status timed(idugks_ctx *x, int kid, F &&launch) {
     hipError_t e = launch();
     if (e != hipSuccess)
         return fail(IDUGKS_E_DEVICE, std::string("kernel ") + kKernelNames[kid] + ": " + hipGetErrorString(e));
-    if (x->prof) HIPCHK(hipEventRecord(x->evs[2 * slot + 1], x->st));
+    if (rec) HIPCHK(hipEventRecord(x->evs[2 * slot + 1], x->st));
     return IDUGKS_OK;
 }
 
@@ -1221,10 +1223,12 @@ int32_t idugks_num_kernels(void) { return KID_COUNT; }
 
 const char *idugks_kernel_name(int32_t k) { return (k >= 0 && k < KID_COUNT) ? kKernelNames[k] : ""; }
 
-idugks_status idugks_profile(idugks_ctx *x, int32_t mode, int32_t nsteps, double *ms, int64_t *counts) {
+idugks_status idugks_profile_mask(idugks_ctx *x, int32_t mode, int32_t nsteps, uint32_t kernel_mask,
+                                  double *ms, int64_t *counts) {
     if (!x || !ms) return fail(IDUGKS_E_INVALID, "null argument");
     for (int k = 0; k < KID_COUNT; ++k) { x->ms[k] = 0.0; x->cnt[k] = 0; }
     x->prof = true;
+    x->prof_mask = kernel_mask;
     x->ev_used = 0;
     idugks_status s = idugks_step(x, mode, nsteps, nullptr);
     x->prof = false;
@@ -1240,6 +1244,10 @@ idugks_status idugks_profile(idugks_ctx *x, int32_t mode, int32_t nsteps, double
         if (counts) counts[k] = x->cnt[k];
     }
     return s;
+}
+
+idugks_status idugks_profile(idugks_ctx *x, int32_t mode, int32_t nsteps, double *ms, int64_t *counts) {
+    return idugks_profile_mask(x, mode, nsteps, 0xFFFFFFFFu, ms, counts);
 }
 
 }  // extern "C"

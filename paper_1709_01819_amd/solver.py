@@ -150,11 +150,16 @@ class Solver:
         n = self._lib.idugks_num_kernels()
         return [self._lib.idugks_kernel_name(k).decode() for k in range(n)]
 
-    def profile(self, mode=IMPLICIT, n=1):
-        """Per-kernel HIP-event milliseconds over n steps: {name: (ms_total, launches)}."""
-        nk = self._lib.idugks_num_kernels()
+    def profile(self, mode=IMPLICIT, n=1, kernels=None):
+        """Per-kernel HIP-event milliseconds over n steps: {name: (ms_total, launches)}.
+
+        kernels: names of the kernels to bracket with events (default all); the others run
+        without events and report (0.0, 0)."""
+        names = self.kernel_names()
+        nk = len(names)
+        mask = 0xFFFFFFFF if kernels is None else sum(1 << names.index(k) for k in kernels)
         ms = np.zeros(nk)
         cnt = np.zeros(nk, dtype=np.int64)
-        self._check(self._lib.idugks_profile(self._h, mode, n, _dp(ms),
-                                             cnt.ctypes.data_as(C.POINTER(C.c_int64))))
-        return {name: (float(ms[k]), int(cnt[k])) for k, name in enumerate(self.kernel_names())}
+        self._check(self._lib.idugks_profile_mask(self._h, mode, n, mask, _dp(ms),
+                                                  cnt.ctypes.data_as(C.POINTER(C.c_int64))))
+        return {name: (float(ms[k]), int(cnt[k])) for k, name in enumerate(names)}

@@ -27,6 +27,15 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(abi.EXPORTED)
 
 
+def test_library_binds_to_the_hip_runtime_torch_uses():
+    """The workspace and stream come from PyTorch: the library must share its HIP runtime
+    (two runtimes in one process leave the library without a device)."""
+    abi.load_library()
+    with open("/proc/self/maps") as fh:
+        runtimes = {ln.split()[-1] for ln in fh if "libamdhip64" in ln}
+    assert len(runtimes) == 1, runtimes
+
+
 def test_kernel_names():
     lib = abi.load_library()
     n = lib.idugks_num_kernels()
