@@ -625,8 +625,8 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
     Layout L;
     const size_t S = c->precision == IDUGKS_FP32_MIXED ? 4 : 8, TW = (size_t)nvx + nvy;
     // rows of the hyperplane-ordered sweep arrays: the staging waves read whole passes past
-    // the last cell of a hyperplane, so these arrays carry min(ni, nj) + 32 spare rows
-    const size_t ncs = (size_t)nc + std::min(c->ni, c->nj) + 32;
+    // the last cell of a hyperplane, so these arrays carry min(ni, nj) + HP_SPARE spare rows
+    const size_t ncs = (size_t)nc + std::min(c->ni, c->nj) + HP_SPARE;
     const int nv = c->nvx * c->nvy, nch = (nv + vel_chunk(nv) - 1) / vel_chunk(nv);
     const size_t adj = adjoint_capable(c) ? 1 : 0;
     const size_t sizes[R_COUNT] = {

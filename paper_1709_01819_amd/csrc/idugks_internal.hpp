@@ -73,9 +73,12 @@ inline int vel_chunk(int nv) { return nv <= 4096 ? nv : 2048; }
 constexpr int RT_N = 16;
 
 constexpr int SG_N = 16, SR_N = 12;
-// macro row: M_W (dW* after the forward sweep) [4], 1/D, packed side codes, then per side
-// nx, ny, S, lambda_j, W_j [4]
-constexpr int MH_SIDE = 6, MH_SN = 8, MH_N = MH_SIDE + 4 * MH_SN, MH_CODE_BITS = 4;
+// macro row: M_W (dW* after the forward sweep) [4], 1/D, packed side codes, the cell's W [4]
+// and sound speed, then per side nx, ny, S
+constexpr int MH_SIDE = 11, MH_SN = 3, MH_N = MH_SIDE + 4 * MH_SN, MH_CODE_BITS = 4;
+// spare rows after the last cell of the hyperplane-ordered arrays (beyond min(ni, nj)): the
+// staging waves read whole passes past the last cell of a hyperplane
+constexpr int HP_SPARE = 48;
 
 // Static per-cell data of the micro sweeps (built on the host), per cell side: nx S and
 // ny S (0 on a self-periodic side, which has no flux) and the coupling weights of the

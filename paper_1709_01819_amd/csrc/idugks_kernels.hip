@@ -624,7 +624,7 @@ DEV double rcp_nr(double x) {
 
 // Euler flux through a face of unit normal n of the state W = (rho, rho U, rho V, rho E);
 // ik2 = 1/(K+2), so that p = (2 rho E - rho |U|^2)/(K+2)
-DEV void euler_flux_n(const double W[4], double nx, double ny, double ik2, double F[4]) {
+DEV double euler_flux_n(const double W[4], double nx, double ny, double ik2, double F[4]) {
     const double ir = rcp_nr(W[0]);
     const double U = W[1] * ir, V = W[2] * ir;
     const double pr = (2.0 * W[3] - W[0] * (U * U + V * V)) * ik2;
@@ -633,13 +633,14 @@ DEV void euler_flux_n(const double W[4], double nx, double ny, double ik2, doubl
     F[1] = W[1] * un + pr * nx;
     F[2] = W[2] * un + pr * ny;
     F[3] = (W[3] + pr) * un;
+    return un;
 }
 
 // Everything of Eq. 30-31 that does not depend on the increments, all cells in parallel:
-// implicit time step, inverse diagonal (a wall face carries its whole lambda S: mirrored
-// ghost), and per cell side with a neighbour j the neighbour's lambda_j and W_j (the
-// sweep recomputes F_n(W_j): a shorter row stages faster).  Rows are stored in i+j
-// hyperplane order: M_W, 1/D, packed side codes, per side nx, ny, S, lambda_j, W_j.
+// implicit time step and inverse diagonal (a wall face carries its whole lambda S: mirrored
+// ghost).  Rows are stored in i+j hyperplane order: M_W, 1/D, packed side codes, the cell's
+// W and sound speed, per side nx, ny, S.  The sweep takes a neighbour's W and sound speed
+// from the neighbour's own row (through LDS) and forms lambda_j there.
 __global__ __launch_bounds__(256) void k_macro_prep(Params p) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= p.nc) return;
@@ -657,17 +658,16 @@ __global__ __launch_bounds__(256) void k_macro_prep(Params p) {
         const double l = (fabs(U * cs[s].nx + V * cs[s].ny) + C) * cs[s].S;
         ls += l;
         if (cs[s].type == FT_WALL) lw += l;
-        const int j = cs[s].nb;
-        if (j < 0) continue;
-        const double *Wj = p.Wc + (size_t)j * 4;
-        ms[3] = fabs((Wj[1] * cs[s].nx + Wj[2] * cs[s].ny) / Wj[0]) + sqrt(p.gam * p.rec[j].RT);
-        for (int a = 0; a < 4; ++a) ms[4 + a] = Wj[a];
     }
     const double dti = p.cfl_imp * p.area[c] / ls;
     p.dtimp[c] = dti;
-    for (int a = 0; a < 4; ++a) m[a] = p.MW[(size_t)c * 4 + a];
+    for (int a = 0; a < 4; ++a) {
+        m[a] = p.MW[(size_t)c * 4 + a];
+        m[6 + a] = p.Wc[(size_t)c * 4 + a];
+    }
     m[4] = 1.0 / (p.area[c] / dti + 0.5 * ls + 0.5 * lw);
     m[5] = (double)codes;
+    m[10] = C;
 }
 
 // All data exchanged inside the sweep kernels goes through LDS, so their barrier orders
@@ -693,16 +693,16 @@ DEV void hp_bounds(int s, int ni, int nj, int &lo, int &hi) {
 constexpr int SDEPTH = 4;  // hyperplanes of staging loads in flight (micro sweeps)
 static_assert(SG_UPPER < 1 << MH_CODE_BITS, "side codes must fit their field of the macro row");
 // a staging wave reads up to 64 x 16 values past the first row of a hyperplane, the last of
-// which starts at row nc - 1: the min(ni, nj) + 32 spare rows of the staged arrays cover it
-static_assert(33 * MH_N >= 64 * 16, "macro staging reads past the spare rows");
+// which starts at row nc - 1: the min(ni, nj) + HP_SPARE spare rows of the staged arrays cover it
+static_assert((HP_SPARE + 1) * MH_N >= 64 * 16, "macro staging reads past the spare rows");
 
 // x of the lane (lane ^ 1) or (lane ^ 2) of the same quad: a DPP quad permutation
 // (CTRL 0xB1 = [1,0,3,2], 0x4E = [2,3,0,1]), two 32-bit moves in registers
 template <int CTRL>
 DEV double quad_swap(double x) {
     const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -719,26 +719,32 @@ DEV void stage_store(const double (&reg)[N], double *dst, int n, int sl, int nsl
 // compute, LPC lanes per cell of a hyperplane, lane q taking the sides q NS .. q NS + NS - 1
 // (NS = 4 / LPC: with two lanes, one has the i sides and the other the j sides, so each
 // has one coupled side per direction in the interior):
-//   r -= 1/2 S (F_n(W_j + dW_j) - F_n(W_j) - lambda_j dW_j)
+//   r -= 1/2 S (F_n(W_j + dW_j) - F_n(W_j) - lambda_j dW_j),  lambda_j = |U_j.n| + c_j
 // over the lower (forward) or upper (backward) neighbours; the lanes of a cell sum their
-// parts in a fixed order by quad permutations and lane q finishes the components q,
-// q + LPC, ....  LDS holds the previous hyperplane's increments (fronts, with a padding
-// cell at each end), those of the cells next to a periodic seam (wI: column i = 0 / ni-1,
-// wJ: row j = 0 / nj-1, the only non-adjacent neighbours) and the staged rows of the
-// current and the next hyperplane.  The forward
-// sweep writes dW* into the first four values of each cell's row, which the backward
-// sweep stages back.  The staging waves keep MD hyperplanes of SPWM values per lane in
-// flight: the row is short enough that one CU's load latency, not its bandwidth, bounds
-// the step, so the depth matters more than the lane count.
+// parts by quad permutations, each keeping the components it finishes (q, q + LPC, ...).
+// LDS holds, per cell of the previous hyperplane, its increment, W and sound speed (fronts
+// of MF values, with a padding cell at each end), the same for the cells next to a periodic
+// seam (wI: column i = 0 / ni-1, wJ: row j = 0 / nj-1, the only non-adjacent neighbours),
+// the staged rows of the current and the next hyperplane and the increments of the last
+// two hyperplanes on their way to HBM.  The forward sweep's dW* go into the first four
+// values of each cell's row, which the backward sweep stages back.  The staging waves keep
+// MD hyperplanes of SPWM values per lane in flight and write the increments out one step
+// later (the compute waves only touch LDS); one CU's load latency, not its bandwidth,
+// bounds the staging, so the depth matters more than the lane count.
+constexpr int MF = 9;  // front entry: dW [4], W [4], c
+
 template <int LPC, int SPWM, int MD>
 __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
     extern __shared__ double lds[];
     const int ni = p.ni, nj = p.nj, nh = ni + nj - 1, L = ni < nj ? ni : nj;
-    double *fr0 = lds + 4, *fr1 = fr0 + 4 * (ni + 1), *wI = fr1 + 4 * (ni + 1), *wJ = wI + 4 * nj;
-    double *st0 = wJ + 4 * ni, *st1 = st0 + (size_t)L * MH_N;
-    int *hpo = (int *)(st1 + (size_t)L * MH_N);
+    // LDS offsets (in doubles): the two fronts, the seam copies, the staged rows, the
+    // out-buffers; the front of the previous hyperplane is A after an even number of steps
+    const int oA = MF, oB = oA + MF * (ni + 1), oI = oB + MF * (ni + 1), oJ = oI + MF * nj;
+    double *st0 = lds + oJ + MF * ni, *st1 = st0 + (size_t)L * MH_N;
+    double *ob0 = st1 + (size_t)L * MH_N, *ob1 = ob0 + 4 * L;  // out-buffers by step parity
+    int *hpo = (int *)(ob1 + 4 * L);
     for (int h = threadIdx.x; h <= nh; h += blockDim.x) hpo[h] = p.hp_off[h];
-    for (int e = threadIdx.x; e < 12 * ni + 4 * nj + 12; e += blockDim.x) lds[e] = 0.0;
+    for (int e = threadIdx.x; e < oJ + MF * ni; e += blockDim.x) lds[e] = 0.0;
     __syncthreads();
     const double ik2 = 1.0 / (p.K + 2);
     // Both roles run the same number of barriers: one after the prologue and one per
@@ -759,6 +765,20 @@ __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
             auto hp = [&](int t) { return upper ? nh - 1 - t : t; };
             auto hcl = [&](int t) { return hp(t < nh ? t : nh - 1); };  // repeated rows are not staged
             auto cells = [&](int t) { return hpo[hp(t) + 1] - hpo[hp(t)]; };
+            // the increments of hyperplane t, left in the out-buffer of its parity by the
+            // compute waves during step t, go to HBM during step t+1: dW* into the first
+            // four values of the rows (forward), dW (backward)
+            auto flush = [&](int t) {
+                const int h = hp(t), n = 4 * cells(t);
+                const double *ob = t & 1 ? ob1 : ob0;
+                int lo, hi;
+                hp_bounds(h, ni, nj, lo, hi);
+                for (int e = sl; e < n; e += nsl) {
+                    const int kk = e >> 2, a = e & 3;
+                    if (upper) p.dW[(size_t)(lo + kk + (h - lo - kk) * ni) * 4 + a] = ob[e];
+                    else p.mh[(size_t)(hpo[h] + kk) * MH_N + a] = ob[e];
+                }
+            };
             issue(reg[0], hcl(0));
             stage_store(reg[0], st0, cells(0) * MH_N, sl, nsl);
 #pragma unroll
@@ -771,6 +791,7 @@ __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
                     const int t = t0 + d;
                     if (t + 1 < nh) stage_store(reg[(d + 1) % MD], (t + 1) & 1 ? st1 : st0, cells(t + 1) * MH_N, sl, nsl);
                     issue(reg[(d + 1) % MD], hcl(t + 1 + MD));
+                    if (t > 0) flush(t - 1);
                     lds_barrier();
                 }
             }
@@ -779,82 +800,108 @@ __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
                 const int t = t0 + d;
                 if (t < nh) {
                     if (t + 1 < nh) stage_store(reg[(d + 1) % MD], (t + 1) & 1 ? st1 : st0, cells(t + 1) * MH_N, sl, nsl);
+                    if (t > 0) flush(t - 1);
                     lds_barrier();
                 }
             }
+            flush(nh - 1);
             __syncthreads();
         }
         return;
     }
     constexpr int NS = 4 / LPC;  // sides (and components) per lane
     const int k = (int)threadIdx.x / LPC, q = (int)threadIdx.x % LPC;
+    int T = 0;  // steps so far
     for (int dir = 0; dir < 2; ++dir) {
         const bool upper = dir == 1;
         const int need = upper ? SG_UPPER : SG_LOWER;
+        // The one neighbour each side of this lane can couple to in this direction (sides
+        // i-, i+, j-, j+): forward front[i-1], wI[j], front[i], wJ[i]; backward wI[j],
+        // front[i+1], wJ[i], front[i].  Per side: whether it is a front entry, the offset of
+        // its index, and the seam copy (indexed by j for wI, i for wJ).
+        bool isf[NS], usej[NS];
+        int dl[NS], sb[NS];
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int sd = q * NS + u;
+            isf[u] = (sd & 1) == (upper ? 1 : 0);
+            usej[u] = !isf[u] && sd < 2;
+            dl[u] = isf[u] && sd < 2 ? (upper ? 1 : -1) : 0;
+            sb[u] = sd < 2 ? oI : oJ;
+        }
         lds_barrier();
-        for (int t = 0; t < nh; ++t) {
+        for (int t = 0; t < nh; ++t, ++T) {
             const int s = upper ? nh - 1 - t : t;
             int lo, hi;
             hp_bounds(s, ni, nj, lo, hi);
+            const int cur = T & 1 ? oB : oA, nxt = T & 1 ? oA : oB;
             // idle lanes (past the hyperplane's end) read the data of its first cell
             const bool live = lo + k <= hi;
             const int i = live ? lo + k : lo, j = s - i;
             const double *m = (t & 1 ? st1 : st0) + (size_t)(live ? k : 0) * MH_N;
-            // this lane's side values and the one neighbour increment each of its sides can
-            // couple to in this direction (sides i-, i+, j-, j+): forward fr0[i-1], wI[j],
-            // fr0[i], wJ[i]; backward wI[j], fr0[i+1], wJ[i], fr0[i]; one batch of LDS reads
+            // this lane's row values and its neighbours' front entries: one batch of LDS reads
             const int codes = (int)m[5];
-            double ms[NS][MH_SN], mr[NS], dW[NS][4];
+            double ms[NS][MH_SN], mr[NS], wo[NS], nb[NS][MF];
 #pragma unroll
             for (int u = 0; u < NS; ++u) {
-                const int sd = q * NS + u;
-                mr[u] = m[q + u * LPC];  // component q + u LPC, which this lane finishes
+                const int o = (isf[u] ? cur : sb[u]) + MF * (usej[u] ? j : i + dl[u]);
 #pragma unroll
-                for (int e = 0; e < MH_SN; ++e) ms[u][e] = m[MH_SIDE + MH_SN * sd + e];
-                const double *src = upper ? (sd == 0 ? wI + 4 * j : sd == 1 ? fr0 + 4 * (i + 1) : sd == 2 ? wJ + 4 * i : fr0 + 4 * i)
-                                          : (sd == 0 ? fr0 + 4 * (i - 1) : sd == 1 ? wI + 4 * j : sd == 2 ? fr0 + 4 * i : wJ + 4 * i);
+                for (int e = 0; e < MF; ++e) nb[u][e] = lds[o + e];
+                mr[u] = m[q + u * LPC];      // component q + u LPC of M_W, which this lane finishes
+                wo[u] = m[6 + q + u * LPC];  // and of the cell's own W
 #pragma unroll
-                for (int a = 0; a < 4; ++a) dW[u][a] = src[a];
+                for (int e = 0; e < MH_SN; ++e) ms[u][e] = m[MH_SIDE + MH_SN * (q * NS + u) + e];
             }
-            const double iD = m[4];
+            const double iD = m[4], co = m[10];
             double r[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int u = 0; u < NS; ++u) {
                 const int sd = q * NS + u;
                 if (!(live && ((codes >> (MH_CODE_BITS * sd)) & need))) continue;
+                const double *dW = nb[u], *Wj = nb[u] + 4;
                 double Wn[4], F0[4], F1[4];
 #pragma unroll
-                for (int a = 0; a < 4; ++a) Wn[a] = ms[u][4 + a] + dW[u][a];
-                euler_flux_n(&ms[u][4], ms[u][0], ms[u][1], ik2, F0);
+                for (int a = 0; a < 4; ++a) Wn[a] = Wj[a] + dW[a];
+                const double lam = fabs(euler_flux_n(Wj, ms[u][0], ms[u][1], ik2, F0)) + nb[u][8];
                 euler_flux_n(Wn, ms[u][0], ms[u][1], ik2, F1);
                 const double hS = 0.5 * ms[u][2];
 #pragma unroll
-                for (int a = 0; a < 4; ++a) r[a] += hS * (F1[a] - F0[a] - ms[u][3] * dW[u][a]);
+                for (int a = 0; a < 4; ++a) r[a] += hS * (F1[a] - F0[a] - lam * dW[a]);
             }
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                if (LPC >= 2) r[a] += quad_swap<0xB1>(r[a]);
-                if (LPC >= 4) r[a] += quad_swap<0x4E>(r[a]);
+            // Sum over the cell's lanes, each lane keeping only the components it finishes
+            // (q + u LPC): exchange with lane q^1 the two components of the other parity,
+            // then (four lanes) with lane q^2 the one of the other half.
+            const bool p1 = q & 1;
+            const double c0 = (p1 ? r[1] : r[0]) + quad_swap<0xB1>(p1 ? r[0] : r[1]);
+            const double c1 = (p1 ? r[3] : r[2]) + quad_swap<0xB1>(p1 ? r[2] : r[3]);
+            double ra[NS];
+            if (LPC == 4) {
+                const bool h1 = q & 2;
+                ra[0] = (h1 ? c1 : c0) + quad_swap<0x4E>(h1 ? c0 : c1);
+            } else {
+                ra[0] = c0;
+                ra[NS - 1] = c1;
             }
             if (live) {
+                const bool sI = i == (upper ? ni - 1 : 0), sJ = j == (upper ? nj - 1 : 0);
 #pragma unroll
                 for (int u = 0; u < NS; ++u) {
                     const int a = q + u * LPC;
-                    double ra = r[0];
-#pragma unroll
-                    for (int b = 1; b < 4; ++b)
-                        if (a == b) ra = r[b];
                     // forward dW* = (M_W - r)/D, backward dW = dW* - r/D
-                    const double d = upper ? mr[u] - ra * iD : (mr[u] - ra) * iD;
-                    if (upper) p.dW[(size_t)(i + j * ni) * 4 + a] = d;
-                    else p.mh[(size_t)(hpo[s] + k) * MH_N + a] = d;
-                    fr1[4 * i + a] = d;
-                    if (i == (upper ? ni - 1 : 0)) wI[4 * j + a] = d;
-                    if (j == (upper ? nj - 1 : 0)) wJ[4 * i + a] = d;
+                    const double d = upper ? mr[u] - ra[u] * iD : (mr[u] - ra[u]) * iD;
+                    (t & 1 ? ob1 : ob0)[4 * k + a] = d;  // to HBM by the staging waves
+                    lds[nxt + MF * i + a] = d;
+                    lds[nxt + MF * i + 4 + a] = wo[u];
+                    if (sI) { lds[oI + MF * j + a] = d; lds[oI + MF * j + 4 + a] = wo[u]; }
+                    if (sJ) { lds[oJ + MF * i + a] = d; lds[oJ + MF * i + 4 + a] = wo[u]; }
+                }
+                if (q == 0) {
+                    lds[nxt + MF * i + 8] = co;
+                    if (sI) lds[oI + MF * j + 8] = co;
+                    if (sJ) lds[oJ + MF * i + 8] = co;
                 }
             }
             lds_barrier();
-            double *tp = fr0; fr0 = fr1; fr1 = tp;
         }
         // the forward sweep's row writes must be visible to the backward staging loads
         __syncthreads();
@@ -1879,7 +1926,7 @@ MacroShape macro_shape(int ni, int nj) {
         }
         if (m.threads <= 1024) break;
     }
-    m.lds = (size_t)(12 * ni + 4 * nj + 12 + 2 * L * MH_N) * sizeof(double) + (size_t)(nh + 1) * sizeof(int);
+    m.lds = (size_t)(MF * (3 * ni + nj + 3) + 2 * L * MH_N + 8 * L) * sizeof(double) + (size_t)(nh + 1) * sizeof(int);
     return m;
 }
 
