@@ -408,27 +408,42 @@ __global__ __launch_bounds__(256) void k_records(Params p, int which) {
 // ---------------------------------------------------------------------------------------
 // phi-bar-plus (Eq. 10 and Eq. 12 combined) and the limited least-squares gradient
 // ---------------------------------------------------------------------------------------
+// Loop-invariant data of a face-partial block, staged into LDS once: the records of the
+// cell (slot 0) and of its neighbours (slot 1 + side; zeros for a missing neighbour) and
+// the cell's side data.  The per-velocity loop then reads only the state and the velocity
+// set from memory.
+template <class S>
+struct PartStage {
+    S rec[5][RT_N];
+    double ax[4], ay[4], dx[4], dy[4], nx[4], ny[4];
+    int nb[4], face[4], type[4], tie[4];
+};
+
+// phi-bar-plus = ab phi~ + bb phi_eq of one cell at one velocity (Eq. 10, 12), from its
+// record r, factored Maxwellian tb and state row f (G, then H at f + nvp)
 template <class S, class T, bool SHAK>
-DEV void barplus(const Params &p, int j, int v, int ix, int iy, T x, T y, T sc, T &bG, T &bH) {
-    const RecT<T> r = load_recT<S>(p.recT, j);
-    const S *tb = (const S *)p.tab + (size_t)j * (p.nvx + p.nvy);
-    const T E = (T)tb[ix] * (T)tb[p.nvx + iy];
+DEV void barplus(const S *r, const S *tb, int nvx, const S *f, int nvp, int v, int ix, int iy, T x,
+                 T y, T sc, T &bG, T &bH) {
+    RecT<T> q;
+    q.U = r[0]; q.V = r[1]; q.c0 = r[2]; q.c1 = r[3]; q.c2c = r[4]; q.c3 = r[5];
+    q.kqx = r[6]; q.kqy = r[7]; q.iRT = r[8]; q.KRT = r[9]; q.ab = r[10]; q.bb = r[11];
+    const T E = (T)tb[ix] * (T)tb[nvx + iy];
     T eG, eH;
-    eq_eval<T, SHAK>(r, x, y, E, eG, eH);
-    const T XG = sc * (T)rowp<S>(p, p.f, j, 0)[v], XH = sc * (T)rowp<S>(p, p.f, j, 1)[v];
-    bG = r.ab * XG + r.bb * eG;
-    bH = r.ab * XH + r.bb * eH;
+    eq_eval<T, SHAK>(q, x, y, E, eG, eH);
+    const T XG = sc * (T)f[v], XH = sc * (T)f[nvp + v];
+    bG = q.ab * XG + q.bb * eG;
+    bH = q.ab * XH + q.bb * eH;
 }
 
 template <class T>
 DEV T venkat(T x) { return (x * x + T(2) * x) / (x * x + x + T(2)); }
 
 template <class T>
-DEV T limiter_phi(const CellSide *cs, T b0, T bmax, T bmin, T gx, T gy) {
+DEV T limiter_phi(const double *dx, const double *dy, T b0, T bmax, T bmin, T gx, T gy) {
     T phi = T(1);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const T d = gx * (T)cs[s].dx + gy * (T)cs[s].dy;
+        const T d = gx * (T)dx[s] + gy * (T)dy[s];
         T th = T(1);
         if (d > T(0)) th = venkat<T>((bmax - b0) / d);
         else if (d < T(0)) th = venkat<T>((bmin - b0) / d);
@@ -437,59 +452,82 @@ DEV T limiter_phi(const CellSide *cs, T b0, T bmax, T bmin, T gx, T gy) {
     return phi;
 }
 
-template <class S, class T, bool SHAK, bool LIM>
-DEV void recon_cell(const Params &p, int j, int v, int ix, int iy, T x, T y, T sc, T &bG, T &bH,
-                    T &gxG, T &gyG, T &gxH, T &gyH) {
-    const CellSide *cs = p.cs + 4 * j;
-    barplus<S, T, SHAK>(p, j, v, ix, iy, x, y, sc, bG, bH);
-    gxG = gyG = gxH = gyH = T(0);
-    T mxG = bG, mnG = bG, mxH = bH, mnH = bH;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int n = cs[s].nb;
-        if (n < 0) continue;
-        T nG, nH;
-        barplus<S, T, SHAK>(p, n, v, ix, iy, x, y, sc, nG, nH);
-        const T ax = (T)cs[s].ax, ay = (T)cs[s].ay, dG = nG - bG, dH = nH - bH;
-        gxG += ax * dG; gyG += ay * dG; gxH += ax * dH; gyH += ay * dH;
-        if (LIM) {
-            mxG = nG > mxG ? nG : mxG; mnG = nG < mnG ? nG : mnG;
-            mxH = nH > mxH ? nH : mxH; mnH = nH < mnH ? nH : mnH;
-        }
-    }
-    if (LIM) {
-        const T pG = limiter_phi<T>(cs, bG, mxG, mnG, gxG, gyG);
-        const T pH = limiter_phi<T>(cs, bH, mxH, mnH, gxH, gyH);
-        gxG *= pG; gyG *= pG; gxH *= pH; gyH *= pH;
-    }
-}
-
 // ---------------------------------------------------------------------------------------
 // face values: per (cell, velocity) the reconstruction of phi-bar-plus (value, limited
-// gradient), then at each face the cell is upwind of, the reconstructed phi-bar stored
-// for the face-record and flux kernels
+// least-squares gradient, Eq. 13-16), then at each face the cell is upwind of, the
+// reconstructed phi-bar stored for the face-record and flux kernels.  TL: the five cells'
+// factored Maxwellians are staged into LDS as well (when they fit).
 // ---------------------------------------------------------------------------------------
-template <class S, bool SHAK, bool LIM>
+template <class S, bool SHAK, bool LIM, bool TL>
 __global__ __launch_bounds__(256) void k_partials(Params p) {
     using T = S;
+    extern __shared__ double pdyn[];
+    __shared__ PartStage<S> ps;
     int c, v0, v1;
     if (!chunk_block(p, p.nv, c, v0, v1)) return;
     const CellSide *cs = p.cs + 4 * c;
+    const int TW = p.nvx + p.nvy, nvx = p.nvx, nvp = p.nvp, tid = threadIdx.x;
+    if (tid < 4) {
+        const CellSide &q = cs[tid];
+        ps.nb[tid] = q.nb; ps.face[tid] = q.face; ps.type[tid] = q.type; ps.tie[tid] = q.tie;
+        ps.ax[tid] = q.ax; ps.ay[tid] = q.ay; ps.dx[tid] = q.dx; ps.dy[tid] = q.dy;
+        ps.nx[tid] = q.nx; ps.ny[tid] = q.ny;
+    }
+    if (tid < 5 * RT_N) {
+        const int q = tid / RT_N, e = tid - q * RT_N, j = q == 0 ? c : cs[q - 1].nb;
+        ps.rec[q][e] = j >= 0 ? ((const S *)p.recT)[(size_t)j * RT_N + e] : S(0);
+    }
+    S *lt = (S *)pdyn;
+    if (TL)
+        for (int e = tid; e < 5 * TW; e += blockDim.x) {
+            const int q = e / TW, i = e - q * TW, j = q == 0 ? c : cs[q - 1].nb;
+            lt[e] = j >= 0 ? ((const S *)p.tab)[(size_t)j * TW + i] : S(0);
+        }
+    __syncthreads();
+    auto tab_of = [&](int q, int j) {
+        return TL ? (const S *)lt + q * TW : (const S *)p.tab + (size_t)j * TW;
+    };
     const T sc = (T)p.scal[SC_SCALE], h = (T)p.h;
-    for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+    for (int v = v0 + tid; v < v1; v += blockDim.x) {
+        // keep the staged records in LDS, read per iteration (hoisted, the five records
+        // would hold about 120 registers and halve the occupancy); emits no code
+        asm volatile("" ::: "memory");
         const int ix = p.vix[v], iy = p.viy[v];
-        const T x = (T)p.xi[v], y = (T)p.eta[v];
-        T bG, bH, gxG, gyG, gxH, gyH;
-        recon_cell<S, T, SHAK, LIM>(p, c, v, ix, iy, x, y, sc, bG, bH, gxG, gyG, gxH, gyH);
+        const double xd = p.xi[v], yd = p.eta[v];
+        const T x = (T)xd, y = (T)yd;
+        T bG, bH;
+        barplus<S, T, SHAK>(ps.rec[0], tab_of(0, c), nvx, (const S *)p.f + (size_t)c * 2 * nvp, nvp, v,
+                            ix, iy, x, y, sc, bG, bH);
+        T gxG = T(0), gyG = T(0), gxH = T(0), gyH = T(0);
+        T mxG = bG, mnG = bG, mxH = bH, mnH = bH;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            if (cs[s].type == FT_SELF) continue;
-            const double un = normal_speed(p.xi[v], p.eta[v], cs[s].nx, cs[s].ny);
-            if (!(un > 0.0 || (un == 0.0 && cs[s].tie))) continue;
-            const T rx = (T)cs[s].dx - h * x, ry = (T)cs[s].dy - h * y;
-            S *fv = (S *)p.fv + (size_t)cs[s].face * 2 * p.nvp + v;
+            const int n = ps.nb[s];
+            if (n < 0) continue;
+            T nG, nH;
+            barplus<S, T, SHAK>(ps.rec[1 + s], tab_of(1 + s, n), nvx, (const S *)p.f + (size_t)n * 2 * nvp,
+                                nvp, v, ix, iy, x, y, sc, nG, nH);
+            const T ax = (T)ps.ax[s], ay = (T)ps.ay[s], dG = nG - bG, dH = nH - bH;
+            gxG += ax * dG; gyG += ay * dG; gxH += ax * dH; gyH += ay * dH;
+            if (LIM) {
+                mxG = nG > mxG ? nG : mxG; mnG = nG < mnG ? nG : mnG;
+                mxH = nH > mxH ? nH : mxH; mnH = nH < mnH ? nH : mnH;
+            }
+        }
+        if (LIM) {
+            const T pG = limiter_phi<T>(ps.dx, ps.dy, bG, mxG, mnG, gxG, gyG);
+            const T pH = limiter_phi<T>(ps.dx, ps.dy, bH, mxH, mnH, gxH, gyH);
+            gxG *= pG; gyG *= pG; gxH *= pH; gyH *= pH;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (ps.type[s] == FT_SELF) continue;
+            const double un = normal_speed(xd, yd, ps.nx[s], ps.ny[s]);
+            if (!(un > 0.0 || (un == 0.0 && ps.tie[s]))) continue;
+            const T rx = (T)ps.dx[s] - h * x, ry = (T)ps.dy[s] - h * y;
+            S *fv = (S *)p.fv + (size_t)ps.face[s] * 2 * nvp + v;
             fv[0] = (S)(bG + gxG * rx + gyG * ry);
-            fv[p.nvp] = (S)(bH + gxH * rx + gyH * ry);
+            fv[nvp] = (S)(bH + gxH * rx + gyH * ry);
         }
     }
 }
@@ -1874,15 +1912,23 @@ static hipError_t combine(const double *src, double *dst, const Params &p, int n
     return hipGetLastError();
 }
 
-hipError_t launch_partials(const Params &p, bool fp32, hipStream_t st) {
+// the factored Maxwellians of the five cells go to LDS when they take at most 16 KiB
+template <class S, bool SHAK, bool LIM>
+static void launch_partials_t(const Params &p, hipStream_t st) {
     const dim3 g = chunk_grid(p, 1);
+    const size_t tl = (size_t)5 * (p.nvx + p.nvy) * sizeof(S);
+    if (tl <= 16384) hipLaunchKernelGGL((k_partials<S, SHAK, LIM, true>), g, dim3(256), tl, st, p);
+    else hipLaunchKernelGGL((k_partials<S, SHAK, LIM, false>), g, dim3(256), 0, st, p);
+}
+
+hipError_t launch_partials(const Params &p, bool fp32, hipStream_t st) {
     DISPATCH_S(fp32, {
         if (p.model == 1) {
-            if (p.limiter) hipLaunchKernelGGL((k_partials<S, true, true>), g, dim3(256), 0, st, p);
-            else hipLaunchKernelGGL((k_partials<S, true, false>), g, dim3(256), 0, st, p);
+            if (p.limiter) launch_partials_t<S, true, true>(p, st);
+            else launch_partials_t<S, true, false>(p, st);
         } else {
-            if (p.limiter) hipLaunchKernelGGL((k_partials<S, false, true>), g, dim3(256), 0, st, p);
-            else hipLaunchKernelGGL((k_partials<S, false, false>), g, dim3(256), 0, st, p);
+            if (p.limiter) launch_partials_t<S, false, true>(p, st);
+            else launch_partials_t<S, false, false>(p, st);
         }
     });
     return hipGetLastError();
