@@ -589,59 +589,92 @@ __global__ __launch_bounds__(256) void k_face_records(Params p) {
 // ---------------------------------------------------------------------------------------
 // flux: M_i(v) = -sum_k S (xi.n_out) phi_k (Eq. 18, 19, 23) and M_W = sum w psi M (Eq. 27)
 // ---------------------------------------------------------------------------------------
-template <class S, bool SHAK>
+// Loop-invariant data of a flux block, staged into LDS once: per side the face record
+// (with alpha and the wall density) and the side data.
+template <class S>
+struct FluxStage {
+    S rec[4][RT_N];
+    double nx[4], ny[4], S_[4];
+    int face[4], type[4], tie[4], wside[4];
+};
+
+template <class S, bool SHAK, bool TL>
 __global__ __launch_bounds__(256) void k_flux(Params p) {
     using T = S;
+    extern __shared__ double fdyn[];
+    __shared__ FluxStage<S> fs;
     __shared__ double sh[4 * 4];
     int c, v0, v1;
     if (!chunk_block(p, p.vch, c, v0, v1)) return;
     const CellSide *cs = p.cs + 4 * c;
-    const int TW = p.nvx + p.nvy;
-    S *MG = (S *)p.d1 + ((size_t)c * 2) * p.nvp, *MH = MG + p.nvp;
+    const int TW = p.nvx + p.nvy, nvx = p.nvx, nvp = p.nvp, tid = threadIdx.x;
+    if (tid < 4) {
+        const CellSide &q = cs[tid];
+        fs.face[tid] = q.face; fs.type[tid] = q.type; fs.tie[tid] = q.tie; fs.wside[tid] = q.wside;
+        fs.nx[tid] = q.nx; fs.ny[tid] = q.ny; fs.S_[tid] = q.S;
+    }
+    if (tid < 4 * RT_N) {
+        const int q = tid / RT_N, e = tid - q * RT_N;
+        fs.rec[q][e] = cs[q].type == FT_SELF ? S(0) : ((const S *)p.recfT)[(size_t)cs[q].face * RT_N + e];
+    }
+    S *lt = (S *)fdyn;
+    if (TL)
+        for (int e = tid; e < 4 * TW; e += blockDim.x) {
+            const int q = e / TW, i = e - q * TW;
+            lt[e] = cs[q].type == FT_SELF ? S(0) : ((const S *)p.tabf)[(size_t)cs[q].face * TW + i];
+        }
+    __syncthreads();
+    S *MG = (S *)p.d1 + ((size_t)c * 2) * nvp, *MH = MG + nvp;
     double mw[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+    for (int v = v0 + tid; v < v1; v += blockDim.x) {
+        // keep the staged records in LDS, read per iteration (emits no code)
+        asm volatile("" ::: "memory");
         const int ix = p.vix[v], iy = p.viy[v];
-        const T x = (T)p.xi[v], y = (T)p.eta[v];
+        const double xd = p.xi[v], yd = p.eta[v];
+        const T x = (T)xd, y = (T)yd;
         T accG = T(0), accH = T(0);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int type = cs[s].type;
+            const int type = fs.type[s];
             if (type == FT_SELF) continue;
-            const int k = cs[s].face;
-            const double und = normal_speed(p.xi[v], p.eta[v], cs[s].nx, cs[s].ny);
-            const bool mine = und > 0.0 || (und == 0.0 && cs[s].tie);
+            const int k = fs.face[s];
+            const double und = normal_speed(xd, yd, fs.nx[s], fs.ny[s]);
+            const bool mine = und > 0.0 || (und == 0.0 && fs.tie[s]);
             const T un = (T)und;
+            const S *r = fs.rec[s];
             T fG, fH;
             if (mine || type == FT_INTERIOR) {  // reconstructed by the upwind cell
-                const S *fv = (const S *)p.fv + (size_t)k * 2 * p.nvp + v;
+                const S *fv = (const S *)p.fv + (size_t)k * 2 * nvp + v;
                 fG = fv[0];
-                fH = fv[p.nvp];
+                fH = fv[nvp];
             } else if (type == FT_WALL) {
-                const T rw = ((const S *)p.recfT)[(size_t)k * RT_N + 13];
-                const T g = (T)p.gw[(size_t)cs[s].wside * p.nvp + v];
+                const T rw = r[13];
+                const T g = (T)p.gw[(size_t)fs.wside[s] * nvp + v];
                 fG = rw * g;
-                fH = rw * (T)p.wKRT[cs[s].wside] * g;
+                fH = rw * (T)p.wKRT[fs.wside[s]] * g;
             } else {
                 fG = (T)p.ginf[v];
                 fH = (T)p.hinf[v];
             }
-            const RecT<T> rf = load_recT<S>(p.recfT, k);
-            const S *tf = (const S *)p.tabf + (size_t)k * TW;
+            RecT<T> rf;
+            rf.U = r[0]; rf.V = r[1]; rf.c0 = r[2]; rf.c1 = r[3]; rf.c2c = r[4]; rf.c3 = r[5];
+            rf.kqx = r[6]; rf.kqy = r[7]; rf.iRT = r[8]; rf.KRT = r[9]; rf.ab = r[10]; rf.bb = r[11];
+            const S *tf = TL ? (const S *)lt + s * TW : (const S *)p.tabf + (size_t)k * TW;
             T eG, eH;
-            eq_eval<T, SHAK>(rf, x, y, (T)tf[ix] * (T)tf[p.nvx + iy], eG, eH);
-            const T al = ((const S *)p.recfT)[(size_t)__builtin_amdgcn_readfirstlane(k) * RT_N + 12];
+            eq_eval<T, SHAK>(rf, x, y, (T)tf[ix] * (T)tf[nvx + iy], eG, eH);
+            const T al = r[12];
             const T pG = al * fG + (T(1) - al) * eG, pH = al * fH + (T(1) - al) * eH;
-            const T fl = (T)cs[s].S * un;
+            const T fl = (T)fs.S_[s] * un;
             accG -= fl * pG;
             accH -= fl * pH;
         }
         MG[v] = (S)accG;
         MH[v] = (S)accH;
-        const double wv = p.w[v], dx = (double)x, dy = (double)y, dG = (double)accG;
+        const double wv = p.w[v], dG = (double)accG;
         mw[0] += wv * dG;
-        mw[1] += wv * dx * dG;
-        mw[2] += wv * dy * dG;
-        mw[3] += 0.5 * wv * ((dx * dx + dy * dy) * dG + (double)accH);
+        mw[1] += wv * (double)x * dG;
+        mw[2] += wv * (double)y * dG;
+        mw[3] += 0.5 * wv * (((double)x * (double)x + (double)y * (double)y) * dG + (double)accH);
     }
     block_sum_store<4>(mw, sh, p.nch > 1 ? p.MWc + ((size_t)c * p.nch + v0 / p.vch) * 4 : p.MW + (size_t)c * 4);
 }
@@ -1943,11 +1976,19 @@ hipError_t launch_face_records(const Params &p, bool fp32, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_flux(const Params &p, bool fp32, hipStream_t st) {
+// the factored Maxwellians of the four faces go to LDS when they take at most 16 KiB
+template <class S, bool SHAK>
+static void launch_flux_t(const Params &p, hipStream_t st) {
     const dim3 g = chunk_grid(p, p.nch);
+    const size_t tl = (size_t)4 * (p.nvx + p.nvy) * sizeof(S);
+    if (tl <= 16384) hipLaunchKernelGGL((k_flux<S, SHAK, true>), g, dim3(256), tl, st, p);
+    else hipLaunchKernelGGL((k_flux<S, SHAK, false>), g, dim3(256), 0, st, p);
+}
+
+hipError_t launch_flux(const Params &p, bool fp32, hipStream_t st) {
     DISPATCH_S(fp32, {
-        if (p.model == 1) hipLaunchKernelGGL((k_flux<S, true>), g, dim3(256), 0, st, p);
-        else hipLaunchKernelGGL((k_flux<S, false>), g, dim3(256), 0, st, p);
+        if (p.model == 1) launch_flux_t<S, true>(p, st);
+        else launch_flux_t<S, false>(p, st);
     });
     if (p.nch > 1) return combine(p.MWc, p.MW, p, 4, st);
     return hipGetLastError();
