@@ -683,8 +683,14 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
 // predicted macroscopic step: LU-SGS of Eq. 29-31 (Rusanov split, matrix-free flux
 // differences, mirrored wall ghost) over i+j hyperplanes in one block
 // ---------------------------------------------------------------------------------------
-// 1/x within about an ulp: the hardware estimate refined by two Newton steps (a shorter
-// dependency chain than a correctly rounded division; x is a positive density here)
+// 1/x within about an ulp for a positive normal x (a density, a diagonal): the hardware
+// estimate refined by Newton steps, a shorter dependency chain than a correctly rounded
+// division
+DEV float rcp_nr(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 DEV double rcp_nr(double x) {
     double r = __builtin_amdgcn_rcp(x);
     double e = fma(-x, r, 1.0);
@@ -1186,9 +1192,6 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
             // this direction (sides i-, i+, j-, j+): forward f0[i-1], wI[j], f0[i], wJ[i];
             // backward wI[j], f0[i+1], wJ[i], f0[i] (the neighbours across a periodic seam
             // sit in wI / wJ), all read in one batch.
-            T mr[STG];
-#pragma unroll
-            for (int e = 0; e < STG; ++e) mr[e] = m[e];
             const T *sp[4];
             if (UPPER) { sp[0] = wI + fj; sp[1] = f0 + fi + W; sp[2] = wJ + fi; sp[3] = f0 + fi; }
             else { sp[0] = f0 + fi - W; sp[1] = wI + fj; sp[2] = f0 + fi; sp[3] = wJ + fi; }
@@ -1200,6 +1203,9 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
                     fg[u][sd] = sp[sd][u * vb];
                     fh[u][sd] = sp[sd][FR + u * vb];
                 }
+            T mr[STG];
+#pragma unroll
+            for (int e = 0; e < STG; ++e) mr[e] = m[e];
             RecT<T> r;
             if (!UPPER && !ADJ) {
                 r.U = mr[0]; r.V = mr[1]; r.c0 = mr[2]; r.c1 = mr[3]; r.c2c = mr[4]; r.c3 = mr[5];
@@ -1244,7 +1250,7 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
                         sH += gw * kw[sd];
                     }
                 }
-                const T iD = T(1) / D;
+                const T iD = rcp_nr(D);
                 dG[u] = UPPER ? cur.aG[u] + sG * iD : sG * iD;
                 dH[u] = UPPER ? cur.aH[u] + sH * iD : sH * iD;
             }
