@@ -550,14 +550,27 @@ __global__ __launch_bounds__(256) void k_face_records(Params p) {
     const S *fvG = (const S *)p.fv + (size_t)k * 2 * p.nvp, *fvH = fvG + p.nvp;
     double m[NM];
     for (int i = 0; i < NM; ++i) m[i] = 0.0;
-    for (int v = lane; v < p.nv; v += 64) {
-        bool use = true;
-        if (F.type != FT_INTERIOR) {
-            const double un = normal_speed(p.xi[v], p.eta[v], cL.nx, cL.ny);
-            use = un > 0.0 || (un == 0.0 && cL.tie);
+    // four velocities per lane and pass, so that a wave keeps four passes of loads in flight
+    for (int v0 = lane; v0 < p.nv; v0 += 256) {
+        double xs[4], ys[4], ws[4], gs[4], hs[4];
+        bool use[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int v = v0 + 64 * u;
+            use[u] = v < p.nv;
+            const int vc = use[u] ? v : 0;
+            xs[u] = p.xi[vc]; ys[u] = p.eta[vc]; ws[u] = p.w[vc];
+            gs[u] = (double)fvG[vc]; hs[u] = (double)fvH[vc];
         }
-        // (the inflow half of a boundary face is never written: skip it, do not weight it)
-        if (use) acc_moments<NM>(m, p.w[v], p.xi[v], p.eta[v], (double)fvG[v], (double)fvH[v]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (F.type != FT_INTERIOR) {
+                const double un = normal_speed(xs[u], ys[u], cL.nx, cL.ny);
+                use[u] = use[u] && (un > 0.0 || (un == 0.0 && cL.tie));
+            }
+            // (the inflow half of a boundary face is never written: skip it, do not weight it)
+            if (use[u]) acc_moments<NM>(m, ws[u], xs[u], ys[u], gs[u], hs[u]);
+        }
     }
     wave_sum<NM>(m);
     double rw = 0.0;
@@ -1311,9 +1324,19 @@ __global__ __launch_bounds__(256) void k_wall_ghost(Params p) {
     const Face F = p.faces[k];
     const S *d = (const S *)p.d1 + ((size_t)F.L * 2) * p.nvp;
     double a[1] = {0.0};
-    for (int v = lane; v < p.nv; v += 64) {
-        const double un = p.xi[v] * F.nx + p.eta[v] * F.ny;
-        if (un > 0.0) a[0] += p.w[v] * un * (double)d[v];
+    // four velocities per lane and pass (four passes of loads in flight per wave)
+    for (int v0 = lane; v0 < p.nv; v0 += 256) {
+        double un[4], ws[4], ds[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int v = v0 + 64 * u, vc = v < p.nv ? v : 0;
+            un[u] = v < p.nv ? p.xi[vc] * F.nx + p.eta[vc] * F.ny : 0.0;
+            ws[u] = p.w[vc];
+            ds[u] = (double)d[vc];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (un[u] > 0.0) a[0] += ws[u] * un[u] * ds[u];
     }
     wave_sum<1>(a);
     if (lane == 0) {
