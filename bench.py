@@ -18,11 +18,16 @@ sys.path.insert(0, ROOT)
 METRIC = "cell·velocity updates/s per LU-SGS iter; time-to-residual 1e-8; % HBM peak"
 HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per cell-velocity pair and launch (s = bytes per stored value,
-# both species G and H): flux reads phi~ and writes M; the forward sweep reads M and phi~
-# and writes the increment; the backward sweep reads the increment and phi~, writes phi~
-ALGO_BYTES = {"flux": 4, "sweep_lower": 6, "sweep_upper": 6, "face_partials": 2,
-              "raw_moments": 2, "explicit_update": 6}
-MACRO_DOUBLES_PER_CELL = 25   # M_W (4), W (4), RT (1), face nx, ny, S (12) in; dW (4) out
+# both species G and H; a cell has about two faces of its own, nf ~ 2 nc): the face
+# partials read phi~ and write the reconstructed value at every face (one writer per face
+# and velocity, 4s); the face records read those (4s); the flux reads each face value
+# (once: the second cell of a face finds it in L2) and writes M; the forward sweep reads
+# M and phi~ and writes the increment; the backward sweep reads the increment and phi~,
+# writes phi~
+ALGO_BYTES = {"face_partials": 6, "face_records": 4, "flux": 6, "sweep_lower": 6,
+              "sweep_upper": 6, "raw_moments": 2, "explicit_update": 6}
+# per cell: M_W (4), W (4), sound speed, 1/D, side codes, face nx, ny, S (12) in; dW (4) out
+MACRO_DOUBLES_PER_CELL = 27
 
 
 def measured_traffic(tag, kernel):
@@ -215,7 +220,6 @@ def main():
     s_bytes = 8 if prec == wl.FP64 else 4
     per_launch_bytes = ALGO_BYTES.get(dom, 0) * s_bytes * nc * nv
     if dom == "macro_lusgs":
-        # per cell: M_W, W, RT and the normals and lengths of four faces in, dW out
         per_launch_bytes = nc * 8 * MACRO_DOUBLES_PER_CELL
     achieved = per_launch_bytes / (kernels[dom]["ms_avg_timed_region"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "kernel_ms": kernels[dom]["ms_avg_timed_region"],
@@ -227,7 +231,7 @@ def main():
         roofline["note"] = ("one workgroup sweeps 2 x (ni+nj-1) dependent hyperplane steps: "
                             "bound by the step latency, not by bandwidth")
     streaming = {}
-    for k in ("flux", "sweep_lower", "sweep_upper"):
+    for k in ("face_partials", "face_records", "flux", "sweep_lower", "sweep_upper"):
         if k in kernels:
             b = ALGO_BYTES[k] * s_bytes * nc * nv
             gbs = b / (kernels[k]["ms_avg"] * 1e-3) / 1e9
