@@ -47,6 +47,40 @@ DEV void wave_sum(double (&a)[N]) {
     }
 }
 
+// x of another lane by a DPP control (quad permutations 0xB1 = lane^1, 0x4E = lane^2; row
+// mirror 0x140 = lane 15-i and half-row mirror 0x141 = lane 7-i within 16 lanes), two
+// 32-bit moves; every lane of the wave must be active
+template <int CTRL>
+DEV double dpp_d(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+DEV double readlane_d(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the wave by DPP (the same value in every lane, fixed order): quad sums, then
+// the sums of 8 and of 16 lanes by the mirrors (both partners add the same two values,
+// so every lane of a row holds its row's sum), then the four row sums in order.  For
+// waves with every lane active; a few register moves instead of six LDS permutes.
+template <int N>
+DEV void wave_sum_dpp(double (&a)[N]) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        double x = a[m];
+        x += dpp_d<0xB1>(x);
+        x += dpp_d<0x4E>(x);
+        x += dpp_d<0x141>(x);
+        x += dpp_d<0x140>(x);
+        a[m] = (readlane_d(x, 0) + readlane_d(x, 16)) + (readlane_d(x, 32) + readlane_d(x, 48));
+    }
+}
+
 // Sum over the whole block; sh must hold (blockDim/64)*N doubles.  Fixed order.
 template <int N>
 DEV void block_sum(double (&a)[N], double *sh) {
@@ -180,29 +214,28 @@ DEV double tau_of(const Params &p, double rho, double RT) {
     return p.mu_ref * pow(2.0 * RT, p.omega) / (rho * RT);
 }
 
-DEV void solve4(double A[4][4], double b[4]) {
+// A x = b for a symmetric positive definite A (the moment matrix of the conserved-moment
+// basis under a positive weight): elimination without pivoting is stable for it and
+// unrolls to straight-line code (no dynamic register indexing)
+DEV void solve_spd4(double A[4][4], double b[4]) {
+    double ik[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        int piv = k;
-        for (int r = k + 1; r < 4; ++r)
-            if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
-        if (piv != k) {
-            for (int c = 0; c < 4; ++c) {
-                double t = A[k][c]; A[k][c] = A[piv][c]; A[piv][c] = t;
-            }
-            double t = b[k]; b[k] = b[piv]; b[piv] = t;
-        }
+        ik[k] = 1.0 / A[k][k];
+#pragma unroll
         for (int r = k + 1; r < 4; ++r) {
-            double m = A[r][k] / A[k][k];
-            for (int c = k; c < 4; ++c) A[r][c] -= m * A[k][c];
+            const double m = A[r][k] * ik[k];
+#pragma unroll
+            for (int c = k + 1; c < 4; ++c) A[r][c] -= m * A[k][c];
             b[r] -= m * b[k];
         }
     }
 #pragma unroll
     for (int k = 3; k >= 0; --k) {
         double s = b[k];
+#pragma unroll
         for (int c = k + 1; c < 4; ++c) s -= A[k][c] * b[c];
-        b[k] = s / A[k][k];
+        b[k] = s * ik[k];
     }
 }
 
@@ -235,8 +268,8 @@ DEV void build_eq(const Params &p, double rho, double U, double V, double RT, do
 #pragma unroll
         for (int k = 0; k < NP; ++k) { Y[k] += t; t *= cy; }
     }
-    wave_sum<NP>(X);
-    wave_sum<NP>(Y);
+    wave_sum_dpp<NP>(X);
+    wave_sum_dpp<NP>(Y);
     auto m = [&](int a, int b) { return A0 * X[a] * Y[b]; };
     double A[4][4], Ac[4][4], r[4];
     A[0][0] = m(0, 0); A[0][1] = m(1, 0); A[0][2] = m(0, 1); A[0][3] = 0.5 * (m(2, 0) + m(0, 2));
@@ -251,7 +284,7 @@ DEV void build_eq(const Params &p, double rho, double U, double V, double RT, do
     r[3] = rho * RT - A[0][3];
     for (int a = 0; a < 4; ++a)
         for (int b = 0; b < 4; ++b) Ac[a][b] = A[a][b];
-    solve4(Ac, r);
+    solve_spd4(Ac, r);
     double kap = 0.0;
     if (SHAK && (qx != 0.0 || qy != 0.0)) {
         kap = (1.0 - p.Pr) / (5.0 * rho * RT * RT);
@@ -275,7 +308,7 @@ DEV void build_eq(const Params &p, double rho, double U, double V, double RT, do
             d[a] *= kap;
             for (int b = 0; b < 4; ++b) Ac[a][b] = A[a][b];
         }
-        solve4(Ac, d);
+        solve_spd4(Ac, d);
         for (int a = 0; a < 4; ++a) r[a] -= d[a];
     }
     if (lane == 0) {
@@ -572,7 +605,7 @@ __global__ __launch_bounds__(256) void k_face_records(Params p) {
             if (use[u]) acc_moments<NM>(m, ws[u], xs[u], ys[u], gs[u], hs[u]);
         }
     }
-    wave_sum<NM>(m);
+    wave_sum_dpp<NM>(m);
     double rw = 0.0;
     if (F.type != FT_INTERIOR) {
         const double *b = p.bhalf + (size_t)k * NM_MAX;
@@ -1338,7 +1371,7 @@ __global__ __launch_bounds__(256) void k_wall_ghost(Params p) {
         for (int u = 0; u < 4; ++u)
             if (un[u] > 0.0) a[0] += ws[u] * un[u] * ds[u];
     }
-    wave_sum<1>(a);
+    wave_sum_dpp<1>(a);
     if (lane == 0) {
         const double d = -a[0] / p.wden[k];
         p.drho[k] = d;
