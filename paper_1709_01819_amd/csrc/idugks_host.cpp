@@ -682,12 +682,19 @@ idugks_status timed(idugks_ctx *x, int kid, F &&launch) {
         if (s_ != IDUGKS_OK) return s_;                           \
     } while (0)
 
-idugks_status flux_pipeline(idugks_ctx *x) {
+// cell and face records, reconstruction at the faces
+idugks_status face_pipeline(idugks_ctx *x) {
     const Params &p = x->p;
     RUN(KID_RECORDS, launch_records(p, x->fp32, 0, x->st));
     RUN(KID_PARTIALS, launch_partials(p, x->fp32, x->st));
     RUN(KID_FACE_RECORDS, launch_face_records(p, x->fp32, x->st));
-    RUN(KID_FLUX, launch_flux(p, x->fp32, x->st));
+    return IDUGKS_OK;
+}
+
+idugks_status flux_pipeline(idugks_ctx *x) {
+    idugks_status s = face_pipeline(x);
+    if (s != IDUGKS_OK) return s;
+    RUN(KID_FLUX, launch_flux(x->p, x->fp32, x->st));
     return IDUGKS_OK;
 }
 
@@ -700,16 +707,24 @@ idugks_status finalize_state(idugks_ctx *x, int mode) {
 
 idugks_status one_step(idugks_ctx *x, int mode) {
     const Params &p = x->p;
-    idugks_status s = flux_pipeline(x);
+    idugks_status s = face_pipeline(x);
     if (s != IDUGKS_OK) return s;
     if (mode == IDUGKS_IMPLICIT) {
-        RUN(KID_MACRO_PREP, launch_macro_prep(p, x->st));
+        if (p.nch == 1) {  // the flux blocks write the macro rows
+            Params q = p;
+            q.prep_in_flux = 1;
+            RUN(KID_FLUX, launch_flux(q, x->fp32, x->st));
+        } else {
+            RUN(KID_FLUX, launch_flux(p, x->fp32, x->st));
+            RUN(KID_MACRO_PREP, launch_macro_prep(p, x->st));
+        }
         RUN(KID_MACRO, launch_macro(p, x->st));
         RUN(KID_RECORDS_PRED, launch_records(p, x->fp32, 1, x->st));
         RUN(KID_LOWER, launch_sweep(p, x->fp32, false, x->sweep, x->st));
         RUN(KID_WALL_GHOST, launch_wall_ghost(p, x->fp32, x->st));
         RUN(KID_UPPER, launch_sweep(p, x->fp32, true, x->sweep, x->st));
     } else {
+        RUN(KID_FLUX, launch_flux(p, x->fp32, x->st));
         RUN(KID_EXPLICIT, launch_explicit(p, x->fp32, x->st));
     }
     return finalize_state(x, mode == IDUGKS_IMPLICIT ? 1 : 2);
@@ -807,7 +822,7 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     Params &p = x->p;
     memset(&p, 0, sizeof p);
     p.ni = b.ni; p.nj = b.nj; p.nc = b.nc; p.nf = b.nf; p.nv = b.nv; p.nvp = b.nvp;
-    p.vch = vel_chunk(b.nv); p.nch = (b.nv + p.vch - 1) / p.vch;
+    p.vch = vel_chunk(b.nv); p.nch = (b.nv + p.vch - 1) / p.vch; p.prep_in_flux = 0;
     p.nvx = b.nvx; p.nvy = b.nvy; p.K = cfg->K; p.model = cfg->model; p.limiter = cfg->limiter;
     p.closed = b.closed; p.nm = cfg->model == IDUGKS_SHAKHOV ? NM_SHAKHOV : NM_BGK; p.nwall = b.nwall;
     p.dt = b.dt; p.h = 0.5 * b.dt; p.Pr = cfg->Pr; p.mu_ref = cfg->Kn / sqrt(M_PI);

@@ -96,6 +96,7 @@ enum Scalar : int { SC_SCALE = 0, SC_RES = 1, SC_MASS = 2, SC_FLAG = 3, SC_NUM =
 struct Params {
     int ni, nj, nc, nf, nv, nvp, nvx, nvy, K, model, limiter, closed, nm, nwall;
     int vch, nch;            // velocities per chunk of the flux kernel, chunks
+    int prep_in_flux;        // the flux kernel (one chunk) also writes the macro rows
     double dt, h, Pr, mu_ref, omega, cfl_imp, M0, gam;
     // velocity set
     const double *xi, *eta, *w;

@@ -633,7 +633,43 @@ __global__ __launch_bounds__(256) void k_face_records(Params p) {
 }
 
 // ---------------------------------------------------------------------------------------
-// flux: M_i(v) = -sum_k S (xi.n_out) phi_k (Eq. 18, 19, 23) and M_W = sum w psi M (Eq. 27)
+// Everything of Eq. 30-31 that does not depend on the increments, per cell: implicit time
+// step and inverse diagonal (a wall face carries its whole lambda S: mirrored ghost), stored
+// as the cell's macro row in i+j hyperplane order: M_W, 1/D, packed side codes, the cell's
+// W and sound speed, per side nx, ny, S.  The sweep takes a neighbour's W and sound speed
+// from the neighbour's own row (through LDS) and forms lambda_j there.
+// ---------------------------------------------------------------------------------------
+DEV void macro_row(const Params &p, int c, const double mw[4]) {
+    const CellSide *cs = p.cs + 4 * c;
+    double *m = p.mh + (size_t)p.hp_pos[c] * MH_N;
+    const double U = p.rec[c].U, V = p.rec[c].V, C = sqrt(p.gam * p.rec[c].RT);
+    double ls = 0.0, lw = 0.0;
+    int codes = 0;
+    for (int s = 0; s < 4; ++s) {
+        if (cs[s].type != FT_SELF && cs[s].nb >= 0)
+            codes |= (cs[s].nb < c ? SG_LOWER : SG_UPPER) << (MH_CODE_BITS * s);
+        double *ms = m + MH_SIDE + MH_SN * s;
+        ms[0] = cs[s].nx; ms[1] = cs[s].ny; ms[2] = cs[s].S;
+        if (cs[s].type == FT_SELF) continue;
+        const double l = (fabs(U * cs[s].nx + V * cs[s].ny) + C) * cs[s].S;
+        ls += l;
+        if (cs[s].type == FT_WALL) lw += l;
+    }
+    const double dti = p.cfl_imp * p.area[c] / ls;
+    p.dtimp[c] = dti;
+    for (int a = 0; a < 4; ++a) {
+        m[a] = mw[a];
+        m[6 + a] = p.Wc[(size_t)c * 4 + a];
+    }
+    m[4] = 1.0 / (p.area[c] / dti + 0.5 * ls + 0.5 * lw);
+    m[5] = (double)codes;
+    m[10] = C;
+}
+
+// ---------------------------------------------------------------------------------------
+// flux: M_i(v) = -sum_k S (xi.n_out) phi_k (Eq. 18, 19, 23) and M_W = sum w psi M (Eq. 27);
+// with a single velocity chunk the block holds its cell's whole M_W and, in an implicit
+// step, writes the cell's macro row as well (no separate launch)
 // ---------------------------------------------------------------------------------------
 // Loop-invariant data of a flux block, staged into LDS once: per side the face record
 // (with alpha and the wall density) and the side data.
@@ -644,7 +680,7 @@ struct FluxStage {
     int face[4], type[4], tie[4], wside[4];
 };
 
-template <class S, bool SHAK, bool TL>
+template <class S, bool SHAK, bool TL, bool PREP>
 __global__ __launch_bounds__(256) void k_flux(Params p) {
     using T = S;
     extern __shared__ double fdyn[];
@@ -722,7 +758,16 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
         mw[2] += wv * (double)y * dG;
         mw[3] += 0.5 * wv * (((double)x * (double)x + (double)y * (double)y) * dG + (double)accH);
     }
-    block_sum_store<4>(mw, sh, p.nch > 1 ? p.MWc + ((size_t)c * p.nch + v0 / p.vch) * 4 : p.MW + (size_t)c * 4);
+    if (PREP) {
+        block_sum<4>(mw, sh);
+        if (tid == 0) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) p.MW[(size_t)c * 4 + a] = mw[a];
+            macro_row(p, c, mw);
+        }
+    } else {
+        block_sum_store<4>(mw, sh, p.nch > 1 ? p.MWc + ((size_t)c * p.nch + v0 / p.vch) * 4 : p.MW + (size_t)c * 4);
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -759,38 +804,14 @@ DEV double euler_flux_n(const double W[4], double nx, double ny, double ik2, dou
     return un;
 }
 
-// Everything of Eq. 30-31 that does not depend on the increments, all cells in parallel:
-// implicit time step and inverse diagonal (a wall face carries its whole lambda S: mirrored
-// ghost).  Rows are stored in i+j hyperplane order: M_W, 1/D, packed side codes, the cell's
-// W and sound speed, per side nx, ny, S.  The sweep takes a neighbour's W and sound speed
-// from the neighbour's own row (through LDS) and forms lambda_j there.
+// The macro row of cell c from its M_W (the rest of Eq. 30-31 that does not depend on the
+// increments is computed here).
 __global__ __launch_bounds__(256) void k_macro_prep(Params p) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= p.nc) return;
-    const CellSide *cs = p.cs + 4 * c;
-    double *m = p.mh + (size_t)p.hp_pos[c] * MH_N;
-    const double U = p.rec[c].U, V = p.rec[c].V, C = sqrt(p.gam * p.rec[c].RT);
-    double ls = 0.0, lw = 0.0;
-    int codes = 0;
-    for (int s = 0; s < 4; ++s) {
-        if (cs[s].type != FT_SELF && cs[s].nb >= 0)
-            codes |= (cs[s].nb < c ? SG_LOWER : SG_UPPER) << (MH_CODE_BITS * s);
-        double *ms = m + MH_SIDE + MH_SN * s;
-        ms[0] = cs[s].nx; ms[1] = cs[s].ny; ms[2] = cs[s].S;
-        if (cs[s].type == FT_SELF) continue;
-        const double l = (fabs(U * cs[s].nx + V * cs[s].ny) + C) * cs[s].S;
-        ls += l;
-        if (cs[s].type == FT_WALL) lw += l;
-    }
-    const double dti = p.cfl_imp * p.area[c] / ls;
-    p.dtimp[c] = dti;
-    for (int a = 0; a < 4; ++a) {
-        m[a] = p.MW[(size_t)c * 4 + a];
-        m[6 + a] = p.Wc[(size_t)c * 4 + a];
-    }
-    m[4] = 1.0 / (p.area[c] / dti + 0.5 * ls + 0.5 * lw);
-    m[5] = (double)codes;
-    m[10] = C;
+    double mw[4];
+    for (int a = 0; a < 4; ++a) mw[a] = p.MW[(size_t)c * 4 + a];
+    macro_row(p, c, mw);
 }
 
 // All data exchanged inside the sweep kernels goes through LDS, so their barrier orders
@@ -2043,8 +2064,13 @@ template <class S, bool SHAK>
 static void launch_flux_t(const Params &p, hipStream_t st) {
     const dim3 g = chunk_grid(p, p.nch);
     const size_t tl = (size_t)4 * (p.nvx + p.nvy) * sizeof(S);
-    if (tl <= 16384) hipLaunchKernelGGL((k_flux<S, SHAK, true>), g, dim3(256), tl, st, p);
-    else hipLaunchKernelGGL((k_flux<S, SHAK, false>), g, dim3(256), 0, st, p);
+    if (p.prep_in_flux) {  // one chunk per cell (checked by the caller)
+        if (tl <= 16384) hipLaunchKernelGGL((k_flux<S, SHAK, true, true>), g, dim3(256), tl, st, p);
+        else hipLaunchKernelGGL((k_flux<S, SHAK, false, true>), g, dim3(256), 0, st, p);
+    } else {
+        if (tl <= 16384) hipLaunchKernelGGL((k_flux<S, SHAK, true, false>), g, dim3(256), tl, st, p);
+        else hipLaunchKernelGGL((k_flux<S, SHAK, false, false>), g, dim3(256), 0, st, p);
+    }
 }
 
 hipError_t launch_flux(const Params &p, bool fp32, hipStream_t st) {
