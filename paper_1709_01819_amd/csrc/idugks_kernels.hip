@@ -81,10 +81,12 @@ DEV void wave_sum_dpp(double (&a)[N]) {
     }
 }
 
-// Sum over the whole block; sh must hold (blockDim/64)*N doubles.  Fixed order.
-template <int N>
+// Sum over the whole block; sh must hold (blockDim/64)*N doubles.  Fixed order.  DPP: the
+// wave sums by DPP (every lane of the block active at the call).
+template <int N, bool DPP = false>
 DEV void block_sum(double (&a)[N], double *sh) {
-    wave_sum<N>(a);
+    if (DPP) wave_sum_dpp<N>(a);
+    else wave_sum<N>(a);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (lane == 0)
 #pragma unroll
@@ -101,9 +103,10 @@ DEV void block_sum(double (&a)[N], double *sh) {
 
 // Sum over the whole block written to out[0..N) by lanes 0..N-1 (fixed order; no dynamic
 // indexing of the register array).  sh must hold (blockDim/64)*N doubles.
-template <int N>
+template <int N, bool DPP = false>
 DEV void block_sum_store(double (&a)[N], double *sh, double *out) {
-    wave_sum<N>(a);
+    if (DPP) wave_sum_dpp<N>(a);
+    else wave_sum<N>(a);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (lane == 0)
 #pragma unroll
@@ -350,9 +353,20 @@ __global__ __launch_bounds__(256) void k_raw(Params p) {
     double a[NM];
 #pragma unroll
     for (int m = 0; m < NM; ++m) a[m] = 0.0;
-    for (int v = threadIdx.x; v < p.nv; v += blockDim.x)
-        acc_moments<NM>(a, p.w[v], p.xi[v], p.eta[v], (double)G[v], (double)H[v]);
-    block_sum_store<NM>(a, sh, p.raw + (size_t)c * NM_MAX);
+    // four velocities per lane and pass (four passes of loads in flight)
+    for (int v0 = threadIdx.x; v0 < p.nv; v0 += 4 * blockDim.x) {
+        double ws[4], xs[4], ys[4], gs[4], hs[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int v = v0 + u * blockDim.x, vc = v < p.nv ? v : 0;
+            ws[u] = v < p.nv ? p.w[vc] : 0.0;
+            xs[u] = p.xi[vc]; ys[u] = p.eta[vc];
+            gs[u] = (double)G[vc]; hs[u] = (double)H[vc];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc_moments<NM>(a, ws[u], xs[u], ys[u], gs[u], hs[u]);
+    }
+    block_sum_store<NM, true>(a, sh, p.raw + (size_t)c * NM_MAX);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -362,21 +376,47 @@ __global__ __launch_bounds__(256) void k_raw(Params p) {
 __global__ __launch_bounds__(1024) void k_finalize(Params p, int mode) {
     __shared__ double sh[16 * 3];
     const int NM = NM_MAX;
+    // each thread takes the cells tid, tid + B, ... (B = blockDim), four per pass so that
+    // four passes of loads are in flight, and sums them in that order
+    const int B = blockDim.x, tid = threadIdx.x;
     double a[1] = {0.0};
-    for (int c = threadIdx.x; c < p.nc; c += blockDim.x) a[0] += p.area[c] * p.raw[(size_t)c * NM];
-    block_sum<1>(a, sh);
+    for (int c0 = tid; c0 < p.nc; c0 += 4 * B) {
+        double ar[4], rr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + u * B, cc = c < p.nc ? c : 0;
+            ar[u] = c < p.nc ? p.area[cc] : 0.0;
+            rr[u] = p.raw[(size_t)cc * NM];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (c0 + u * B < p.nc) a[0] += ar[u] * rr[u];
+    }
+    block_sum<1, true>(a, sh);
     const double mass = a[0];
     const double s = (mode == 1 && p.closed) ? p.M0 / mass : 1.0;
     double b[3] = {0.0, 0.0, 0.0};
-    for (int c = threadIdx.x; c < p.nc; c += blockDim.x) {
-        const double r = s * p.raw[(size_t)c * NM], d = r - p.rho_old[c];
-        b[0] += d * d;
-        b[1] += r * r;
-        const double e = s * p.raw[(size_t)c * NM + 3];
-        if (!(r > 0.0) || !(e > 0.0) || !isfinite(r) || !isfinite(e)) b[2] += 1.0;
-        p.rho_old[c] = r;
+    for (int c0 = tid; c0 < p.nc; c0 += 4 * B) {
+        double r0[4], r3[4], ro[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + u * B, cc = c < p.nc ? c : 0;
+            r0[u] = p.raw[(size_t)cc * NM];
+            r3[u] = p.raw[(size_t)cc * NM + 3];
+            ro[u] = p.rho_old[cc];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (c0 + u * B >= p.nc) continue;
+            const double r = s * r0[u], d = r - ro[u];
+            b[0] += d * d;
+            b[1] += r * r;
+            const double e = s * r3[u];
+            if (!(r > 0.0) || !(e > 0.0) || !isfinite(r) || !isfinite(e)) b[2] += 1.0;
+            p.rho_old[c0 + u * B] = r;
+        }
     }
-    block_sum<3>(b, sh);
+    block_sum<3, true>(b, sh);
     if (threadIdx.x == 0) {
         p.scal[SC_SCALE] = s;
         p.scal[SC_MASS] = s * mass;
@@ -759,14 +799,14 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
         mw[3] += 0.5 * wv * (((double)x * (double)x + (double)y * (double)y) * dG + (double)accH);
     }
     if (PREP) {
-        block_sum<4>(mw, sh);
+        block_sum<4, true>(mw, sh);
         if (tid == 0) {
 #pragma unroll
             for (int a = 0; a < 4; ++a) p.MW[(size_t)c * 4 + a] = mw[a];
             macro_row(p, c, mw);
         }
     } else {
-        block_sum_store<4>(mw, sh, p.nch > 1 ? p.MWc + ((size_t)c * p.nch + v0 / p.vch) * 4 : p.MW + (size_t)c * 4);
+        block_sum_store<4, true>(mw, sh, p.nch > 1 ? p.MWc + ((size_t)c * p.nch + v0 / p.vch) * 4 : p.MW + (size_t)c * 4);
     }
 }
 
