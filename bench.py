@@ -228,8 +228,11 @@ def main():
                 "traffic": measured_traffic(f"{args.workload}:{args.precision}", dom),
                 "algorithmic_bytes_per_launch": per_launch_bytes}
     if dom == "macro_lusgs":
+        steps = 2 * (cfg["ni"] + cfg["nj"] - 1)
         roofline["note"] = ("one workgroup sweeps 2 x (ni+nj-1) dependent hyperplane steps: "
                             "bound by the step latency, not by bandwidth")
+        roofline["dependent_steps_per_launch"] = steps
+        roofline["us_per_step"] = 1e3 * roofline["kernel_ms"] / steps
     streaming = {}
     for k in ("face_partials", "face_records", "flux", "sweep_lower", "sweep_upper"):
         if k in kernels:
