@@ -175,8 +175,9 @@ idugks_status validate(const idugks_config *c) {
     if (!c) return fail(IDUGKS_E_INVALID, "null config");
     if (c->struct_size != sizeof(idugks_config)) return fail(IDUGKS_E_INVALID, "struct_size mismatch");
     if (c->ni < 1 || c->nj < 1) return fail(IDUGKS_E_INVALID, "mesh needs ni, nj >= 1");
-    if (std::min(c->ni, c->nj) > 280 || macro_shape(c->ni, c->nj).lds > 150 * 1024 ||
-        macro_shape(c->ni, c->nj).threads > 1024 || sweep_shape(c->ni, c->nj, 1, 8).vb == 0)
+    const bool per_i = c->bc[0] == IDUGKS_BC_PERIODIC, per_j = c->bc[2] == IDUGKS_BC_PERIODIC;
+    if (std::min(c->ni, c->nj) > 280 || macro_shape(c->ni, c->nj, per_i, per_j).lds > 150 * 1024 ||
+        macro_shape(c->ni, c->nj, per_i, per_j).threads > 1024 || sweep_shape(c->ni, c->nj, 1, 8).vb == 0)
         return fail(IDUGKS_E_INVALID, "mesh too large for the LDS-resident sweep fronts");
     if (!c->xn || !c->yn) return fail(IDUGKS_E_INVALID, "missing node coordinates");
     if (c->nvx < 2 || c->nvy < 2) return fail(IDUGKS_E_INVALID, "need nv >= 2 per direction");
@@ -823,6 +824,7 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     memset(&p, 0, sizeof p);
     p.ni = b.ni; p.nj = b.nj; p.nc = b.nc; p.nf = b.nf; p.nv = b.nv; p.nvp = b.nvp;
     p.vch = vel_chunk(b.nv); p.nch = (b.nv + p.vch - 1) / p.vch; p.prep_in_flux = 0;
+    p.per_i = cfg->bc[0] == IDUGKS_BC_PERIODIC; p.per_j = cfg->bc[2] == IDUGKS_BC_PERIODIC;
     p.nvx = b.nvx; p.nvy = b.nvy; p.K = cfg->K; p.model = cfg->model; p.limiter = cfg->limiter;
     p.closed = b.closed; p.nm = cfg->model == IDUGKS_SHAKHOV ? NM_SHAKHOV : NM_BGK; p.nwall = b.nwall;
     p.dt = b.dt; p.h = 0.5 * b.dt; p.Pr = cfg->Pr; p.mu_ref = cfg->Kn / sqrt(M_PI);

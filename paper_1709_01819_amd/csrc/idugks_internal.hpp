@@ -97,6 +97,7 @@ struct Params {
     int ni, nj, nc, nf, nv, nvp, nvx, nvy, K, model, limiter, closed, nm, nwall;
     int vch, nch;            // velocities per chunk of the flux kernel, chunks
     int prep_in_flux;        // the flux kernel (one chunk) also writes the macro rows
+    int per_i, per_j;        // the mesh is periodic in i / in j
     double dt, h, Pr, mu_ref, omega, cfl_imp, M0, gam;
     // velocity set
     const double *xi, *eta, *w;

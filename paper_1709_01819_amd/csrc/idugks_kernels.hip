@@ -908,7 +908,8 @@ DEV void stage_store(const double (&reg)[N], double *dst, int n, int sl, int nsl
 // parts by quad permutations, each keeping the components it finishes (q, q + LPC, ...).
 // LDS holds, per cell of the previous hyperplane, its increment, W and sound speed (fronts
 // of MF values, with a padding cell at each end), the same for the cells next to a periodic
-// seam (wI: column i = 0 / ni-1, wJ: row j = 0 / nj-1, the only non-adjacent neighbours),
+// seam (wI: column i = 0 / ni-1, wJ: row j = 0 / nj-1, the only non-adjacent neighbours;
+// allocated and written for periodic directions only),
 // the staged rows of the current and the next hyperplane and the increments of the last
 // two hyperplanes on their way to HBM.  The forward sweep's dW* go into the first four
 // values of each cell's row, which the backward sweep stages back.  The staging waves keep
@@ -923,12 +924,13 @@ __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
     const int ni = p.ni, nj = p.nj, nh = ni + nj - 1, L = ni < nj ? ni : nj;
     // LDS offsets (in doubles): the two fronts, the seam copies, the staged rows, the
     // out-buffers; the front of the previous hyperplane is A after an even number of steps
-    const int oA = MF, oB = oA + MF * (ni + 1), oI = oB + MF * (ni + 1), oJ = oI + MF * nj;
-    double *st0 = lds + oJ + MF * ni, *st1 = st0 + (size_t)L * MH_N;
+    const int oA = MF, oB = oA + MF * (ni + 1), oI = oB + MF * (ni + 1);
+    const int oJ = oI + (p.per_i ? MF * nj : 0), oE = oJ + (p.per_j ? MF * ni : 0);
+    double *st0 = lds + oE, *st1 = st0 + (size_t)L * MH_N;
     double *ob0 = st1 + (size_t)L * MH_N, *ob1 = ob0 + 4 * L;  // out-buffers by step parity
     int *hpo = (int *)(ob1 + 4 * L);
     for (int h = threadIdx.x; h <= nh; h += blockDim.x) hpo[h] = p.hp_off[h];
-    for (int e = threadIdx.x; e < oJ + MF * ni; e += blockDim.x) lds[e] = 0.0;
+    for (int e = threadIdx.x; e < oE; e += blockDim.x) lds[e] = 0.0;
     __syncthreads();
     const double ik2 = 1.0 / (p.K + 2);
     // Both roles run the same number of barriers: one after the prologue and one per
@@ -1002,8 +1004,9 @@ __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
         // The one neighbour each side of this lane can couple to in this direction (sides
         // i-, i+, j-, j+): forward front[i-1], wI[j], front[i], wJ[i]; backward wI[j],
         // front[i+1], wJ[i], front[i].  Per side: whether it is a front entry, the offset of
-        // its index, and the seam copy (indexed by j for wI, i for wJ).
-        bool isf[NS], usej[NS];
+        // its index, and the seam copy (indexed by j for wI, i for wJ).  A seam side of a
+        // direction that is not periodic has no coupling; it reads entry 0 of front A.
+        bool isf[NS], usej[NS], idx[NS];
         int dl[NS], sb[NS];
 #pragma unroll
         for (int u = 0; u < NS; ++u) {
@@ -1011,7 +1014,9 @@ __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
             isf[u] = (sd & 1) == (upper ? 1 : 0);
             usej[u] = !isf[u] && sd < 2;
             dl[u] = isf[u] && sd < 2 ? (upper ? 1 : -1) : 0;
-            sb[u] = sd < 2 ? oI : oJ;
+            const bool per = sd < 2 ? p.per_i : p.per_j;
+            idx[u] = isf[u] || per;
+            sb[u] = per ? (sd < 2 ? oI : oJ) : oA;
         }
         lds_barrier();
         for (int t = 0; t < nh; ++t, ++T) {
@@ -1028,7 +1033,7 @@ __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
             double ms[NS][MH_SN], mr[NS], wo[NS], nb[NS][MF];
 #pragma unroll
             for (int u = 0; u < NS; ++u) {
-                const int o = (isf[u] ? cur : sb[u]) + MF * (usej[u] ? j : i + dl[u]);
+                const int o = (isf[u] ? cur : sb[u]) + (idx[u] ? MF * (usej[u] ? j : i + dl[u]) : 0);
 #pragma unroll
                 for (int e = 0; e < MF; ++e) nb[u][e] = lds[o + e];
                 mr[u] = m[q + u * LPC];      // component q + u LPC of M_W, which this lane finishes
@@ -1067,7 +1072,7 @@ __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
                 ra[NS - 1] = c1;
             }
             if (live) {
-                const bool sI = i == (upper ? ni - 1 : 0), sJ = j == (upper ? nj - 1 : 0);
+                const bool sI = p.per_i && i == (upper ? ni - 1 : 0), sJ = p.per_j && j == (upper ? nj - 1 : 0);
 #pragma unroll
                 for (int u = 0; u < NS; ++u) {
                     const int a = q + u * LPC;
@@ -2127,7 +2132,7 @@ static int round64(int n) { return (n + 63) / 64 * 64; }
 // The deepest staging prefetch first (fewest values per staging lane: 32 registers hold
 // MD x SPWM values), then the most lanes per cell (4 or 2), that fit 1024 lanes.  Meshes
 // too wide for that are rejected at init (their LDS would not fit either).
-MacroShape macro_shape(int ni, int nj) {
+MacroShape macro_shape(int ni, int nj, bool per_i, bool per_j) {
     const int L = ni < nj ? ni : nj, nh = ni + nj - 1;
     auto waves = [&](int spw) { return (L * MH_N + 64 * spw - 1) / (64 * spw); };
     MacroShape m{};
@@ -2141,7 +2146,8 @@ MacroShape macro_shape(int ni, int nj) {
         }
         if (m.threads <= 1024) break;
     }
-    m.lds = (size_t)(MF * (3 * ni + nj + 3) + 2 * L * MH_N + 8 * L) * sizeof(double) + (size_t)(nh + 1) * sizeof(int);
+    const int seams = (per_i ? nj : 0) + (per_j ? ni : 0);
+    m.lds = (size_t)(MF * (2 * ni + 3 + seams) + 2 * L * MH_N + 8 * L) * sizeof(double) + (size_t)(nh + 1) * sizeof(int);
     return m;
 }
 
@@ -2172,7 +2178,7 @@ hipError_t launch_macro_prep(const Params &p, hipStream_t st) {
 }
 
 hipError_t launch_macro(const Params &p, hipStream_t st) {
-    const MacroShape m = macro_shape(p.ni, p.nj);
+    const MacroShape m = macro_shape(p.ni, p.nj, p.per_i, p.per_j);
     return m.lpc == 4 ? launch_macro_l<4>(p, m, st) : launch_macro_l<2>(p, m, st);
 }
 

@@ -7,6 +7,6 @@ from .cases import (  # noqa: F401
     BC_WALL, BC_FARFIELD, BC_PERIODIC, GAUSS_HERMITE, NEWTON_COTES, BGK, SHAKHOV,
     FP64, FP32_MIXED, EXPLICIT, IMPLICIT,
     uniform_nodes, tanh_nodes, cartesian_mesh, ogrid_mesh,
-    couette, cavity, cylinder, periodic_box, shrink, case, CASE_NAMES,
+    couette, cavity, cavity_re, cylinder, periodic_box, shrink, case, CASE_NAMES,
     perturbation,
 )
