@@ -80,6 +80,11 @@ typedef struct {
     int32_t precision;           /* IDUGKS_FP64 or IDUGKS_FP32_MIXED (FP32 distributions,
                                     FP64 moments, records, predictor and residuals) */
     double init_rho, init_u, init_v, init_T; /* initial uniform equilibrium */
+    int32_t predictor;           /* macroscopic prediction step (Section 2.2; the conclusions
+                                    name both): 0 LU-SGS sweeps of Eq. 29-31, 1 point
+                                    relaxation of the same system (Jacobi) */
+    int32_t relax_sweeps;        /* point relaxation: Jacobi sweeps after the point-implicit
+                                    step dW = D^-1 M_W, 0..64 */
 } idugks_config;
 
 typedef struct {

@@ -86,7 +86,7 @@ struct orc_problem {
     double *fmx, *fmy;           /* midpoint in L's frame */
     double *fshx, *fshy;         /* periodic shift: R's frame = L's frame - shift */
     /* gas */
-    int model, K, limiter, closed;
+    int model, K, limiter, closed, predictor, relax_sweeps;
     double Kn, Pr, omega, mu_ref, dt, h, cfl_imp;
     double wall_u[4], wall_v[4], wall_RT[4];
     double *gw;                  /* [4][nv] G of the wall Maxwellian at unit density */
@@ -575,6 +575,8 @@ static int validate(const orc_config *c)
     if (!c) return fail(ORC_INVALID, "null config");
     if (c->ni < 1 || c->nj < 1) return fail(ORC_INVALID, "mesh needs ni, nj >= 1");
     if (!c->xn || !c->yn) return fail(ORC_INVALID, "missing node coordinates");
+    if (c->predictor < 0 || c->predictor > 1) return fail(ORC_INVALID, "unknown predictor");
+    if (c->relax_sweeps < 0 || c->relax_sweeps > 64) return fail(ORC_INVALID, "relax_sweeps must be 0..64");
     if (c->nvx < 2 || c->nvy < 2) return fail(ORC_INVALID, "need nv >= 2");
     if (!(c->Kn > 0)) return fail(ORC_INVALID, "Kn must be positive");
     if (!(c->Pr > 0)) return fail(ORC_INVALID, "Pr must be positive");
@@ -646,6 +648,8 @@ int orc_create(const orc_config *cfg, orc_problem **out)
     p->model = cfg->model;
     p->K = cfg->K;
     p->limiter = cfg->limiter;
+    p->predictor = cfg->predictor;
+    p->relax_sweeps = cfg->relax_sweeps;
     p->Kn = cfg->Kn;
     p->Pr = cfg->Pr;
     p->omega = cfg->omega;
@@ -1171,7 +1175,50 @@ static void euler_flux(const double W[4], double nx, double ny, int K, double F[
     F[3] = (W[3] + pr) * un;
 }
 
-/* Predicted macroscopic step (Eq. 27-31): LU-SGS on (L + D + U) dW = M_W. */
+/* 1/2 S (F_n(W_j + dW_j) - F_n(W_j) - lambda_j dW_j) of one cell side m with neighbour j:
+   the matrix-free off-diagonal term of Eq. 30 (Rusanov split, lambda of Eq. 31) */
+static void offdiag(const orc_problem *p, const double *C, int m, int j, const double *dWj,
+                    double out[4])
+{
+    double nx = p->onx[m], ny = p->ony[m], S = p->sS[m];
+    const double *Wj = p->W + 4 * j;
+    double lam = fabs((Wj[1] * nx + Wj[2] * ny) / Wj[0]) + C[j];
+    double Wn[4] = {Wj[0] + dWj[0], Wj[1] + dWj[1], Wj[2] + dWj[2], Wj[3] + dWj[3]};
+    double F1[4], F0[4];
+    euler_flux(Wn, nx, ny, p->K, F1);
+    euler_flux(Wj, nx, ny, p->K, F0);
+    for (int a = 0; a < 4; ++a) out[a] = 0.5 * S * (F1[a] - F0[a] - lam * dWj[a]);
+}
+
+/* Point relaxation of (L + D + U) dW = M_W (the paper's second predictor, Section 4; it
+   gives no formula): the point-implicit step dW = D^-1 M_W, then Jacobi sweeps
+   dW <- D^-1 (M_W - (L + U) dW) with every neighbour's dW of the previous sweep. */
+static void macro_point_relax(orc_problem *p, const double *C)
+{
+    const int nc = p->nc;
+    double *old = malloc(4 * (size_t)nc * sizeof(double));
+    for (int c = 0; c < nc; ++c)
+        for (int a = 0; a < 4; ++a) p->dW[4 * c + a] = p->MW[4 * c + a] / p->DW[c];
+    for (int k = 0; k < p->relax_sweeps; ++k) {
+        memcpy(old, p->dW, 4 * (size_t)nc * sizeof(double));
+        for (int c = 0; c < nc; ++c) {
+            double r[4];
+            for (int a = 0; a < 4; ++a) r[a] = p->MW[4 * c + a];
+            for (int side = 0; side < 4; ++side) {
+                int m = 4 * c + side, kf = p->cf[m], j = p->nb[m];
+                if (p->ftype[kf] == F_SELF || j < 0) continue;
+                double o[4];
+                offdiag(p, C, m, j, old + 4 * j, o);
+                for (int a = 0; a < 4; ++a) r[a] -= o[a];
+            }
+            for (int a = 0; a < 4; ++a) p->dW[4 * c + a] = r[a] / p->DW[c];
+        }
+    }
+    free(old);
+}
+
+/* Predicted macroscopic step (Eq. 27-31): LU-SGS on (L + D + U) dW = M_W, or point
+   relaxation of the same system. */
 static void macro_lusgs(orc_problem *p)
 {
     const int nc = p->nc, K = p->K;
@@ -1194,40 +1241,44 @@ static void macro_lusgs(orc_problem *p)
         p->dtimp[c] = p->cfl_imp * p->area[c] / ls;
         p->DW[c] = p->area[c] / p->dtimp[c] + 0.5 * ls + 0.5 * lw;
     }
-    /* lower sweep (ascending cell index) */
-    for (int c = 0; c < nc; ++c) {
-        double r[4];
-        for (int a = 0; a < 4; ++a) r[a] = p->MW[4 * c + a];
-        for (int side = 0; side < 4; ++side) {
-            int m = 4 * c + side, k = p->cf[m], j = p->nb[m];
-            if (p->ftype[k] == F_SELF || j < 0 || j > c) continue;
-            double nx = p->onx[m], ny = p->ony[m], S = p->sS[m];
-            const double *Wj = p->W + 4 * j, *dWj = p->dW + 4 * j;
-            double lam = fabs((Wj[1] * nx + Wj[2] * ny) / Wj[0]) + C[j];
-            double Wn[4] = {Wj[0] + dWj[0], Wj[1] + dWj[1], Wj[2] + dWj[2], Wj[3] + dWj[3]};
-            double F1[4], F0[4];
-            euler_flux(Wn, nx, ny, K, F1);
-            euler_flux(Wj, nx, ny, K, F0);
-            for (int a = 0; a < 4; ++a) r[a] -= 0.5 * S * (F1[a] - F0[a] - lam * dWj[a]);
+    if (p->predictor == 1) {
+        macro_point_relax(p, C);
+    } else {
+        /* lower sweep (ascending cell index) */
+        for (int c = 0; c < nc; ++c) {
+            double r[4];
+            for (int a = 0; a < 4; ++a) r[a] = p->MW[4 * c + a];
+            for (int side = 0; side < 4; ++side) {
+                int m = 4 * c + side, k = p->cf[m], j = p->nb[m];
+                if (p->ftype[k] == F_SELF || j < 0 || j > c) continue;
+                double nx = p->onx[m], ny = p->ony[m], S = p->sS[m];
+                const double *Wj = p->W + 4 * j, *dWj = p->dW + 4 * j;
+                double lam = fabs((Wj[1] * nx + Wj[2] * ny) / Wj[0]) + C[j];
+                double Wn[4] = {Wj[0] + dWj[0], Wj[1] + dWj[1], Wj[2] + dWj[2], Wj[3] + dWj[3]};
+                double F1[4], F0[4];
+                euler_flux(Wn, nx, ny, K, F1);
+                euler_flux(Wj, nx, ny, K, F0);
+                for (int a = 0; a < 4; ++a) r[a] -= 0.5 * S * (F1[a] - F0[a] - lam * dWj[a]);
+            }
+            for (int a = 0; a < 4; ++a) p->dW[4 * c + a] = r[a] / p->DW[c];
         }
-        for (int a = 0; a < 4; ++a) p->dW[4 * c + a] = r[a] / p->DW[c];
-    }
-    /* upper sweep (descending cell index) */
-    for (int c = nc - 1; c >= 0; --c) {
-        double r[4] = {0, 0, 0, 0};
-        for (int side = 0; side < 4; ++side) {
-            int m = 4 * c + side, k = p->cf[m], j = p->nb[m];
-            if (p->ftype[k] == F_SELF || j < 0 || j < c) continue;
-            double nx = p->onx[m], ny = p->ony[m], S = p->sS[m];
-            const double *Wj = p->W + 4 * j, *dWj = p->dW + 4 * j;
-            double lam = fabs((Wj[1] * nx + Wj[2] * ny) / Wj[0]) + C[j];
-            double Wn[4] = {Wj[0] + dWj[0], Wj[1] + dWj[1], Wj[2] + dWj[2], Wj[3] + dWj[3]};
-            double F1[4], F0[4];
-            euler_flux(Wn, nx, ny, K, F1);
-            euler_flux(Wj, nx, ny, K, F0);
-            for (int a = 0; a < 4; ++a) r[a] += 0.5 * S * (F1[a] - F0[a] - lam * dWj[a]);
+        /* upper sweep (descending cell index) */
+        for (int c = nc - 1; c >= 0; --c) {
+            double r[4] = {0, 0, 0, 0};
+            for (int side = 0; side < 4; ++side) {
+                int m = 4 * c + side, k = p->cf[m], j = p->nb[m];
+                if (p->ftype[k] == F_SELF || j < 0 || j < c) continue;
+                double nx = p->onx[m], ny = p->ony[m], S = p->sS[m];
+                const double *Wj = p->W + 4 * j, *dWj = p->dW + 4 * j;
+                double lam = fabs((Wj[1] * nx + Wj[2] * ny) / Wj[0]) + C[j];
+                double Wn[4] = {Wj[0] + dWj[0], Wj[1] + dWj[1], Wj[2] + dWj[2], Wj[3] + dWj[3]};
+                double F1[4], F0[4];
+                euler_flux(Wn, nx, ny, K, F1);
+                euler_flux(Wj, nx, ny, K, F0);
+                for (int a = 0; a < 4; ++a) r[a] += 0.5 * S * (F1[a] - F0[a] - lam * dWj[a]);
+            }
+            for (int a = 0; a < 4; ++a) p->dW[4 * c + a] -= r[a] / p->DW[c];
         }
-        for (int a = 0; a < 4; ++a) p->dW[4 * c + a] -= r[a] / p->DW[c];
     }
     free(C);
     /* W* = W^n + dW; tau* and the predicted equilibrium (heat flux of step n) */

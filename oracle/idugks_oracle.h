@@ -38,6 +38,8 @@ typedef struct {
     double cfl_phys, cfl_imp;       /* physical (flux) and implicit (pseudo-time) CFL numbers */
     int32_t limiter;                /* 0 none, 1 Venkatakrishnan (Eq. 16-17) */
     double init_rho, init_u, init_v, init_T;
+    int32_t predictor;              /* 0 LU-SGS, 1 point relaxation (both named in Section 4) */
+    int32_t relax_sweeps;           /* point relaxation: Jacobi sweeps after the diagonal step */
 } orc_config;
 
 typedef struct orc_problem orc_problem;

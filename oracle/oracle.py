@@ -36,7 +36,7 @@ class OrcConfig(C.Structure):
         ("K", C.c_int32),
         ("cfl_phys", C.c_double), ("cfl_imp", C.c_double), ("limiter", C.c_int32),
         ("init_rho", C.c_double), ("init_u", C.c_double), ("init_v", C.c_double),
-        ("init_T", C.c_double),
+        ("init_T", C.c_double), ("predictor", C.c_int32), ("relax_sweeps", C.c_int32),
     ]
 
 
@@ -128,6 +128,8 @@ class Oracle:
                   "Kn", "Pr", "omega", "K", "cfl_phys", "cfl_imp", "limiter", "init_rho",
                   "init_u", "init_v", "init_T"):
             setattr(c, k, cfg[k])
+        c.predictor = cfg.get("predictor", 0)
+        c.relax_sweeps = cfg.get("relax_sweeps", 0)
         h = _P()
         rc = lib.orc_create(C.byref(c), C.byref(h))
         if rc:

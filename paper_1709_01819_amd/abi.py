@@ -35,7 +35,7 @@ class Config(C.Structure):
         ("cfl_phys", C.c_double), ("cfl_imp", C.c_double), ("limiter", C.c_int32),
         ("precision", C.c_int32),
         ("init_rho", C.c_double), ("init_u", C.c_double), ("init_v", C.c_double),
-        ("init_T", C.c_double),
+        ("init_T", C.c_double), ("predictor", C.c_int32), ("relax_sweeps", C.c_int32),
     ]
 
 
@@ -124,6 +124,8 @@ def make_config(cfg):
               "Pr", "omega", "K", "cfl_phys", "cfl_imp", "limiter", "precision", "init_rho",
               "init_u", "init_v", "init_T"):
         setattr(c, k, cfg[k])
+    c.predictor = cfg.get("predictor", 0)
+    c.relax_sweeps = cfg.get("relax_sweeps", 0)
     return c, (xn, yn)
 
 

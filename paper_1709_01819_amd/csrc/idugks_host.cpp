@@ -139,11 +139,13 @@ struct Layout {
 
 enum KernelId {
     KID_RECORDS, KID_PARTIALS, KID_FACE_RECORDS, KID_FLUX, KID_MACRO_PREP, KID_MACRO, KID_RECORDS_PRED,
-    KID_LOWER, KID_WALL_GHOST, KID_UPPER, KID_EXPLICIT, KID_RAW, KID_FINALIZE, KID_COUNT
+    KID_LOWER, KID_WALL_GHOST, KID_UPPER, KID_EXPLICIT, KID_RAW, KID_FINALIZE, KID_MACRO_RELAX,
+    KID_COUNT
 };
 const char *kKernelNames[KID_COUNT] = {
     "records", "face_partials", "face_records", "flux", "macro_prep", "macro_lusgs", "records_pred",
-    "sweep_lower", "wall_ghost", "sweep_upper", "explicit_update", "raw_moments", "finalize"};
+    "sweep_lower", "wall_ghost", "sweep_upper", "explicit_update", "raw_moments", "finalize",
+    "macro_relax"};
 
 }  // namespace
 
@@ -180,6 +182,9 @@ idugks_status validate(const idugks_config *c) {
         macro_shape(c->ni, c->nj, per_i, per_j).threads > 1024 || sweep_shape(c->ni, c->nj, 1, 8).vb == 0)
         return fail(IDUGKS_E_INVALID, "mesh too large for the LDS-resident sweep fronts");
     if (!c->xn || !c->yn) return fail(IDUGKS_E_INVALID, "missing node coordinates");
+    if (c->predictor != 0 && c->predictor != 1) return fail(IDUGKS_E_INVALID, "unknown predictor");
+    if (c->relax_sweeps < 0 || c->relax_sweeps > 64)
+        return fail(IDUGKS_E_INVALID, "relax_sweeps must be 0..64");
     if (c->nvx < 2 || c->nvy < 2) return fail(IDUGKS_E_INVALID, "need nv >= 2 per direction");
     if (c->nvx > 4096 || c->nvy > 4096) return fail(IDUGKS_E_INVALID, "velocity grid too large");
     {
@@ -611,7 +616,7 @@ enum Region {
     R_STAGE, R_HPOFF, R_HPPOS, R_SGEO, R_SREC, R_SDRHO, R_MH, R_FV, R_MWC, R_RECT, R_RECFT,
     // sensitivities (empty unless BGK, no limiter, FP64)
     R_LT, R_GJ, R_FBAR, R_YBUF, R_AGR, R_FADJ, R_CADJ, R_DGW, R_DWDEN, R_JACC, R_JACF, R_RED,
-    R_ADJS, R_COUNT
+    R_ADJS, R_DWR, R_COUNT
 };
 
 // Sensitivities are available for BGK without limiter in the FP64 form.
@@ -646,7 +651,8 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
         adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 2 * (size_t)nc * nvp,
         adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 6 * (size_t)nc * nvp, adj * 8 * (size_t)FA_N * nf,
         adj * 8 * (size_t)CA_N * nc, adj * 8 * 8 * (size_t)nvp, adj * 8 * 2 * (size_t)nf,
-        adj * 8 * 32 * (size_t)nc, adj * 8 * 32 * (size_t)nf, adj * 8 * (size_t)RED_N, adj * 8 * ADJS_N};
+        adj * 8 * 32 * (size_t)nc, adj * 8 * 32 * (size_t)nf, adj * 8 * (size_t)RED_N, adj * 8 * ADJS_N,
+        8 * 4 * (size_t)nc};
     for (int r = 0; r < R_COUNT; ++r) L.add(sizes[r]);
     L.bytes = (L.bytes + 255) & ~size_t(255);
     return L;
@@ -719,7 +725,8 @@ idugks_status one_step(idugks_ctx *x, int mode) {
             RUN(KID_FLUX, launch_flux(p, x->fp32, x->st));
             RUN(KID_MACRO_PREP, launch_macro_prep(p, x->st));
         }
-        RUN(KID_MACRO, launch_macro(p, x->st));
+        if (p.predictor == 1) RUN(KID_MACRO_RELAX, launch_macro_relax(p, x->st));
+        else RUN(KID_MACRO, launch_macro(p, x->st));
         RUN(KID_RECORDS_PRED, launch_records(p, x->fp32, 1, x->st));
         RUN(KID_LOWER, launch_sweep(p, x->fp32, false, x->sweep, x->st));
         RUN(KID_WALL_GHOST, launch_wall_ghost(p, x->fp32, x->st));
@@ -842,6 +849,8 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     p.rec = (Rec *)R(R_REC); p.recs = (Rec *)R(R_RECS); p.recf = (Rec *)R(R_RECF);
     p.fields = (double *)R(R_FIELDS); p.raw = (double *)R(R_RAW); p.Wc = (double *)R(R_WC);
     p.MW = (double *)R(R_MW); p.dW = (double *)R(R_DW); p.DWd = (double *)R(R_DWD);
+    p.dWr = (double *)R(R_DWR);
+    p.predictor = cfg->predictor; p.relax_sweeps = cfg->relax_sweeps;
     p.dtimp = (double *)R(R_DTIMP); p.rho_old = (double *)R(R_RHOOLD); p.drho = (double *)R(R_DRHO);
     p.scal = (double *)R(R_SCAL);
     p.hp_off = (const int *)R(R_HPOFF); p.hp_pos = (const int *)R(R_HPPOS);
@@ -1021,7 +1030,8 @@ idugks_status idugks_predict(idugks_ctx *x, double *Wstar, double *dt_imp, int32
     idugks_status s = flux_pipeline(x);
     if (s != IDUGKS_OK) return s;
     RUN(KID_MACRO_PREP, launch_macro_prep(x->p, x->st));
-    RUN(KID_MACRO, launch_macro(x->p, x->st));
+    if (x->p.predictor == 1) RUN(KID_MACRO_RELAX, launch_macro_relax(x->p, x->st));
+    else RUN(KID_MACRO, launch_macro(x->p, x->st));
     const int nc = x->p.nc;
     std::vector<double> W(4 * nc), dW(4 * nc);
     HIPCHK(hipMemcpyAsync(W.data(), x->p.Wc, sizeof(double) * 4 * nc, hipMemcpyDeviceToHost, x->st));

@@ -98,6 +98,7 @@ struct Params {
     int vch, nch;            // velocities per chunk of the flux kernel, chunks
     int prep_in_flux;        // the flux kernel (one chunk) also writes the macro rows
     int per_i, per_j;        // the mesh is periodic in i / in j
+    int predictor, relax_sweeps; // macro prediction: 0 LU-SGS, 1 point relaxation (sweeps)
     double dt, h, Pr, mu_ref, omega, cfl_imp, M0, gam;
     // velocity set
     const double *xi, *eta, *w;
@@ -124,6 +125,7 @@ struct Params {
     double *fields;          // [nc][8] cell fields returned by idugks_moments
     double *raw, *Wc, *MW, *dW, *DWd, *dtimp, *rho_old, *drho, *scal;
     double *MWc;             // [nc][nch][4] per-chunk sums of MW (nch > 1)
+    double *dWr;             // [nc][4] second increment buffer of the point relaxation
     // per-cell data of the sweeps stored in i+j hyperplane order (position hp_pos[c]), so
     // that the cells of one hyperplane are contiguous and can be staged into LDS at once
     const int *hp_off;       // [nh+1] first position of each hyperplane

@@ -1098,6 +1098,48 @@ __global__ __launch_bounds__(1024) void k_macro_sweep(Params p, int nct) {
 }
 
 // ---------------------------------------------------------------------------------------
+// point relaxation of the macroscopic system (L + D + U) dW = M_W (the paper's second
+// prediction scheme, named in its conclusions without a formula): sweep 0 is the
+// point-implicit step dW = D^-1 M_W, every later sweep a Jacobi sweep
+//   dW_i <- D_i^-1 (M_W,i - sum_j 1/2 S (F_n(W_j + dW_j) - F_n(W_j) - lambda_j dW_j))
+// over all neighbours j with the previous sweep's dW.  One thread per cell; the cell's
+// M_W, 1/D and side geometry and the neighbours' W and sound speed come from the macro
+// rows (hyperplane order), the increments in and out in cell order.
+// ---------------------------------------------------------------------------------------
+template <bool FIRST>
+__global__ __launch_bounds__(256) void k_macro_relax(Params p, const double *dWin, double *dWout) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= p.nc) return;
+    const double *m = p.mh + (size_t)p.hp_pos[c] * MH_N;
+    double r[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) r[a] = m[a];
+    if (!FIRST) {
+        const CellSide *cs = p.cs + 4 * c;
+        const double ik2 = 1.0 / (p.K + 2);
+        for (int sd = 0; sd < 4; ++sd) {
+            const int j = cs[sd].nb;
+            if (cs[sd].type == FT_SELF || j < 0) continue;
+            const double *mj = p.mh + (size_t)p.hp_pos[j] * MH_N, *dWj = dWin + (size_t)j * 4;
+            const double nx = m[MH_SIDE + MH_SN * sd], ny = m[MH_SIDE + MH_SN * sd + 1];
+            const double hS = 0.5 * m[MH_SIDE + MH_SN * sd + 2];
+            double Wj[4], Wn[4], F0[4], F1[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                Wj[a] = mj[6 + a];
+                Wn[a] = Wj[a] + dWj[a];
+            }
+            const double lam = fabs(euler_flux_n(Wj, nx, ny, ik2, F0)) + mj[10];
+            euler_flux_n(Wn, nx, ny, ik2, F1);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) r[a] -= hS * (F1[a] - F0[a] - lam * dWj[a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) dWout[(size_t)c * 4 + a] = r[a] * m[4];
+}
+
+// ---------------------------------------------------------------------------------------
 // micro LU-SGS sweeps (Eq. 24-26) over i+j hyperplanes.  One block per slice of vb
 // velocities (slices of one XCD are contiguous, so neighbouring slices share cache lines
 // in its L2); compute lane = (cell of the hyperplane, velocity of the slice), handling
@@ -2174,6 +2216,19 @@ static hipError_t launch_macro_l(const Params &p, const MacroShape &m, hipStream
 
 hipError_t launch_macro_prep(const Params &p, hipStream_t st) {
     hipLaunchKernelGGL(k_macro_prep, dim3((p.nc + 255) / 256), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+// sweeps 0 .. relax_sweeps alternate between dWr and dW so that the last one writes dW
+hipError_t launch_macro_relax(const Params &p, hipStream_t st) {
+    const dim3 g((p.nc + 255) / 256);
+    double *buf[2] = {p.dW, p.dWr};
+    int o = p.relax_sweeps % 2 == 0 ? 0 : 1;
+    hipLaunchKernelGGL(k_macro_relax<true>, g, dim3(256), 0, st, p, (const double *)nullptr, buf[o]);
+    for (int k = 1; k <= p.relax_sweeps; ++k) {
+        hipLaunchKernelGGL(k_macro_relax<false>, g, dim3(256), 0, st, p, (const double *)buf[o], buf[1 - o]);
+        o = 1 - o;
+    }
     return hipGetLastError();
 }
 

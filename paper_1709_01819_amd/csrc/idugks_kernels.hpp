@@ -25,6 +25,7 @@ struct SweepShape {
     size_t lds;                 // vb = 0: no shape fits
 };
 MacroShape macro_shape(int ni, int nj, bool per_i, bool per_j);
+hipError_t launch_macro_relax(const Params &p, hipStream_t st);
 SweepShape sweep_shape(int ni, int nj, int nv, size_t s_bytes);
 hipError_t launch_macro_prep(const Params &p, hipStream_t st);  // k_macro_prep
 hipError_t launch_macro(const Params &p, hipStream_t st);       // k_macro_sweep (after the prep)

@@ -65,7 +65,8 @@ def test_workspace_size_scales_with_precision():
 @pytest.mark.parametrize("field,value,msg", [
     ("Kn", 0.0, "Kn"), ("Kn", -1.0, "Kn"), ("Pr", 0.0, "Pr"), ("K", -1, "K must"),
     ("nvx", 1, "nv >= 2"), ("model", 7, "model"), ("precision", 3, "precision"),
-    ("cfl_imp", 0.0, "CFL"), ("limiter", 5, "limiter"),
+    ("cfl_imp", 0.0, "CFL"), ("limiter", 5, "limiter"), ("predictor", 2, "predictor"),
+    ("relax_sweeps", -1, "relax_sweeps"), ("relax_sweeps", 65, "relax_sweeps"),
 ])
 def test_invalid_configs_rejected(field, value, msg):
     cfg = wl.case("couette")

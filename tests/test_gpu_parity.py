@@ -88,10 +88,19 @@ def test_flux_parity(name):
 # the j sides and two of the four components) instead of four
 PRED_CASES = dict(CASES, cavity_80=lambda: wl.cavity(n=80, stretch=1.5, nv=4, Kn=0.075),
                   cavity_120=lambda: wl.cavity(n=120, stretch=1.5, nv=4, Kn=0.075))
+# the point-relaxation predictor (Jacobi sweeps of the macroscopic system)
+RELAX_CASES = {
+    "cavity_tanh_relax0": lambda: dict(CASES["cavity_tanh"](), predictor=1, relax_sweeps=0),
+    "cavity_tanh_relax3": lambda: dict(CASES["cavity_tanh"](), predictor=1, relax_sweeps=3),
+    "couette_relax2": lambda: dict(CASES["couette"](), predictor=1, relax_sweeps=2),
+    "cylinder_limiter_relax1": lambda: dict(CASES["cylinder_limiter"](), predictor=1, relax_sweeps=1),
+    "periodic_box_relax4": lambda: dict(CASES["periodic_box"](), predictor=1, relax_sweeps=4),
+}
+PRED_CASES.update(RELAX_CASES)
 
 
 @pytest.mark.parametrize("name", ["couette", "cavity_tanh", "cavity_shakhov_nc", "cylinder_limiter",
-                                  "cavity_80", "cavity_120"])
+                                  "cavity_80", "cavity_120"] + list(RELAX_CASES))
 def test_predictor_parity(name):
     o, g = _pair(PRED_CASES[name](), seed=3)
     Wg, dg = g.predict()
@@ -101,9 +110,9 @@ def test_predictor_parity(name):
         assert _rel(Wg[:, a], Wo[:, a]) <= 1e-12
 
 
-@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("name", list(CASES) + ["cavity_tanh_relax3", "cylinder_limiter_relax1"])
 def test_implicit_step_parity(name):
-    o, g = _pair(CASES[name](), seed=4)
+    o, g = _pair(PRED_CASES[name](), seed=4)
     for n in (1, 4):
         ro = o.implicit_step(n)
         rg = g.step(wl.IMPLICIT, n)
