@@ -62,6 +62,12 @@ def parse():
     ap.add_argument("--no-ttr", action="store_true", help="skip the time-to-residual runs")
     ap.add_argument("--cpu-sample-iters", type=int, default=0,
                     help="oracle iterations of the CPU baseline (0 = sized to ~15 s)")
+    ap.add_argument("--ttr-suite", default="", metavar="NAMES",
+                    help="also time the solve to residual 1e-8 of these comma-separated "
+                         "workloads in FP64 and FP32-mixed (e.g. couette,cavity_kn10,cylinder_ma5; "
+                         "name@CFL sets the implicit CFL)")
+    ap.add_argument("--ttr-budget", type=float, default=45.0,
+                    help="wall-clock seconds per solve of --ttr-suite")
     ap.add_argument("--no-explicit", action="store_true",
                     help="skip the explicit-vs-implicit wall-clock comparison")
     ap.add_argument("--explicit-cap", type=int, default=200000,
@@ -157,6 +163,45 @@ def explicit_vs_implicit(workload, cfg, cap):
     out["equal_steady_residual"] = {"target": target, "explicit_steps": n2,
                                     "explicit_seconds": t2, "reached": steady <= target,
                                     "speedup": t2 / t_imp}
+    return out
+
+
+def ttr_suite(names, budget_s):
+    """Time to residual 1e-8 of each named workload in FP64 and FP32-mixed, from its
+    initial state, in chunks of 50 iterations until converged or out of budget (then
+    reported unconverged with the iterations done)."""
+    import torch
+    import workloads as wl
+    from paper_1709_01819_amd import Solver
+    out = {}
+    for spec in [n for n in names.split(",") if n]:
+        name, _, cfl = spec.partition("@")  # name@CFL overrides the workload's implicit CFL
+        for pname, prec in (("fp64", wl.FP64), ("fp32_mixed", wl.FP32_MIXED)):
+            cfg = dict(wl.case(name), precision=prec)
+            if cfl:
+                cfg["cfl_imp"] = float(cfl)
+            s = Solver(cfg)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            it, res, ok, err = 0, float("inf"), False, None
+            try:
+                while not ok and time.perf_counter() - t0 < budget_s:
+                    n, res, ok = s.solve(1e-8, 50)
+                    it += n
+            except RuntimeError as e:  # a diverged solve is reported, not raised
+                err = str(e)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            it = int(s.info().iterations)  # includes a diverged one
+            out[f"{spec}:{pname}"] = {"seconds": sec, "iterations": it, "res": res, "converged": ok,
+                                      "ms_per_iteration": 1e3 * sec / max(it, 1),
+                                      "cells": s.nc, "velocities": s.nv, "cfl_imp": cfg["cfl_imp"]}
+            if err:
+                out[f"{spec}:{pname}"]["error"] = err
+            print(f"ttr {spec} {pname}: {it} iterations, {sec:.2f} s, res {res:.3e}, converged {ok}",
+                  file=sys.stderr, flush=True)
+            del s
+            torch.cuda.empty_cache()
     return out
 
 
@@ -280,6 +325,8 @@ def main():
                                  "res": res, "converged": ok}
             del gk
         out["time_to_residual_1e-8_point_relaxation"] = pr
+    if args.ttr_suite:
+        out["time_to_residual_1e-8_suite"] = ttr_suite(args.ttr_suite, args.ttr_budget)
     if not args.no_explicit and nc * nv <= 2e7:
         out["explicit_vs_implicit"] = explicit_vs_implicit(args.workload, cfg, args.explicit_cap)
     if not args.no_cpu_baseline:
