@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--ttr-suite", default="", metavar="NAMES",
                     help="also time the solve to residual 1e-8 of these comma-separated "
                          "workloads in FP64 and FP32-mixed (e.g. couette,cavity_kn10,cylinder_ma5; "
-                         "name@CFL sets the implicit CFL)")
+                         "name@CFL sets the implicit CFL, name@CFL@START@GROWTH its start-up ramp)")
     ap.add_argument("--ttr-budget", type=float, default=45.0,
                     help="wall-clock seconds per solve of --ttr-suite")
     ap.add_argument("--no-explicit", action="store_true",
@@ -175,11 +175,15 @@ def ttr_suite(names, budget_s):
     from paper_1709_01819_amd import Solver
     out = {}
     for spec in [n for n in names.split(",") if n]:
-        name, _, cfl = spec.partition("@")  # name@CFL overrides the workload's implicit CFL
+        # name@CFL overrides the workload's implicit CFL, name@CFL@START@GROWTH also sets the
+        # start-up ramp of the CFL
+        name, *ov = spec.split("@")
         for pname, prec in (("fp64", wl.FP64), ("fp32_mixed", wl.FP32_MIXED)):
             cfg = dict(wl.case(name), precision=prec)
-            if cfl:
-                cfg["cfl_imp"] = float(cfl)
+            if ov:
+                cfg["cfl_imp"] = float(ov[0])
+            if len(ov) == 3:
+                cfg["cfl_start"], cfg["cfl_growth"] = float(ov[1]), float(ov[2])
             s = Solver(cfg)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -195,7 +199,9 @@ def ttr_suite(names, budget_s):
             it = int(s.info().iterations)  # includes a diverged one
             out[f"{spec}:{pname}"] = {"seconds": sec, "iterations": it, "res": res, "converged": ok,
                                       "ms_per_iteration": 1e3 * sec / max(it, 1),
-                                      "cells": s.nc, "velocities": s.nv, "cfl_imp": cfg["cfl_imp"]}
+                                      "cells": s.nc, "velocities": s.nv, "cfl_imp": cfg["cfl_imp"],
+                                      "cfl_start": cfg.get("cfl_start", 0.0),
+                                      "cfl_growth": cfg.get("cfl_growth", 1.0)}
             if err:
                 out[f"{spec}:{pname}"]["error"] = err
             print(f"ttr {spec} {pname}: {it} iterations, {sec:.2f} s, res {res:.3e}, converged {ok}",

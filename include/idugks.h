@@ -85,6 +85,11 @@ typedef struct {
                                     relaxation of the same system (Jacobi) */
     int32_t relax_sweeps;        /* point relaxation: Jacobi sweeps after the point-implicit
                                     step dW = D^-1 M_W, 0..64 */
+    double cfl_start;            /* start-up ramp of the implicit CFL (an addition; the paper
+                                    starts at its final CFL): with cfl_start > 0, implicit
+                                    iteration n, counted from init or the last set_state, uses
+                                    min(cfl_imp, cfl_start * cfl_growth^n); 0 = no ramp */
+    double cfl_growth;           /* ramp factor per implicit iteration, 1 <= g < 1000 */
 } idugks_config;
 
 typedef struct {

@@ -31,7 +31,9 @@
  *     density increment of Eq. 35 is then formed from the forward-sweep increments of
  *     the wall cell and enters the backward sweep;
  *   - closed domains are rescaled to their initial mass after each implicit step;
- *   - Res = ||rho^{n+1} - rho^n||_2 / ||rho^{n+1}||_2 over cells.
+ *   - Res = ||rho^{n+1} - rho^n||_2 / ||rho^{n+1}||_2 over cells;
+ *   - an optional start-up ramp of the implicit CFL, min(cfl_imp, cfl_start g^n) at
+ *     implicit iteration n (the paper starts at its final CFL and gives no ramp).
  */
 #include "idugks_oracle.h"
 
@@ -87,7 +89,8 @@ struct orc_problem {
     double *fshx, *fshy;         /* periodic shift: R's frame = L's frame - shift */
     /* gas */
     int model, K, limiter, closed, predictor, relax_sweeps;
-    double Kn, Pr, omega, mu_ref, dt, h, cfl_imp;
+    double Kn, Pr, omega, mu_ref, dt, h, cfl_imp, cfl_start, cfl_growth;
+    long imp_iters;              /* implicit iterations done (the CFL ramp's n) */
     double wall_u[4], wall_v[4], wall_RT[4];
     double *gw;                  /* [4][nv] G of the wall Maxwellian at unit density */
     double *ginf, *hinf;         /* [nv] free-stream equilibrium */
@@ -586,6 +589,8 @@ static int validate(const orc_config *c)
     if (c->quad != 0 && c->quad != 1) return fail(ORC_INVALID, "unknown quadrature");
     if (c->quad == 1 && !(c->vmax > 0)) return fail(ORC_INVALID, "Newton-Cotes needs vmax > 0");
     if (!(c->cfl_phys > 0) || !(c->cfl_imp > 0)) return fail(ORC_INVALID, "CFL must be positive");
+    if (!(c->cfl_start >= 0) || (c->cfl_start > 0 && !(c->cfl_growth >= 1 && c->cfl_growth < 1e3)))
+        return fail(ORC_INVALID, "CFL ramp needs cfl_start >= 0 and 1 <= cfl_growth < 1000");
     for (int s = 0; s < 4; ++s)
         if (c->bc[s] < 0 || c->bc[s] > 2) return fail(ORC_INVALID, "unknown boundary type");
     if ((c->bc[0] == BC_PERIODIC) != (c->bc[1] == BC_PERIODIC) ||
@@ -654,6 +659,9 @@ int orc_create(const orc_config *cfg, orc_problem **out)
     p->Pr = cfg->Pr;
     p->omega = cfg->omega;
     p->cfl_imp = cfg->cfl_imp;
+    p->cfl_start = cfg->cfl_start;
+    p->cfl_growth = cfg->cfl_growth;
+    p->imp_iters = 0;
     p->mu_ref = cfg->Kn / sqrt(M_PI); /* Eq. 37 with rho = L = 2RT = 1 */
     if ((rc = build_mesh(p, cfg))) {
         free_problem(p);
@@ -832,6 +840,7 @@ void orc_set_state(orc_problem *p, const double *f)
     memcpy(p->f, f, (size_t)2 * p->nc * p->nv * sizeof(double));
     p->M0 = total_mass(p, p->f);
     p->predicted = 0;
+    p->imp_iters = 0;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -1219,10 +1228,20 @@ static void macro_point_relax(orc_problem *p, const double *C)
 
 /* Predicted macroscopic step (Eq. 27-31): LU-SGS on (L + D + U) dW = M_W, or point
    relaxation of the same system. */
+/* The implicit CFL of the current iteration: cfl_imp, or the start-up ramp
+   min(cfl_imp, cfl_start cfl_growth^n) after n implicit iterations. */
+static double implicit_cfl(const orc_problem *p)
+{
+    if (!(p->cfl_start > 0)) return p->cfl_imp;
+    const double c = p->cfl_start * pow(p->cfl_growth, (double)p->imp_iters);
+    return c < p->cfl_imp ? c : p->cfl_imp;
+}
+
 static void macro_lusgs(orc_problem *p)
 {
     const int nc = p->nc, K = p->K;
     const double gam = (K + 4.0) / (K + 2.0);
+    const double cfl = implicit_cfl(p);
     double *C = malloc(nc * sizeof(double));
     for (int c = 0; c < nc; ++c) C[c] = sqrt(gam * p->RT[c]);
     for (int c = 0; c < nc; ++c) {
@@ -1238,7 +1257,7 @@ static void macro_lusgs(orc_problem *p)
             int m = 4 * c + side, k = p->cf[m];
             if (p->ftype[k] == F_WALL) lw += (fabs(U * p->onx[m] + V * p->ony[m]) + C[c]) * p->sS[m];
         }
-        p->dtimp[c] = p->cfl_imp * p->area[c] / ls;
+        p->dtimp[c] = cfl * p->area[c] / ls;
         p->DW[c] = p->area[c] / p->dtimp[c] + 0.5 * ls + 0.5 * lw;
     }
     if (p->predictor == 1) {
@@ -1451,6 +1470,7 @@ int orc_implicit_step(orc_problem *p, int32_t nsteps, double *res)
             for (size_t i = 0; i < (size_t)2 * nc * nv; ++i) p->f[i] *= s;
         }
         r = density_change(p, rho0);
+        ++p->imp_iters;
         if (!isfinite(r)) {
             free(rho0);
             return fail(ORC_DIVERGED, "non-finite residual");

@@ -40,6 +40,10 @@ typedef struct {
     double init_rho, init_u, init_v, init_T;
     int32_t predictor;              /* 0 LU-SGS, 1 point relaxation (both named in Section 4) */
     int32_t relax_sweeps;           /* point relaxation: Jacobi sweeps after the diagonal step */
+    /* start-up ramp of the implicit CFL (not in the paper): with cfl_start > 0, implicit
+       iteration n (counted from creation) uses min(cfl_imp, cfl_start cfl_growth^n);
+       cfl_start = 0 keeps cfl_imp throughout */
+    double cfl_start, cfl_growth;
 } orc_config;
 
 typedef struct orc_problem orc_problem;

@@ -37,6 +37,7 @@ class OrcConfig(C.Structure):
         ("cfl_phys", C.c_double), ("cfl_imp", C.c_double), ("limiter", C.c_int32),
         ("init_rho", C.c_double), ("init_u", C.c_double), ("init_v", C.c_double),
         ("init_T", C.c_double), ("predictor", C.c_int32), ("relax_sweeps", C.c_int32),
+        ("cfl_start", C.c_double), ("cfl_growth", C.c_double),
     ]
 
 
@@ -130,6 +131,8 @@ class Oracle:
             setattr(c, k, cfg[k])
         c.predictor = cfg.get("predictor", 0)
         c.relax_sweeps = cfg.get("relax_sweeps", 0)
+        c.cfl_start = cfg.get("cfl_start", 0.0)
+        c.cfl_growth = cfg.get("cfl_growth", 1.0)
         h = _P()
         rc = lib.orc_create(C.byref(c), C.byref(h))
         if rc:

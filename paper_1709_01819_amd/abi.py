@@ -36,6 +36,7 @@ class Config(C.Structure):
         ("precision", C.c_int32),
         ("init_rho", C.c_double), ("init_u", C.c_double), ("init_v", C.c_double),
         ("init_T", C.c_double), ("predictor", C.c_int32), ("relax_sweeps", C.c_int32),
+        ("cfl_start", C.c_double), ("cfl_growth", C.c_double),
     ]
 
 
@@ -126,6 +127,8 @@ def make_config(cfg):
         setattr(c, k, cfg[k])
     c.predictor = cfg.get("predictor", 0)
     c.relax_sweeps = cfg.get("relax_sweeps", 0)
+    c.cfl_start = cfg.get("cfl_start", 0.0)
+    c.cfl_growth = cfg.get("cfl_growth", 1.0)
     return c, (xn, yn)
 
 

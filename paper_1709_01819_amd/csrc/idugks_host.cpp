@@ -160,6 +160,8 @@ struct idugks_ctx {
     std::vector<double> area_h, xi_h, eta_h, w_h;
     double *stage;  // [nc][nvp] FP64 staging of one canonical species
     int64_t iters;
+    double cfl_start, cfl_growth;  // start-up ramp of the implicit CFL (0: none)
+    int64_t imp_iters;             // implicit iterations since init or set_state (its n)
     // profiling: one event pair per launch, read after the stream drains
     bool prof;
     hipEvent_t ev0, ev1;
@@ -185,6 +187,8 @@ idugks_status validate(const idugks_config *c) {
     if (c->predictor != 0 && c->predictor != 1) return fail(IDUGKS_E_INVALID, "unknown predictor");
     if (c->relax_sweeps < 0 || c->relax_sweeps > 64)
         return fail(IDUGKS_E_INVALID, "relax_sweeps must be 0..64");
+    if (!(c->cfl_start >= 0) || (c->cfl_start > 0 && !(c->cfl_growth >= 1 && c->cfl_growth < 1e3)))
+        return fail(IDUGKS_E_INVALID, "CFL ramp needs cfl_start >= 0 and 1 <= cfl_growth < 1000");
     if (c->nvx < 2 || c->nvy < 2) return fail(IDUGKS_E_INVALID, "need nv >= 2 per direction");
     if (c->nvx > 4096 || c->nvy > 4096) return fail(IDUGKS_E_INVALID, "velocity grid too large");
     {
@@ -712,18 +716,27 @@ idugks_status finalize_state(idugks_ctx *x, int mode) {
     return IDUGKS_OK;
 }
 
+// The implicit CFL of the next implicit iteration: cfl_imp, or the start-up ramp
+// min(cfl_imp, cfl_start cfl_growth^n) after n implicit iterations.
+double implicit_cfl(const idugks_ctx *x) {
+    if (!(x->cfl_start > 0)) return x->p.cfl_imp;
+    const double c = x->cfl_start * pow(x->cfl_growth, (double)x->imp_iters);
+    return c < x->p.cfl_imp ? c : x->p.cfl_imp;
+}
+
 idugks_status one_step(idugks_ctx *x, int mode) {
     const Params &p = x->p;
     idugks_status s = face_pipeline(x);
     if (s != IDUGKS_OK) return s;
     if (mode == IDUGKS_IMPLICIT) {
+        Params q = p;  // the macro rows (implicit time step) take this iteration's CFL
+        q.cfl_imp = implicit_cfl(x);
         if (p.nch == 1) {  // the flux blocks write the macro rows
-            Params q = p;
             q.prep_in_flux = 1;
             RUN(KID_FLUX, launch_flux(q, x->fp32, x->st));
         } else {
             RUN(KID_FLUX, launch_flux(p, x->fp32, x->st));
-            RUN(KID_MACRO_PREP, launch_macro_prep(p, x->st));
+            RUN(KID_MACRO_PREP, launch_macro_prep(q, x->st));
         }
         if (p.predictor == 1) RUN(KID_MACRO_RELAX, launch_macro_relax(p, x->st));
         else RUN(KID_MACRO, launch_macro(p, x->st));
@@ -814,6 +827,9 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     x->cfg = *cfg;
     x->cfg.xn = x->cfg.yn = nullptr;
     x->fp32 = cfg->precision == IDUGKS_FP32_MIXED;
+    x->cfl_start = cfg->cfl_start;
+    x->cfl_growth = cfg->cfl_growth;
+    x->imp_iters = 0;
     x->st = (hipStream_t)hip_stream;
     x->sweep = sweep_shape(b.ni, b.nj, b.nv, x->fp32 ? 4 : 8);
     if (x->sweep.vb == 0) {
@@ -941,6 +957,7 @@ idugks_status idugks_step(idugks_ctx *x, int32_t mode, int32_t nsteps, double *r
         idugks_status s = one_step(x, mode);
         if (s != IDUGKS_OK) return s;
         ++x->iters;
+        if (mode == IDUGKS_IMPLICIT) ++x->imp_iters;
     }
     double sc[SC_NUM];
     idugks_status s = read_scalars(x, sc);
@@ -1029,7 +1046,9 @@ idugks_status idugks_predict(idugks_ctx *x, double *Wstar, double *dt_imp, int32
     if (!x) return fail(IDUGKS_E_INVALID, "null context");
     idugks_status s = flux_pipeline(x);
     if (s != IDUGKS_OK) return s;
-    RUN(KID_MACRO_PREP, launch_macro_prep(x->p, x->st));
+    Params q = x->p;
+    q.cfl_imp = implicit_cfl(x);
+    RUN(KID_MACRO_PREP, launch_macro_prep(q, x->st));
     if (x->p.predictor == 1) RUN(KID_MACRO_RELAX, launch_macro_relax(x->p, x->st));
     else RUN(KID_MACRO, launch_macro(x->p, x->st));
     const int nc = x->p.nc;
@@ -1243,6 +1262,7 @@ idugks_status idugks_set_state(idugks_ctx *x, const double *f, int32_t on_host) 
     if (s != IDUGKS_OK) return s;
     x->p.M0 = sc[SC_MASS];
     x->iters = 0;
+    x->imp_iters = 0;
     return IDUGKS_OK;
 }
 

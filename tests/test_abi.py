@@ -75,6 +75,13 @@ def test_invalid_configs_rejected(field, value, msg):
     assert rc == 1 and msg in err
 
 
+@pytest.mark.parametrize("start,growth", [(-1.0, 2.0), (1.0, 0.5), (1.0, 1e3), (1.0, float("nan"))])
+def test_invalid_cfl_ramp_rejected(start, growth):
+    cfg = dict(wl.case("couette"), cfl_start=start, cfl_growth=growth)
+    rc, _, err = _size(cfg)
+    assert rc == 1 and "CFL ramp" in err
+
+
 def test_invalid_geometry_and_boundaries_rejected():
     cfg = wl.cavity(n=4, nv=4)
     cfg["xn"] = cfg["xn"][::-1].copy()   # clockwise cells: negative area

@@ -97,6 +97,13 @@ RELAX_CASES = {
     "periodic_box_relax4": lambda: dict(CASES["periodic_box"](), predictor=1, relax_sweeps=4),
 }
 PRED_CASES.update(RELAX_CASES)
+# the start-up ramp of the implicit CFL (3, 15, 75, 375, then 1000; on the chunked cylinder
+# the macro rows come from their own launch)
+RAMP_CASES = {
+    "cavity_tanh_ramp": lambda: dict(CASES["cavity_tanh"](), cfl_start=3.0, cfl_growth=5.0),
+    "cylinder_chunked_ramp": lambda: dict(CASES["cylinder_chunked"](), cfl_start=0.5, cfl_growth=3.0),
+}
+PRED_CASES.update(RAMP_CASES)
 
 
 @pytest.mark.parametrize("name", ["couette", "cavity_tanh", "cavity_shakhov_nc", "cylinder_limiter",
@@ -110,7 +117,8 @@ def test_predictor_parity(name):
         assert _rel(Wg[:, a], Wo[:, a]) <= 1e-12
 
 
-@pytest.mark.parametrize("name", list(CASES) + ["cavity_tanh_relax3", "cylinder_limiter_relax1"])
+@pytest.mark.parametrize("name", list(CASES) + ["cavity_tanh_relax3", "cylinder_limiter_relax1"]
+                         + list(RAMP_CASES))
 def test_implicit_step_parity(name):
     o, g = _pair(PRED_CASES[name](), seed=4)
     for n in (1, 4):
@@ -118,6 +126,20 @@ def test_implicit_step_parity(name):
         rg = g.step(wl.IMPLICIT, n)
         assert _rel_species(g.get_state(), o.get_state()) <= 1e-12
         assert abs(rg - ro) <= 1e-9 * ro + 1e-15
+
+
+@pytest.mark.parametrize("name", list(RAMP_CASES))
+def test_cfl_ramp_predictor_after_steps(name):
+    """The implicit time steps of the prediction follow the ramp's iteration count on both
+    sides, and set_state restarts the ramp."""
+    o, g = _pair(PRED_CASES[name](), seed=9)
+    o.implicit_step(2)
+    g.step(wl.IMPLICIT, 2)
+    assert _rel(g.predict()[1], o.predict()[1]) <= 1e-12
+    f = o.get_state()
+    o.set_state(f)
+    g.set_state(f)
+    assert _rel(g.predict()[1], o.predict()[1]) <= 1e-13
 
 
 @pytest.mark.parametrize("name", ["couette", "cavity_tanh", "cylinder_limiter"])

@@ -294,3 +294,32 @@ def test_couette_near_continuum_linear_profile_second_order():
     s = np.array(slopes)
     order = np.log2((s[:-2] - s[1:-1]) / (s[1:-1] - s[2:]))
     assert np.all(order > 1.7) and np.all(order < 2.3)
+
+
+def test_cfl_ramp_scales_the_implicit_time_step():
+    """Start-up ramp of the implicit CFL: implicit iteration n takes min(cfl_imp,
+    cfl_start g^n).  The implicit time step (Eq. 30) is proportional to the CFL, so on one
+    state the ramped and the plain problem's dt_imp differ by exactly that ratio; the ramp
+    saturates at cfl_imp, and set_state restarts it.  A ramp that is off, or that starts at
+    cfl_imp, leaves the iteration unchanged."""
+    base = wl.cavity(n=6, stretch=1.5, nv=6, Kn=0.075)
+    cfl = base["cfl_imp"]
+    a, b = Oracle(dict(base, cfl_start=2.0, cfl_growth=3.0)), Oracle(base)
+    f = a.get_state()
+    f = f * wl.perturbation(f.shape, 21, 0.05)
+    a.set_state(f)
+    done = 0
+    for n, expect in ((0, 2.0), (2, 18.0), (5, 486.0), (7, cfl)):
+        a.implicit_step(n - done) if n > done else None
+        done = n
+        b.set_state(a.get_state())
+        ratio = a.predict()[1] / b.predict()[1]
+        np.testing.assert_allclose(ratio, expect / cfl, rtol=1e-14)
+    a.set_state(a.get_state())
+    np.testing.assert_allclose(a.predict()[1] / b.predict()[1], 2.0 / cfl, rtol=1e-14)
+    # saturated from the start: the same iterates as no ramp
+    c = Oracle(dict(base, cfl_start=cfl, cfl_growth=1.0))
+    c.set_state(f)
+    b.set_state(f)
+    assert c.implicit_step(3) == b.implicit_step(3)
+    assert np.array_equal(c.get_state(), b.get_state())
