@@ -62,11 +62,11 @@ def parse():
     ap.add_argument("--no-ttr", action="store_true", help="skip the time-to-residual runs")
     ap.add_argument("--cpu-sample-iters", type=int, default=0,
                     help="oracle iterations of the CPU baseline (0 = sized to ~15 s)")
-    ap.add_argument("--ttr-suite", default="", metavar="NAMES",
-                    help="also time the solve to residual 1e-8 of these comma-separated "
-                         "workloads in FP64 and FP32-mixed (e.g. couette,cavity_kn10,cylinder_ma5; "
-                         "name@CFL sets the implicit CFL, name@CFL@START@GROWTH its start-up ramp)")
-    ap.add_argument("--ttr-budget", type=float, default=45.0,
+    ap.add_argument("--ttr-suite", default="couette,cavity_kn10@100,cylinder_ma5", metavar="NAMES",
+                    help="time the solve to residual 1e-8 of these comma-separated workloads "
+                         "in FP64 and FP32-mixed as well (name@CFL sets the implicit CFL, "
+                         "name@CFL@START@GROWTH its start-up ramp; an empty string skips them)")
+    ap.add_argument("--ttr-budget", type=float, default=20.0,
                     help="wall-clock seconds per solve of --ttr-suite")
     ap.add_argument("--no-explicit", action="store_true",
                     help="skip the explicit-vs-implicit wall-clock comparison")
@@ -331,7 +331,7 @@ def main():
                                  "res": res, "converged": ok}
             del gk
         out["time_to_residual_1e-8_point_relaxation"] = pr
-    if args.ttr_suite:
+    if args.ttr_suite and not args.no_ttr:
         out["time_to_residual_1e-8_suite"] = ttr_suite(args.ttr_suite, args.ttr_budget)
     if not args.no_explicit and nc * nv <= 2e7:
         out["explicit_vs_implicit"] = explicit_vs_implicit(args.workload, cfg, args.explicit_cap)
