@@ -88,7 +88,8 @@ typedef struct {
     double cfl_start;            /* start-up ramp of the implicit CFL (an addition; the paper
                                     starts at its final CFL): with cfl_start > 0, implicit
                                     iteration n, counted from init or the last set_state, uses
-                                    min(cfl_imp, cfl_start * cfl_growth^n); 0 = no ramp */
+                                    min(cfl_imp, cfl_start * cfl_growth^n); 0 = no ramp.
+                                    The adjoint iteration keeps cfl_imp. */
     double cfl_growth;           /* ramp factor per implicit iteration, 1 <= g < 1000 */
 } idugks_config;
 
