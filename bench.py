@@ -223,11 +223,26 @@ def cpu_baseline(cfg, nc, nv, budget_s=15.0, iters=0):
     t0 = time.perf_counter()
     o.implicit_step(n)
     dt = (time.perf_counter() - t0) / n
-    return {"value": nc * nv / dt, "unit": "cell·vel/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} implicit iterations (after 1 untimed) of the same {cfg['ni']}x{cfg['nj']} "
-                      f"x {nv}-velocity problem from its uniform initial state, FP64, "
-                      f"OpenMP over independent cells/velocities",
-            "s_per_iter": dt}
+    out = {"value": nc * nv / dt, "unit": "cell·vel/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n} implicit iterations (after 1 untimed) of the same {cfg['ni']}x{cfg['nj']} "
+                     f"x {nv}-velocity problem from its uniform initial state, FP64, "
+                     f"OpenMP over independent cells/velocities",
+           "s_per_iter": dt}
+    # the same oracle on one thread (three more iterations), through the OpenMP runtime the
+    # oracle library runs on
+    try:
+        import ctypes
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        o.implicit_step(3)
+        d1 = (time.perf_counter() - t0) / 3
+        gomp.omp_set_num_threads(threads)
+        out["value_1_thread"] = nc * nv / d1
+        out["s_per_iter_1_thread"] = d1
+    except OSError:
+        pass
+    return out
 
 
 def main():
