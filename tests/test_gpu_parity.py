@@ -198,6 +198,25 @@ def test_kn10_cavity_128_history_and_divergence():
     np.testing.assert_allclose(rg[:20], ro[:20], rtol=1e-6)
 
 
+@pytest.mark.parametrize("name", ["cavity_kn10", "cylinder_ma5"])
+def test_full_size_fp32_step(name):
+    """The two large workloads in their FP32-mixed benchmark form at full size: the 128^2
+    cavity with 101^2 Newton-Cotes velocities (Shakhov, Kn = 10) and the 96 x 160 O-grid
+    cylinder with 100^2 velocities (Shakhov, limiter, far field, Ma 5, first step of its
+    CFL ramp); about 1.6e8 cell-velocity pairs each, five velocity chunks of 2048 in the
+    flux, two velocities per sweep lane.  One implicit iteration from a seeded
+    perturbation against the FP64 oracle, to the FP32 bar of the small cases."""
+    cfg = wl.case(name)
+    assert cfg["precision"] == wl.FP32_MIXED
+    o, g = _pair(cfg, seed=12, amp=0.02)
+    o.implicit_step(1)
+    g.step(wl.IMPLICIT, 1)
+    fo = o.get_state()
+    fg = g.get_state()
+    for s in range(2):
+        assert _rel(fg[s], fo[s]) <= 2e-6
+
+
 # ------------------------------------------------------------------ full C2, converged
 @pytest.fixture(scope="module")
 def c2_oracle_converged():
