@@ -101,7 +101,7 @@ def copy_calibration(mib):
 
 
 # Table 2 of the paper: explicit steps, implicit iterations and wall-clock speedup to a
-# residual of 5e-8 for the cavity cases this build runs at the same Knudsen numbers
+# residual of 5e-8 for the cavity cases run here at the same Knudsen numbers
 TABLE2 = {"cavity_kn0.075": (11900, 230, 27.49), "cavity_kn1": (9600, 190, 26.80),
           "cavity_kn10": (34200, 640, 28.52)}
 EXPLICIT_TOL = 5e-8
@@ -250,7 +250,7 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU (--gpus 1); the "
+        print(json.dumps({"error": "this solver runs on exactly one GPU (--gpus 1); the "
                                    "velocity-sharded multi-GPU design is documented, not built"}))
         sys.exit(2)
     import torch
