@@ -109,6 +109,9 @@ struct orc_problem {
     double *feqst;               /* [2][nc][nv] */
     double *delta;               /* [2][nc][nv] */
     int predicted;
+    /* optional captures of one implicit iteration (tests): the forward-sweep increment
+       [2][nc][nv] and the wall ghost density increments [nf] */
+    double *cap_dstar, *cap_drho;
 };
 
 /* ------------------------------------------------------------------------- */
@@ -876,6 +879,40 @@ static void cell_records(orc_problem *p)
 /* Theta of the Venkatakrishnan limiter (Eq. 17) */
 static double venkat_theta(double x) { return (x * x + 2.0 * x) / (x * x + x + 2.0); }
 
+/* Least-squares gradient (Eq. 15) of a cell field val[j * stride] at cell c, optionally
+   limited by Venkatakrishnan's function (Eq. 16-17): phi = min over the cell's faces of
+   theta(r_k), r_k the room to the largest (Delta_k > 0) or smallest (Delta_k < 0) value over
+   the cell and its neighbours divided by the unlimited increment Delta_k from the centroid
+   to the face midpoint; theta = 1 where Delta_k = 0, and phi <= 1. */
+static void cell_gradient(const orc_problem *p, int c, const double *val, size_t stride, int limiter,
+                          double *gx_out, double *gy_out)
+{
+    double b0 = val[(size_t)c * stride], gx = 0.0, gy = 0.0, bmax = b0, bmin = b0;
+    for (int side = 0; side < 4; ++side) {
+        int m = 4 * c + side, j = p->nb[m];
+        if (j < 0) continue;
+        double bj = val[(size_t)j * stride];
+        gx += p->ax[m] * (bj - b0);
+        gy += p->ay[m] * (bj - b0);
+        if (bj > bmax) bmax = bj;
+        if (bj < bmin) bmin = bj;
+    }
+    if (limiter) {
+        double phi = 1.0;
+        for (int side = 0; side < 4; ++side) {
+            int m = 4 * c + side;
+            double d = gx * p->fdx[m] + gy * p->fdy[m], th = 1.0;
+            if (d > 0) th = venkat_theta((bmax - b0) / d);
+            else if (d < 0) th = venkat_theta((bmin - b0) / d);
+            if (th < phi) phi = th;
+        }
+        gx *= phi;
+        gy *= phi;
+    }
+    *gx_out = gx;
+    *gy_out = gy;
+}
+
 /* phi-bar-plus at cell centres and its least-squares gradient (Eq. 12-17). */
 static void barplus_gradients(orc_problem *p)
 {
@@ -895,30 +932,7 @@ static void barplus_gradients(orc_problem *p)
         for (int s = 0; s < 2; ++s)
             for (int v = 0; v < nv; ++v) {
                 size_t o = (size_t)(s * nc + c) * nv + v;
-                double b0 = p->bp[o], gx = 0.0, gy = 0.0, bmax = b0, bmin = b0;
-                for (int side = 0; side < 4; ++side) {
-                    int m = 4 * c + side, j = p->nb[m];
-                    if (j < 0) continue;
-                    double bj = p->bp[(size_t)(s * nc + j) * nv + v];
-                    gx += p->ax[m] * (bj - b0);
-                    gy += p->ay[m] * (bj - b0);
-                    if (bj > bmax) bmax = bj;
-                    if (bj < bmin) bmin = bj;
-                }
-                if (p->limiter) {
-                    double phi = 1.0;
-                    for (int side = 0; side < 4; ++side) {
-                        int m = 4 * c + side;
-                        double d = gx * p->fdx[m] + gy * p->fdy[m], th = 1.0;
-                        if (d > 0) th = venkat_theta((bmax - b0) / d);
-                        else if (d < 0) th = venkat_theta((bmin - b0) / d);
-                        if (th < phi) phi = th;
-                    }
-                    gx *= phi;
-                    gy *= phi;
-                }
-                p->sx[o] = gx;
-                p->sy[o] = gy;
+                cell_gradient(p, c, p->bp + (size_t)s * nc * nv + v, nv, p->limiter, p->sx + o, p->sy + o);
             }
 }
 
@@ -1457,6 +1471,8 @@ int orc_implicit_step(orc_problem *p, int32_t nsteps, double *res)
             sweep_lower(p, sv % nv, p->delta + (size_t)(sv / nv) * nc * nv + sv % nv, nv);
         /* wall ghost increments from the forward-sweep result (Eq. 34-35) */
         wall_ghost(p);
+        if (p->cap_dstar) memcpy(p->cap_dstar, p->delta, (size_t)2 * nc * nv * sizeof(double));
+        if (p->cap_drho) memcpy(p->cap_drho, p->drho_g, (size_t)p->nf * sizeof(double));
         /* backward sweeps */
 #pragma omp parallel for schedule(dynamic, 4)
         for (int sv = 0; sv < 2 * nv; ++sv)
@@ -1499,4 +1515,67 @@ int orc_solve(orc_problem *p, double tol, int32_t max_iter, int32_t *iters, doub
     if (iters) *iters = n;
     if (res) *res = r;
     return r < tol ? 0 : fail(ORC_NOT_CONVERGED, "iteration limit reached");
+}
+
+/* ------------------------------------------------------------------------- */
+/* Accessors of intermediate quantities (pins of the individual steps)        */
+/* ------------------------------------------------------------------------- */
+int orc_gradients(orc_problem *p, double *sx, double *sy)
+{
+    cell_records(p);
+    barplus_gradients(p);
+    size_t n = (size_t)2 * p->nc * p->nv;
+    if (sx) memcpy(sx, p->sx, n * sizeof(double));
+    if (sy) memcpy(sy, p->sy, n * sizeof(double));
+    return check_state(p);
+}
+
+int orc_lsq_gradient(const orc_problem *p, const double *phi, int32_t limiter, double *gx, double *gy)
+{
+    for (int c = 0; c < p->nc; ++c) cell_gradient(p, c, phi, 1, limiter, gx + c, gy + c);
+    return 0;
+}
+
+void orc_faces(const orc_problem *p, int32_t *L, int32_t *R, int32_t *type, int32_t *side,
+               double *nx, double *ny, double *S, double *mx, double *my)
+{
+    for (int k = 0; k < p->nf; ++k) {
+        L[k] = p->fL[k];
+        R[k] = p->fR[k];
+        type[k] = p->ftype[k];
+        side[k] = p->fside[k];
+        nx[k] = p->fnx[k];
+        ny[k] = p->fny[k];
+        S[k] = p->fS[k];
+        mx[k] = p->fmx[k];
+        my[k] = p->fmy[k];
+    }
+}
+
+int orc_face_flux(orc_problem *p, double *F)
+{
+    explicit_residual(p);
+    if (F) memcpy(F, p->F, (size_t)2 * p->nf * p->nv * sizeof(double));
+    return check_state(p);
+}
+
+int orc_macro_sweep_rhs(orc_problem *p, const double *rhs, double *dW)
+{
+    cell_records(p);
+    int rc = check_state(p);
+    if (rc) return rc;
+    memcpy(p->MW, rhs, 4 * (size_t)p->nc * sizeof(double));
+    macro_lusgs(p);
+    memcpy(dW, p->dW, 4 * (size_t)p->nc * sizeof(double));
+    return 0;
+}
+
+int orc_implicit_detail(orc_problem *p, double *delta_star, double *drho, double *res)
+{
+    p->cap_dstar = delta_star;
+    p->cap_drho = drho;
+    int rc = orc_implicit_step(p, 1, res);
+    p->cap_dstar = NULL;
+    p->cap_drho = NULL;
+    return rc;
 }

@@ -107,6 +107,26 @@ int orc_solve(orc_problem *p, double tol, int32_t max_iter, int32_t *iters, doub
 /* RMS over cells of M_W / area for each conserved variable */
 int orc_residual(orc_problem *p, double out[4]);
 
+/* Intermediate quantities, for the pins of individual steps: */
+/* limited least-squares gradient of phi-bar-plus of the current state, [2][nc][nv] each */
+int orc_gradients(orc_problem *p, double *sx, double *sy);
+/* least-squares gradient (Eq. 15) of an arbitrary cell field phi [nc], limited by Eq. 16-17
+   when limiter != 0 */
+int orc_lsq_gradient(const orc_problem *p, const double *phi, int32_t limiter, double *gx, double *gy);
+/* faces [nf]: cells L, R (-1 at a boundary), type (0 interior, 1 self-periodic, 2 wall,
+   3 far field), boundary side (-1 inside), unit normal from L to R (outward at a boundary),
+   length, midpoint in L's frame */
+void orc_faces(const orc_problem *p, int32_t *L, int32_t *R, int32_t *type, int32_t *side,
+               double *nx, double *ny, double *S, double *mx, double *my);
+/* face fluxes S (xi.n) phi_k [2][nf][nv] of the current state (Eq. 18-19) */
+int orc_face_flux(orc_problem *p, double *F);
+/* the macroscopic LU-SGS (Eq. 29-31) of the current state applied to the right-hand side
+   rhs [nc][4] in place of M_W; dW [nc][4] */
+int orc_macro_sweep_rhs(orc_problem *p, const double *rhs, double *dW);
+/* one implicit iteration that also returns the forward-sweep increment [2][nc][nv] and the
+   wall ghost density increments [nf] formed from it (Eq. 35) */
+int orc_implicit_detail(orc_problem *p, double *delta_star, double *drho, double *res);
+
 #ifdef __cplusplus
 }
 #endif

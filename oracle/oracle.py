@@ -80,6 +80,12 @@ def load():
         "orc_implicit_step": (C.c_int, [_P, C.c_int32, _D]),
         "orc_solve": (C.c_int, [_P, C.c_double, C.c_int32, _I, _D]),
         "orc_residual": (C.c_int, [_P, _D]),
+        "orc_gradients": (C.c_int, [_P, _D, _D]),
+        "orc_lsq_gradient": (C.c_int, [_P, _D, C.c_int32, _D, _D]),
+        "orc_faces": (None, [_P, _I, _I, _I, _I, _D, _D, _D, _D, _D]),
+        "orc_face_flux": (C.c_int, [_P, _D]),
+        "orc_macro_sweep_rhs": (C.c_int, [_P, _D, _D]),
+        "orc_implicit_detail": (C.c_int, [_P, _D, _D, _D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -278,3 +284,41 @@ class Oracle:
         out = np.zeros(4)
         self._check(self._lib.orc_residual(self._h, _dp(out)))
         return out
+
+    # intermediate quantities (pins of individual steps)
+    def gradients(self):
+        sx = np.zeros((2, self.nc, self.nv))
+        sy = np.zeros((2, self.nc, self.nv))
+        self._check(self._lib.orc_gradients(self._h, _dp(sx), _dp(sy)))
+        return sx, sy
+
+    def lsq_gradient(self, phi, limiter):
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(self.nc)
+        gx, gy = np.zeros(self.nc), np.zeros(self.nc)
+        self._check(self._lib.orc_lsq_gradient(self._h, _dp(phi), int(limiter), _dp(gx), _dp(gy)))
+        return gx, gy
+
+    def faces(self):
+        ints = [np.zeros(self.nf, np.int32) for _ in range(4)]
+        dbl = [np.zeros(self.nf) for _ in range(5)]
+        self._lib.orc_faces(self._h, *[a.ctypes.data_as(_I) for a in ints], *[_dp(a) for a in dbl])
+        keys = ("L", "R", "type", "side", "nx", "ny", "S", "mx", "my")
+        return dict(zip(keys, ints + dbl))
+
+    def face_flux(self):
+        F = np.zeros((2, self.nf, self.nv))
+        self._check(self._lib.orc_face_flux(self._h, _dp(F)))
+        return F
+
+    def macro_sweep_rhs(self, rhs):
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64).reshape(self.nc, 4)
+        dW = np.zeros((self.nc, 4))
+        self._check(self._lib.orc_macro_sweep_rhs(self._h, _dp(rhs), _dp(dW)))
+        return dW
+
+    def implicit_detail(self):
+        ds = np.zeros((2, self.nc, self.nv))
+        dr = np.zeros(self.nf)
+        r = C.c_double(0.0)
+        self._check(self._lib.orc_implicit_detail(self._h, _dp(ds), _dp(dr), C.byref(r)))
+        return ds, dr, r.value
