@@ -1,10 +1,13 @@
 #!/usr/bin/env python3
 """Benchmark of the implicit DUGKS hot path on one MI355X.
 
-One step is one implicit IDUGKS iteration (records, interface flux, predicted
-macroscopic LU-SGS, micro LU-SGS sweeps, update, residual) on the 64x64 tanh-clustered
-lid-driven cavity with 28x28 Gauss-Hermite velocities, BGK, Kn = 0.075, CFL 1000 (the
-problem is resident in HBM before timing starts).  Prints one JSON line.
+One step is one implicit IDUGKS iteration (records, interface flux, predicted macroscopic
+LU-SGS, micro LU-SGS sweeps, update, residual).  The headline workload is the largest
+single-GPU configuration: the 128x128 lid-driven cavity at Kn = 10 with 101x101
+Newton-Cotes velocities (Shakhov, 1.67e8 cell-velocity pairs) in the FP32-bulk /
+FP64-moment form, resident in HBM before timing starts.  The 64x64 tanh cavity with 28x28
+Gauss-Hermite velocities (FP64; small enough to stay in the Infinity Cache and latency
+bound) is measured beside it.  Prints one JSON line.
 """
 import argparse
 import json
@@ -54,14 +57,21 @@ def measured_traffic(tag, kernel):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--workload", default="cavity_kn0.075")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32")
+    ap.add_argument("--workload", default="cavity_kn10")
+    ap.add_argument("--secondary", default="cavity_kn0.075",
+                    help="a second, small workload measured in FP64 beside the headline one; it "
+                         "also carries the time-to-residual and explicit-vs-implicit runs "
+                         "(empty: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-one-thread", action="store_true",
+                    help="skip the single-thread oracle iteration of the CPU baseline")
     ap.add_argument("--no-ttr", action="store_true", help="skip the time-to-residual runs")
     ap.add_argument("--cpu-sample-iters", type=int, default=0,
-                    help="oracle iterations of the CPU baseline (0 = sized to ~15 s)")
+                    help="oracle iterations of the CPU baseline (0 = 3 on workloads above "
+                         "1e8 cell-velocity pairs, else sized to ~15 s)")
     ap.add_argument("--ttr-suite", default="couette,cavity_kn10@100,cylinder_ma5", metavar="NAMES",
                     help="time the solve to residual 1e-8 of these comma-separated workloads "
                          "in FP64 and FP32-mixed as well (name@CFL sets the implicit CFL, "
@@ -166,41 +176,78 @@ def explicit_vs_implicit(workload, cfg, cap):
     return out
 
 
+FLOOR32 = 5e-8   # FP32 iterations hand over to FP64 below this relative density change
+
+
 def ttr_suite(names, budget_s):
-    """Time to residual 1e-8 of each named workload in FP64 and FP32-mixed, from its
-    initial state, in chunks of 50 iterations until converged or out of budget (then
-    reported unconverged with the iterations done)."""
+    """Time to residual 1e-8 of each named workload from its initial state: FP64, FP32-mixed,
+    and FP32-mixed to its rounding floor followed by FP64 iterations from that state
+    (mixed-precision refinement; the handover copies the state through the canonical FP64
+    layout).  Each solve runs in chunks of 50 iterations until converged or out of budget
+    (then reported unconverged with the iterations done)."""
     import torch
     import workloads as wl
     from paper_1709_01819_amd import Solver
+
+    def run(s, t0, budget, handover=False):
+        """Solve to 1e-8 in chunks of 50; with handover, stop once the relative density
+        change is below FLOOR32 and no longer falls by a tenth over a chunk (the FP32
+        floor).  Returns (res, converged, error)."""
+        res, ok, err, prev = float("inf"), False, None, float("inf")
+        try:
+            while not ok and time.perf_counter() - t0 < budget:
+                _, res, ok = s.solve(1e-8, 50)
+                if handover and not ok and res < FLOOR32 and res > 0.9 * prev:
+                    break
+                prev = res
+        except RuntimeError as e:  # a diverged solve is reported, not raised
+            err = str(e)
+        return res, ok, err
+
     out = {}
     for spec in [n for n in names.split(",") if n]:
         # name@CFL overrides the workload's implicit CFL, name@CFL@START@GROWTH also sets the
         # start-up ramp of the CFL
         name, *ov = spec.split("@")
-        for pname, prec in (("fp64", wl.FP64), ("fp32_mixed", wl.FP32_MIXED)):
+
+        def cfg_of(prec):
             cfg = dict(wl.case(name), precision=prec)
             if ov:
                 cfg["cfl_imp"] = float(ov[0])
             if len(ov) == 3:
                 cfg["cfl_start"], cfg["cfl_growth"] = float(ov[1]), float(ov[2])
+            return cfg
+
+        for pname in ("fp64", "fp32_mixed", "fp32_then_fp64"):
+            cfg = cfg_of(wl.FP64 if pname == "fp64" else wl.FP32_MIXED)
             s = Solver(cfg)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            res, ok, err = float("inf"), False, None
-            try:
-                while not ok and time.perf_counter() - t0 < budget_s:
-                    _, res, ok = s.solve(1e-8, 50)
-            except RuntimeError as e:  # a diverged solve is reported, not raised
-                err = str(e)
+            entry = {}
+            if pname == "fp32_then_fp64":
+                res, ok, err = run(s, t0, budget_s, handover=True)
+                it32 = int(s.info().iterations)
+                entry["fp32_iterations"] = it32
+                entry["fp32_res"] = res
+                it = it32
+                if err is None and not ok and res < FLOOR32:
+                    f = s.get_state()
+                    del s
+                    s = Solver(cfg_of(wl.FP64))
+                    s.set_state(f)
+                    res, ok, err = run(s, t0, budget_s)
+                    entry["fp64_iterations"] = int(s.info().iterations)
+                    it = it32 + entry["fp64_iterations"]
+            else:
+                res, ok, err = run(s, t0, budget_s)
+                it = int(s.info().iterations)  # all of them, a diverged one included
             torch.cuda.synchronize()
             sec = time.perf_counter() - t0
-            it = int(s.info().iterations)  # all of them, a diverged one included
-            out[f"{spec}:{pname}"] = {"seconds": sec, "iterations": it, "res": res, "converged": ok,
-                                      "ms_per_iteration": 1e3 * sec / max(it, 1),
-                                      "cells": s.nc, "velocities": s.nv, "cfl_imp": cfg["cfl_imp"],
-                                      "cfl_start": cfg.get("cfl_start", 0.0),
-                                      "cfl_growth": cfg.get("cfl_growth", 1.0)}
+            out[f"{spec}:{pname}"] = dict(
+                {"seconds": sec, "iterations": it, "res": res, "converged": ok,
+                 "ms_per_iteration": 1e3 * sec / max(it, 1), "cells": s.nc, "velocities": s.nv,
+                 "cfl_imp": cfg["cfl_imp"], "cfl_start": cfg.get("cfl_start", 0.0),
+                 "cfl_growth": cfg.get("cfl_growth", 1.0)}, **entry)
             if err:
                 out[f"{spec}:{pname}"]["error"] = err
             print(f"ttr {spec} {pname}: {it} iterations, {sec:.2f} s, res {res:.3e}, converged {ok}",
@@ -210,38 +257,129 @@ def ttr_suite(names, budget_s):
     return out
 
 
-def cpu_baseline(cfg, nc, nv, budget_s=15.0, iters=0):
-    """The FP64 oracle on the host cores, a bounded sample of the same workload."""
+def cpu_baseline(cfg, nc, nv, budget_s=15.0, iters=0, one_thread=True):
+    """The FP64 oracle on the host cores, a bounded sample of the same workload: the median
+    of a few implicit iterations (after one untimed) from the uniform initial state, and
+    one iteration on a single thread."""
+    import statistics
     from oracle import Oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     o = Oracle(cfg)
     t0 = time.perf_counter()
     o.implicit_step(1)
     t1 = time.perf_counter() - t0
-    n = iters if iters > 0 else max(2, min(200, int(budget_s / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    o.implicit_step(n)
-    dt = (time.perf_counter() - t0) / n
-    out = {"value": nc * nv / dt, "unit": "cell·vel/s", "cores": threads, "kind": "oracle",
-           "sample": f"{n} implicit iterations (after 1 untimed) of the same {cfg['ni']}x{cfg['nj']} "
-                     f"x {nv}-velocity problem from its uniform initial state, FP64, "
-                     f"OpenMP over independent cells/velocities",
-           "s_per_iter": dt}
-    # the same oracle on one thread (three more iterations), through the OpenMP runtime the
-    # oracle library runs on
-    try:
-        import ctypes
-        gomp = ctypes.CDLL("libgomp.so.1")
-        gomp.omp_set_num_threads(1)
+    big = nc * nv > 1e8
+    n = iters if iters > 0 else (3 if big else max(3, min(200, int(budget_s / max(t1, 1e-3)))))
+    if big:  # per iteration, median
+        per = []
+        for _ in range(n):
+            t0 = time.perf_counter()
+            o.implicit_step(1)
+            per.append(time.perf_counter() - t0)
+        dt = statistics.median(per)
+        how = f"median of {n} implicit iterations"
+    else:
         t0 = time.perf_counter()
-        o.implicit_step(3)
-        d1 = (time.perf_counter() - t0) / 3
-        gomp.omp_set_num_threads(threads)
-        out["value_1_thread"] = nc * nv / d1
-        out["s_per_iter_1_thread"] = d1
-    except OSError:
+        o.implicit_step(n)
+        dt = (time.perf_counter() - t0) / n
+        how = f"mean of {n} implicit iterations"
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
         pass
+    out = {"value": nc * nv / dt, "unit": "cell·vel/s", "cores": threads, "kind": "oracle",
+           "sample": f"{how} (after 1 untimed) of the same {cfg['ni']}x{cfg['nj']} x "
+                     f"{nv}-velocity problem from its uniform initial state, FP64, OpenMP over "
+                     f"independent cells/velocities",
+           "s_per_iter": dt, "cpu_model": model}
+    # the same oracle on one thread (one more iteration), through the OpenMP runtime the
+    # oracle library runs on
+    if one_thread:
+        try:
+            import ctypes
+            gomp = ctypes.CDLL("libgomp.so.1")
+            gomp.omp_set_num_threads(1)
+            k = 1 if big else 3
+            t0 = time.perf_counter()
+            o.implicit_step(k)
+            d1 = (time.perf_counter() - t0) / k
+            gomp.omp_set_num_threads(threads)
+            out["value_1_thread"] = nc * nv / d1
+            out["s_per_iter_1_thread"] = d1
+        except OSError:
+            pass
     return out
+
+
+def measure(cfg, workload, precision, steps, warmup):
+    """Throughput of whole implicit iterations of one workload, resident in HBM.
+
+    A first pass of `steps` iterations brackets every kernel with a HIP event pair (per-kernel
+    means; each pair costs a few microseconds of launch gap, so this pass is not the timed
+    one).  The timed region is exactly `steps` iterations with one event pair around the
+    dominant kernel only, bracketed by stream synchronisations."""
+    import torch
+    import workloads as wl
+    from paper_1709_01819_amd import Solver
+
+    prec = cfg["precision"]
+    g = Solver(cfg)
+    nc, nv = g.nc, g.nv
+    torch.cuda.synchronize()
+    g.step(wl.IMPLICIT, warmup)
+    torch.cuda.synchronize()
+    prof = g.profile(wl.IMPLICIT, steps)
+    torch.cuda.synchronize()
+    kernels = {k: {"ms_avg": ms / n, "launches": n} for k, (ms, n) in prof.items() if n}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_avg"] * kernels[k]["launches"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    live = g.profile(wl.IMPLICIT, steps, kernels=[dom])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    dom_ms, dom_n = live[dom]
+    kernels[dom]["ms_avg_timed_region"] = dom_ms / dom_n
+    s_bytes = 8 if prec == wl.FP64 else 4
+    per_launch_bytes = ALGO_BYTES.get(dom, 0) * s_bytes * nc * nv
+    if dom == "macro_lusgs":
+        per_launch_bytes = nc * 8 * MACRO_DOUBLES_PER_CELL
+    achieved = per_launch_bytes / (kernels[dom]["ms_avg_timed_region"] * 1e-3) / 1e9
+    tag = f"{workload}:{precision}"
+    roofline = {"bound": "hbm", "kernel": dom, "kernel_ms": kernels[dom]["ms_avg_timed_region"],
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(tag, dom),
+                "algorithmic_bytes_per_launch": per_launch_bytes}
+    if dom == "macro_lusgs":
+        steps_dep = 2 * (cfg["ni"] + cfg["nj"] - 1)
+        roofline["note"] = ("one workgroup sweeps 2 x (ni+nj-1) dependent hyperplane steps: "
+                            "bound by the step latency, not by bandwidth")
+        roofline["dependent_steps_per_launch"] = steps_dep
+        roofline["us_per_step"] = 1e3 * roofline["kernel_ms"] / steps_dep
+    streaming = {}
+    for k, per in ALGO_BYTES.items():
+        if k in kernels:
+            b = per * s_bytes * nc * nv
+            gbs = b / (kernels[k]["ms_avg"] * 1e-3) / 1e9
+            streaming[k] = {"ms": kernels[k]["ms_avg"], "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS,
+                            "algorithmic_bytes": b, "traffic": measured_traffic(tag, k)}
+    del g
+    torch.cuda.empty_cache()
+    return {"value": nc * nv / (elapsed / steps), "ms_per_step": 1e3 * elapsed / steps,
+            "cells": nc, "velocities": nv, "roofline": roofline, "streaming_kernels": streaming,
+            "kernels_ms": {k: round(v["ms_avg"], 5) for k, v in kernels.items()}}
+
+
+def describe(workload, cfg, precision):
+    return (f"{workload}: {cfg['ni']}x{cfg['nj']} cells, {cfg['nvx']}x{cfg['nvy']} velocities, "
+            f"{'Shakhov' if cfg['model'] == 1 else 'BGK'}, Kn={cfg['Kn']}, CFL={cfg['cfl_imp']}, "
+            f"{'FP64' if precision == 'fp64' else 'FP32-mixed'}")
+
+
+def case_cfg(name, prec):
+    import workloads as wl
+    return wl.case(name, precision=prec) if name != "couette" else dict(wl.case("couette"), precision=prec)
 
 
 def main():
@@ -258,70 +396,34 @@ def main():
     from paper_1709_01819_amd import Solver
 
     prec = wl.FP64 if args.precision == "fp64" else wl.FP32_MIXED
-    cfg = wl.case(args.workload, precision=prec) if args.workload != "couette" else wl.case("couette")
-    g = Solver(cfg)
-    nc, nv = g.nc, g.nv
-    torch.cuda.synchronize()
-    g.step(wl.IMPLICIT, args.warmup)
-    torch.cuda.synchronize()
-    # per-kernel breakdown: K iterations with a HIP event pair around every kernel (an
-    # event pair costs a few microseconds, so this pass is not the timed one)
-    prof = g.profile(wl.IMPLICIT, args.steps)
-    torch.cuda.synchronize()
-    kernels = {k: {"ms_avg": ms / n, "launches": n} for k, (ms, n) in prof.items() if n}
-    dom = max(kernels, key=lambda k: kernels[k]["ms_avg"] * kernels[k]["launches"])
-    # timed region: exactly K implicit iterations, HIP events on the solver's stream around
-    # the dominant kernel only (read once at the end)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    live = g.profile(wl.IMPLICIT, args.steps, kernels=[dom])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = nc * nv / (elapsed / args.steps)
-    dom_ms, dom_n = live[dom]
-    kernels[dom]["ms_avg_timed_region"] = dom_ms / dom_n
-
-    s_bytes = 8 if prec == wl.FP64 else 4
-    per_launch_bytes = ALGO_BYTES.get(dom, 0) * s_bytes * nc * nv
-    if dom == "macro_lusgs":
-        per_launch_bytes = nc * 8 * MACRO_DOUBLES_PER_CELL
-    achieved = per_launch_bytes / (kernels[dom]["ms_avg_timed_region"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "kernel_ms": kernels[dom]["ms_avg_timed_region"],
-                "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(f"{args.workload}:{args.precision}", dom),
-                "algorithmic_bytes_per_launch": per_launch_bytes}
-    if dom == "macro_lusgs":
-        steps = 2 * (cfg["ni"] + cfg["nj"] - 1)
-        roofline["note"] = ("one workgroup sweeps 2 x (ni+nj-1) dependent hyperplane steps: "
-                            "bound by the step latency, not by bandwidth")
-        roofline["dependent_steps_per_launch"] = steps
-        roofline["us_per_step"] = 1e3 * roofline["kernel_ms"] / steps
-    streaming = {}
-    for k in ("face_partials", "face_records", "flux", "sweep_lower", "sweep_upper"):
-        if k in kernels:
-            b = ALGO_BYTES[k] * s_bytes * nc * nv
-            gbs = b / (kernels[k]["ms_avg"] * 1e-3) / 1e9
-            streaming[k] = {"GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
-
-    out = {"metric": METRIC, "value": value, "unit": "cell·vel/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+    cfg = case_cfg(args.workload, prec)
+    head = measure(cfg, args.workload, args.precision, args.steps, args.warmup)
+    print(f"headline {args.workload} {args.precision}: {head['ms_per_step']:.3f} ms per iteration",
+          file=sys.stderr, flush=True)
+    out = {"metric": METRIC, "value": head["value"], "unit": "cell·vel/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if prec == wl.FP64 else "f32+f64",
            "data": "synthetic",
-           "config": {"workload": f"{args.workload}: {cfg['ni']}x{cfg['nj']} cells, "
-                                  f"{cfg['nvx']}x{cfg['nvy']} velocities, Kn={cfg['Kn']}, "
-                                  f"CFL={cfg['cfl_imp']}",
-                      "cells": nc, "velocities": nv, "precision": args.precision},
-           "roofline": roofline, "streaming_kernels": streaming,
+           "config": {"workload": describe(args.workload, cfg, args.precision),
+                      "cells": head["cells"], "velocities": head["velocities"],
+                      "precision": args.precision},
+           "roofline": head["roofline"], "streaming_kernels": head["streaming_kernels"],
            # means of a separate K-iteration pass with events around every kernel
-           "kernels_ms": {k: round(v["ms_avg"], 5) for k, v in kernels.items()}}
-    if not args.no_ttr:
+           "kernels_ms": head["kernels_ms"]}
+    # the small benchmark-style cavity (cache resident and latency bound) beside it
+    if args.secondary and args.secondary != args.workload:
+        sec_prec = wl.FP64
+        sc = case_cfg(args.secondary, sec_prec)
+        sm = measure(sc, args.secondary, "fp64", args.steps, args.warmup)
+        out["secondary"] = {"workload": describe(args.secondary, sc, "fp64"), "value": sm["value"],
+                            "ms_per_step": sm["ms_per_step"], "roofline": sm["roofline"],
+                            "kernels_ms": sm["kernels_ms"]}
+    small = args.secondary
+    if small and not args.no_ttr:
         ttr = {}
         for name, pr in (("fp64", wl.FP64), ("fp32_mixed", wl.FP32_MIXED)):
-            c2 = wl.case(args.workload, precision=pr) if args.workload != "couette" else wl.case("couette")
-            s2 = Solver(c2)
+            s2 = Solver(case_cfg(small, pr))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             it, res, ok = s2.solve(1e-8, 5000)
@@ -329,13 +431,12 @@ def main():
             ttr[name] = {"seconds": time.perf_counter() - t0, "iterations": it, "res": res,
                          "converged": ok}
             del s2
-        out["time_to_residual_1e-8"] = ttr
+        out["time_to_residual_1e-8"] = {"workload": small, **ttr}
         # the paper's second predictor (point relaxation, FP64): fewer outer iterations with
         # more Jacobi sweeps, and no serial hyperplane chain in the macroscopic step
         pr = {}
         for k in (16, 32, 64):
-            cp = dict(wl.case(args.workload, precision=wl.FP64) if args.workload != "couette"
-                      else wl.case("couette"), predictor=1, relax_sweeps=k)
+            cp = dict(case_cfg(small, wl.FP64), predictor=1, relax_sweeps=k)
             gk = Solver(cp)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -344,15 +445,17 @@ def main():
             pr[f"sweeps_{k}"] = {"seconds": time.perf_counter() - t0, "iterations": it,
                                  "res": res, "converged": ok}
             del gk
-        out["time_to_residual_1e-8_point_relaxation"] = pr
+        out["time_to_residual_1e-8_point_relaxation"] = {"workload": small, **pr}
     if args.ttr_suite and not args.no_ttr:
         out["time_to_residual_1e-8_suite"] = ttr_suite(args.ttr_suite, args.ttr_budget)
-    if not args.no_explicit and nc * nv <= 2e7:
-        out["explicit_vs_implicit"] = explicit_vs_implicit(args.workload, cfg, args.explicit_cap)
+    if small and not args.no_explicit:
+        ecfg = case_cfg(small, wl.FP64)
+        if ecfg["ni"] * ecfg["nj"] * ecfg["nvx"] * ecfg["nvy"] <= 2e7:
+            out["explicit_vs_implicit"] = explicit_vs_implicit(small, ecfg, args.explicit_cap)
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(wl.case(args.workload, precision=wl.FP64) if args.workload != "couette"
-                          else wl.case("couette"), nc, nv, iters=args.cpu_sample_iters)
-        out["cpu_baseline"] = cb
+        out["cpu_baseline"] = cpu_baseline(case_cfg(args.workload, wl.FP64), head["cells"],
+                                           head["velocities"], iters=args.cpu_sample_iters,
+                                           one_thread=not args.no_cpu_one_thread)
     print(json.dumps(out))
 
 

@@ -112,6 +112,7 @@ struct orc_problem {
     /* optional captures of one implicit iteration (tests): the forward-sweep increment
        [2][nc][nv] and the wall ghost density increments [nf] */
     double *cap_dstar, *cap_drho;
+    int first_order;             /* analysis switch: no gradient in the reconstruction */
 };
 
 /* ------------------------------------------------------------------------- */
@@ -932,7 +933,8 @@ static void barplus_gradients(orc_problem *p)
         for (int s = 0; s < 2; ++s)
             for (int v = 0; v < nv; ++v) {
                 size_t o = (size_t)(s * nc + c) * nv + v;
-                cell_gradient(p, c, p->bp + (size_t)s * nc * nv + v, nv, p->limiter, p->sx + o, p->sy + o);
+                if (p->first_order) p->sx[o] = p->sy[o] = 0.0;
+                else cell_gradient(p, c, p->bp + (size_t)s * nc * nv + v, nv, p->limiter, p->sx + o, p->sy + o);
             }
 }
 
@@ -1579,3 +1581,7 @@ int orc_implicit_detail(orc_problem *p, double *delta_star, double *drho, double
     p->cap_drho = NULL;
     return rc;
 }
+
+/* Analysis switch: with first_order != 0 the reconstruction drops the gradient (the
+   first-order upwind residual, whose Jacobian is the one the micro LU-SGS factorises). */
+void orc_set_first_order(orc_problem *p, int32_t first_order) { p->first_order = first_order != 0; }

@@ -127,6 +127,10 @@ int orc_macro_sweep_rhs(orc_problem *p, const double *rhs, double *dW);
    wall ghost density increments [nf] formed from it (Eq. 35) */
 int orc_implicit_detail(orc_problem *p, double *delta_star, double *drho, double *res);
 
+/* analysis switch: first_order != 0 drops the gradient from the reconstruction (the
+   first-order upwind residual) */
+void orc_set_first_order(orc_problem *p, int32_t first_order);
+
 #ifdef __cplusplus
 }
 #endif

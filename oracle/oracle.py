@@ -86,6 +86,7 @@ def load():
         "orc_face_flux": (C.c_int, [_P, _D]),
         "orc_macro_sweep_rhs": (C.c_int, [_P, _D, _D]),
         "orc_implicit_detail": (C.c_int, [_P, _D, _D, _D]),
+        "orc_set_first_order": (None, [_P, C.c_int32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -322,3 +323,7 @@ class Oracle:
         r = C.c_double(0.0)
         self._check(self._lib.orc_implicit_detail(self._h, _dp(ds), _dp(dr), C.byref(r)))
         return ds, dr, r.value
+
+    def set_first_order(self, on=True):
+        """Analysis switch: reconstruction without the gradient (first-order residual)."""
+        self._lib.orc_set_first_order(self._h, 1 if on else 0)

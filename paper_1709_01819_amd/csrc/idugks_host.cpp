@@ -164,7 +164,6 @@ struct idugks_ctx {
     int64_t imp_iters;             // implicit iterations since init or set_state (its n)
     // profiling: one event pair per launch, read after the stream drains
     bool prof;
-    hipEvent_t ev0, ev1;
     std::vector<hipEvent_t> evs;
     std::vector<int> ev_kid;
     size_t ev_used;
@@ -712,7 +711,7 @@ idugks_status flux_pipeline(idugks_ctx *x) {
 idugks_status finalize_state(idugks_ctx *x, int mode) {
     const Params &p = x->p;
     RUN(KID_RAW, launch_raw(p, x->fp32, p.nm, x->st));
-    RUN(KID_FINALIZE, launch_finalize(p, mode, x->st));
+    RUN(KID_FINALIZE, launch_finalize(p, x->fp32, mode, x->st));
     return IDUGKS_OK;
 }
 
@@ -806,16 +805,10 @@ idugks_status idugks_describe(const idugks_config *cfg, double *xi, double *eta,
     return IDUGKS_OK;
 }
 
-idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t bytes, void *hip_stream,
-                          idugks_ctx **out) {
-    if (!out) return fail(IDUGKS_E_INVALID, "null output");
-    *out = nullptr;
-    idugks_status s = validate(cfg);
-    if (s != IDUGKS_OK) return s;
-    if (!d_workspace) return fail(IDUGKS_E_INVALID, "null workspace");
-    size_t need = 0;
-    idugks_workspace_size(cfg, &need);
-    if (bytes < need) return fail(IDUGKS_E_INVALID, "workspace too small");
+// Context on a validated configuration and a workspace of at least the required size.
+static idugks_status init_ctx(const idugks_config *cfg, void *d_workspace, void *hip_stream,
+                              idugks_ctx **out) {
+    idugks_status s;
     Built b;
     s = build(cfg, b);
     if (s != IDUGKS_OK) return s;
@@ -908,10 +901,6 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
         delete x;
         return fail(IDUGKS_E_DEVICE, std::string("init upload: ") + hipGetErrorString(e));
     }
-    if (hipEventCreate(&x->ev0) != hipSuccess || hipEventCreate(&x->ev1) != hipSuccess) {
-        delete x;
-        return fail(IDUGKS_E_DEVICE, "hipEventCreate failed");
-    }
     s = finalize_state(x, 0);
     double sc[SC_NUM];
     if (s == IDUGKS_OK) s = read_scalars(x, sc);
@@ -924,10 +913,21 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     return IDUGKS_OK;
 }
 
+idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t bytes, void *hip_stream,
+                          idugks_ctx **out) {
+    if (!out) return fail(IDUGKS_E_INVALID, "null output");
+    *out = nullptr;
+    idugks_status s = validate(cfg);
+    if (s != IDUGKS_OK) return s;
+    if (!d_workspace) return fail(IDUGKS_E_INVALID, "null workspace");
+    size_t need = 0;
+    idugks_workspace_size(cfg, &need);
+    if (bytes < need) return fail(IDUGKS_E_INVALID, "workspace too small");
+    return init_ctx(cfg, d_workspace, hip_stream, out);
+}
+
 void idugks_destroy(idugks_ctx *ctx) {
     if (!ctx) return;
-    (void)hipEventDestroy(ctx->ev0);
-    (void)hipEventDestroy(ctx->ev1);
     for (hipEvent_t e : ctx->evs) (void)hipEventDestroy(e);
     delete ctx;
 }

@@ -8,7 +8,7 @@
 //   tabs [nc][nvx+nvy] S   same for the predicted records
 //   tabf [nf][nvx+nvy] S   same for the face records
 //   rec, recs [nc], recf [nf]   FP64 equilibrium records
-//   part [nc][4][NM]   FP64 partial face moments, one slot per cell side
+//   fv   [nf][2][nvp]  S   reconstructed phi-bar at every face (Eq. 13-14)
 //   raw  [nc][NM]      FP64 raw moments of the stored state
 // S is double (FP64 form) or float (FP32-mixed form).  nvp = nv rounded up to 64.
 #pragma once

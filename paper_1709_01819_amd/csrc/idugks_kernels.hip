@@ -371,9 +371,13 @@ __global__ __launch_bounds__(256) void k_raw(Params p) {
 
 // ---------------------------------------------------------------------------------------
 // finalize: closed-domain mass scale, residual, divergence flag (one block)
-// mode 0: after init/set_state (scale 1, no residual); 1: implicit; 2: explicit
+// mode 0: after init/set_state (scale 1, no residual); 1: implicit; 2: explicit.
+// The scale is applied lazily: every reader of the stored state multiplies by it.  With an
+// FP32 state (round32) those readers multiply in FP32, so the scale is rounded to FP32 here
+// and the records, the residual and the moments use that same value; an unrounded FP64 scale
+// would leave a collision term (float(s) - s) phi that never vanishes at steady state.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_finalize(Params p, int mode) {
+__global__ __launch_bounds__(1024) void k_finalize(Params p, int mode, int round32) {
     __shared__ double sh[16 * 3];
     const int NM = NM_MAX;
     // each thread takes the cells tid, tid + B, ... (B = blockDim), four per pass so that
@@ -394,7 +398,8 @@ __global__ __launch_bounds__(1024) void k_finalize(Params p, int mode) {
     }
     block_sum<1, true>(a, sh);
     const double mass = a[0];
-    const double s = (mode == 1 && p.closed) ? p.M0 / mass : 1.0;
+    double s = (mode == 1 && p.closed) ? p.M0 / mass : 1.0;
+    if (round32) s = (double)(float)s;
     double b[3] = {0.0, 0.0, 0.0};
     for (int c0 = tid; c0 < p.nc; c0 += 4 * B) {
         double r0[4], r3[4], ro[4];
@@ -794,9 +799,9 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
         MH[v] = (S)accH;
         const double wv = p.w[v], dG = (double)accG;
         mw[0] += wv * dG;
-        mw[1] += wv * (double)x * dG;
-        mw[2] += wv * (double)y * dG;
-        mw[3] += 0.5 * wv * (((double)x * (double)x + (double)y * (double)y) * dG + (double)accH);
+        mw[1] += wv * xd * dG;
+        mw[2] += wv * yd * dG;
+        mw[3] += 0.5 * wv * ((xd * xd + yd * yd) * dG + (double)accH);
     }
     if (PREP) {
         block_sum<4, true>(mw, sh);
@@ -2094,8 +2099,8 @@ hipError_t launch_raw(const Params &p, bool fp32, int nm, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Params &p, int mode, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, p, mode);
+hipError_t launch_finalize(const Params &p, bool fp32, int mode, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, p, mode, fp32 ? 1 : 0);
     return hipGetLastError();
 }
 

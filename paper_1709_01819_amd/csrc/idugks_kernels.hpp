@@ -9,7 +9,7 @@
 namespace idugks {
 
 hipError_t launch_raw(const Params &p, bool fp32, int nm, hipStream_t st);
-hipError_t launch_finalize(const Params &p, int mode, hipStream_t st);
+hipError_t launch_finalize(const Params &p, bool fp32, int mode, hipStream_t st);
 hipError_t launch_records(const Params &p, bool fp32, int which, hipStream_t st);
 hipError_t launch_partials(const Params &p, bool fp32, hipStream_t st);
 hipError_t launch_face_records(const Params &p, bool fp32, hipStream_t st);
