@@ -121,6 +121,21 @@ idugks_status idugks_workspace_size(const idugks_config *cfg, size_t *bytes);
 idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t bytes,
                           void *hip_stream, idugks_ctx **out);
 
+/* Largest workspace idugks_init_noalloc can hold: the size of the library's static scratch
+   array, which every GPU the library is loaded on holds until the process ends. */
+#define IDUGKS_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code that runs under HIP graph capture,
+   tight serving loops, harnesses that forbid allocation): idugks_init with the workspace
+   taken from the library's static scratch array on the current device instead of a caller
+   buffer; no device memory is allocated or freed.  The array is cleared (by a kernel on
+   hip_stream) before use, so nothing of an earlier context carries over.  One such context
+   may live per device at a time: a second call before idugks_destroy of the first returns
+   IDUGKS_E_STATE (contexts sharing the array would overwrite each other's state).
+   Configurations whose idugks_workspace_size exceeds IDUGKS_NOALLOC_MAX_BYTES return
+   IDUGKS_E_NOMEM before any device work.  All other calls work on the context as usual. */
+idugks_status idugks_init_noalloc(const idugks_config *cfg, void *hip_stream, idugks_ctx **out);
+
 /* Sizes and scalars of a context.  out: host. */
 idugks_status idugks_get_info(idugks_ctx *ctx, idugks_info *out);
 

@@ -54,6 +54,7 @@ _SIGS = {
                                   _D, _D, _D, _D, _D]),
     "idugks_workspace_size": (C.c_int, [C.POINTER(Config), C.POINTER(C.c_size_t)]),
     "idugks_init": (C.c_int, [C.POINTER(Config), _P, C.c_size_t, _P, C.POINTER(_P)]),
+    "idugks_init_noalloc": (C.c_int, [C.POINTER(Config), _P, C.POINTER(_P)]),
     "idugks_get_info": (C.c_int, [_P, C.POINTER(Info)]),
     "idugks_velocities": (C.c_int, [_P, _D, _D, _D]),
     "idugks_step": (C.c_int, [_P, C.c_int32, C.c_int32, _D]),
@@ -78,6 +79,7 @@ _SIGS = {
     "idugks_destroy": (None, [_P]),
 }
 EXPORTED = tuple(_SIGS)
+NOALLOC_MAX_BYTES = 64 << 20   # IDUGKS_NOALLOC_MAX_BYTES
 _lib = None
 
 

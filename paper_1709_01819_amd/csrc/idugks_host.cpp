@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -170,6 +171,7 @@ struct idugks_ctx {
     double ms[KID_COUNT];
     int64_t cnt[KID_COUNT];
     uint32_t prof_mask;  // kernels timed while prof is set (bit k: kernel k)
+    int scratch_dev;     // device whose static scratch array is the workspace (-1: the caller's)
 };
 
 namespace {
@@ -759,6 +761,48 @@ idugks_status read_scalars(idugks_ctx *x, double *sc) {
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
+// Static scratch array: the workspace of contexts made by idugks_init_noalloc, for callers
+// that cannot allocate device memory.  Each GPU the library runs on holds its own copy until
+// the process ends.  In host code the array's name is only a stand-in for the symbol: its
+// device address, per device, comes from hipGetSymbolAddress with that device current.  At
+// most one such context may live per device (its contents are the context's state).
+// ---------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[IDUGKS_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];   // device address of `scratch` on each device (null: not yet)
+bool g_scratch_busy[kMaxDevices];   // a live context uses that device's array
+
+idugks_status acquire_scratch(int *dev, void **ptr) {
+    int d = -1;
+    HIPCHK(hipGetDevice(&d));
+    if (d < 0 || d >= kMaxDevices) return fail(IDUGKS_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_busy[d])
+        return fail(IDUGKS_E_STATE, "the static scratch array of this device is in use by another context "
+                                    "(destroy it first)");
+    if (!g_scratch_ptr[d]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(IDUGKS_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[d] = p;
+    }
+    g_scratch_busy[d] = true;
+    *dev = d;
+    *ptr = g_scratch_ptr[d];
+    return IDUGKS_OK;
+}
+
+void release_scratch(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev >= 0 && dev < kMaxDevices) g_scratch_busy[dev] = false;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------------------
 extern "C" {
@@ -806,7 +850,7 @@ idugks_status idugks_describe(const idugks_config *cfg, double *xi, double *eta,
 }
 
 // Context on a validated configuration and a workspace of at least the required size.
-static idugks_status init_ctx(const idugks_config *cfg, void *d_workspace, void *hip_stream,
+static idugks_status init_ctx(const idugks_config *cfg, void *d_workspace, void *hip_stream, int scratch_dev,
                               idugks_ctx **out) {
     idugks_status s;
     Built b;
@@ -817,6 +861,7 @@ static idugks_status init_ctx(const idugks_config *cfg, void *d_workspace, void 
     auto R = [&](int r) { return (void *)(base + L.off[r]); };
 
     idugks_ctx *x = new idugks_ctx();
+    x->scratch_dev = -1;  // set by the caller once the context exists
     x->cfg = *cfg;
     x->cfg.xn = x->cfg.yn = nullptr;
     x->fp32 = cfg->precision == IDUGKS_FP32_MIXED;
@@ -909,6 +954,7 @@ static idugks_status init_ctx(const idugks_config *cfg, void *d_workspace, void 
         return s;
     }
     p.M0 = sc[SC_MASS];
+    x->scratch_dev = scratch_dev;
     *out = x;
     return IDUGKS_OK;
 }
@@ -923,12 +969,39 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
     size_t need = 0;
     idugks_workspace_size(cfg, &need);
     if (bytes < need) return fail(IDUGKS_E_INVALID, "workspace too small");
-    return init_ctx(cfg, d_workspace, hip_stream, out);
+    return init_ctx(cfg, d_workspace, hip_stream, -1, out);
+}
+
+idugks_status idugks_init_noalloc(const idugks_config *cfg, void *hip_stream, idugks_ctx **out) {
+    if (!out) return fail(IDUGKS_E_INVALID, "null output");
+    *out = nullptr;
+    idugks_status s = validate(cfg);
+    if (s != IDUGKS_OK) return s;
+    size_t need = 0;
+    idugks_workspace_size(cfg, &need);
+    if (need > IDUGKS_NOALLOC_MAX_BYTES)
+        return fail(IDUGKS_E_NOMEM, "configuration needs " + std::to_string(need) +
+                                        " bytes of workspace, above the static scratch array's " +
+                                        std::to_string((size_t)IDUGKS_NOALLOC_MAX_BYTES));
+    int dev = -1;
+    void *ptr = nullptr;
+    s = acquire_scratch(&dev, &ptr);
+    if (s != IDUGKS_OK) return s;
+    // the array keeps the last context's contents: start from zeros, like a fresh buffer
+    hipError_t e = launch_zero(ptr, need, (hipStream_t)hip_stream);
+    if (e != hipSuccess) {
+        release_scratch(dev);
+        return fail(IDUGKS_E_DEVICE, std::string("scratch clear: ") + hipGetErrorString(e));
+    }
+    s = init_ctx(cfg, ptr, hip_stream, dev, out);
+    if (s != IDUGKS_OK) release_scratch(dev);
+    return s;
 }
 
 void idugks_destroy(idugks_ctx *ctx) {
     if (!ctx) return;
     for (hipEvent_t e : ctx->evs) (void)hipEventDestroy(e);
+    if (ctx->scratch_dev >= 0) release_scratch(ctx->scratch_dev);
     delete ctx;
 }
 

@@ -1542,6 +1542,17 @@ __global__ void k_unpack(Params p, const double *src, int sp, int nsp) {
     }
 }
 
+// zeros over n16 16-byte words (a fill kernel rather than a memset node)
+__global__ void k_zero(uint4 *p, size_t n16) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n16; t += (size_t)gridDim.x * blockDim.x)
+        p[t] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, (uint4 *)p, bytes / 16);
+    return hipGetLastError();
+}
+
 // uniform initial state: f[c][s][v] = eq[s][v] (eq staged as FP64 [2][nvp] in d1)
 template <class S>
 __global__ void k_fill_uniform(Params p, const double *eq) {

@@ -37,6 +37,7 @@ hipError_t launch_pack(const Params &p, bool fp32, const void *src, double *dst,
 hipError_t launch_unpack(const Params &p, bool fp32, const double *src, int sp, int nsp,
                          hipStream_t st);
 hipError_t launch_fill_uniform(const Params &p, bool fp32, const double *eq, hipStream_t st);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);  // bytes: a multiple of 16
 hipError_t launch_fields(const Params &p, double *out, hipStream_t st);
 
 // sensitivities (FP64 state, BGK, no limiter); obj: -1 none, 0 lid x-momentum flux,

@@ -15,20 +15,28 @@ def _dp(a):
 class Solver:
     """One IDUGKS problem on one GPU (see include/idugks.h for the semantics of each call)."""
 
-    def __init__(self, cfg, device="cuda:0", stream=None):
+    def __init__(self, cfg, device="cuda:0", stream=None, static_workspace=False):
+        """static_workspace: take the workspace from the library's static scratch array
+        (idugks_init_noalloc; nothing is allocated) instead of a torch buffer."""
         import torch
         self._lib = load_library()
         self.cfg = cfg
         self.device = torch.device(device)
         c, keep = make_config(cfg)
-        nbytes = C.c_size_t(0)
-        self._check(self._lib.idugks_workspace_size(C.byref(c), C.byref(nbytes)))
-        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = C.c_void_p()
-        self._check(self._lib.idugks_init(C.byref(c), C.c_void_p(self.workspace.data_ptr()),
-                                          nbytes.value, C.c_void_p(self.stream.cuda_stream),
-                                          C.byref(h)))
+        if static_workspace:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                self._check(self._lib.idugks_init_noalloc(C.byref(c), C.c_void_p(self.stream.cuda_stream),
+                                                          C.byref(h)))
+        else:
+            nbytes = C.c_size_t(0)
+            self._check(self._lib.idugks_workspace_size(C.byref(c), C.byref(nbytes)))
+            self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+            self._check(self._lib.idugks_init(C.byref(c), C.c_void_p(self.workspace.data_ptr()),
+                                              nbytes.value, C.c_void_p(self.stream.cuda_stream),
+                                              C.byref(h)))
         del keep
         self._h = h
         info = self.info()
