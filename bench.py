@@ -72,7 +72,7 @@ def parse():
     ap.add_argument("--cpu-sample-iters", type=int, default=0,
                     help="oracle iterations of the CPU baseline (0 = 3 on workloads above "
                          "1e8 cell-velocity pairs, else sized to ~15 s)")
-    ap.add_argument("--ttr-suite", default="couette,cavity_kn10@100,cylinder_ma5", metavar="NAMES",
+    ap.add_argument("--ttr-suite", default="couette,cavity_kn10,cylinder_ma5", metavar="NAMES",
                     help="time the solve to residual 1e-8 of these comma-separated workloads "
                          "in FP64 and FP32-mixed as well (name@CFL sets the implicit CFL, "
                          "name@CFL@START@GROWTH its start-up ramp; an empty string skips them)")

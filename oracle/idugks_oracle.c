@@ -82,6 +82,7 @@ struct orc_problem {
     double *onx, *ony;    /* [nc][4] outward unit normal of side s */
     double *sS;           /* [nc][4] face length of side s */
     double *ax, *ay;      /* [nc][4] least-squares weights (Eq. 15) */
+    double *sgn;          /* [nc][4] +1 if the cell is the L end of the side's face, -1 if R */
     /* faces */
     int *fL, *fR, *ftype, *fside;
     double *fnx, *fny, *fS;      /* unit normal from L to R (outward for boundary faces) */
@@ -527,6 +528,7 @@ static int build_mesh(orc_problem *p, const orc_config *cfg)
     p->sS = calloc(4 * nc, sizeof(double));
     p->ax = calloc(4 * nc, sizeof(double));
     p->ay = calloc(4 * nc, sizeof(double));
+    p->sgn = calloc(4 * nc, sizeof(double));
     for (int c = 0; c < nc; ++c)
         for (int s = 0; s < 4; ++s) {
             int k = p->cf[4 * c + s], m = 4 * c + s;
@@ -534,6 +536,7 @@ static int build_mesh(orc_problem *p, const orc_config *cfg)
                face, sides i- / j- the R end (a boundary face's only cell is its L end). */
             int isL = (p->fR[k] < 0) || (s == 1 || s == 3);
             double sgn = isL ? 1.0 : -1.0;
+            p->sgn[m] = sgn;
             p->onx[m] = sgn * p->fnx[k];
             p->ony[m] = sgn * p->fny[k];
             p->sS[m] = p->fS[k];
@@ -574,14 +577,194 @@ static int build_mesh(orc_problem *p, const orc_config *cfg)
     return 0;
 }
 
+/* Unstructured mesh of quadrilaterals and triangles (nodes counter-clockwise; a triangle
+   has -1 as its fourth node).  Side s of a cell is the edge from its node s to the next one;
+   a triangle's fourth side is absent and points at one shared zero-length face of the
+   self type, which every step skips.  Two cells sharing an edge share a face whose L end
+   is the lower-indexed cell; a boundary edge carries the tag (0..3) that selects its
+   boundary condition among the four of the configuration. */
+typedef struct { int a, b, cell, side; } edge_rec;
+
+static int edge_cmp(const void *x, const void *y)
+{
+    const edge_rec *e = x, *f = y;
+    if (e->a != f->a) return e->a < f->a ? -1 : 1;
+    if (e->b != f->b) return e->b < f->b ? -1 : 1;
+    if (e->cell != f->cell) return e->cell < f->cell ? -1 : 1;
+    return e->side - f->side;
+}
+
+static int build_mesh_unstructured(orc_problem *p, const orc_config *cfg, const orc_mesh *m)
+{
+    const int nc = m->ncells;
+    const double *xn = m->xn, *yn = m->yn;
+    p->ni = nc;
+    p->nj = 1;
+    p->nc = nc;
+    p->area = calloc(nc, sizeof(double));
+    p->xc = calloc(nc, sizeof(double));
+    p->yc = calloc(nc, sizeof(double));
+    for (int c = 0; c < nc; ++c) {
+        const int32_t *cn = m->cell_nodes + 4 * c;
+        int nn = cn[3] < 0 ? 3 : 4;
+        double a = 0, cx = 0, cy = 0;
+        for (int k = 0; k < nn; ++k) {
+            int i0 = cn[k], i1 = cn[(k + 1) % nn];
+            if (i0 < 0 || i0 >= m->nnodes || i1 < 0 || i1 >= m->nnodes) return fail(ORC_INVALID, "bad node index");
+            double x0 = xn[i0], y0 = yn[i0], x1 = xn[i1], y1 = yn[i1], cr = x0 * y1 - x1 * y0;
+            a += cr;
+            cx += (x0 + x1) * cr;
+            cy += (y0 + y1) * cr;
+        }
+        a *= 0.5;
+        if (!(a > 0)) return fail(ORC_INVALID, "non-positive cell area (cells must be counter-clockwise)");
+        p->area[c] = a;
+        p->xc[c] = cx / (6.0 * a);
+        p->yc[c] = cy / (6.0 * a);
+    }
+    /* pair up the edges */
+    edge_rec *e = malloc(4 * (size_t)nc * sizeof(edge_rec));
+    int ne = 0;
+    for (int c = 0; c < nc; ++c) {
+        const int32_t *cn = m->cell_nodes + 4 * c;
+        int nn = cn[3] < 0 ? 3 : 4;
+        for (int k = 0; k < nn; ++k) {
+            int i0 = cn[k], i1 = cn[(k + 1) % nn];
+            e[ne].a = i0 < i1 ? i0 : i1;
+            e[ne].b = i0 < i1 ? i1 : i0;
+            e[ne].cell = c;
+            e[ne].side = k;
+            ++ne;
+        }
+    }
+    qsort(e, ne, sizeof(edge_rec), edge_cmp);
+    int maxf = ne + 1;
+    p->fL = malloc(maxf * sizeof(int));
+    p->fR = malloc(maxf * sizeof(int));
+    p->ftype = malloc(maxf * sizeof(int));
+    p->fside = malloc(maxf * sizeof(int));
+    p->fnx = malloc(maxf * sizeof(double));
+    p->fny = malloc(maxf * sizeof(double));
+    p->fS = malloc(maxf * sizeof(double));
+    p->fmx = malloc(maxf * sizeof(double));
+    p->fmy = malloc(maxf * sizeof(double));
+    p->fshx = calloc(maxf, sizeof(double));
+    p->fshy = calloc(maxf, sizeof(double));
+    p->cf = malloc(4 * nc * sizeof(int));
+    p->nb = malloc(4 * nc * sizeof(int));
+    p->nbdx = calloc(4 * nc, sizeof(double));
+    p->nbdy = calloc(4 * nc, sizeof(double));
+    p->fdx = calloc(4 * nc, sizeof(double));
+    p->fdy = calloc(4 * nc, sizeof(double));
+    p->onx = calloc(4 * nc, sizeof(double));
+    p->ony = calloc(4 * nc, sizeof(double));
+    p->sS = calloc(4 * nc, sizeof(double));
+    p->ax = calloc(4 * nc, sizeof(double));
+    p->ay = calloc(4 * nc, sizeof(double));
+    p->sgn = calloc(4 * nc, sizeof(double));
+    for (int k = 0; k < 4 * nc; ++k) { p->cf[k] = -1; p->nb[k] = -1; }
+    int nf = 0, nwall = 0;
+    for (int i = 0; i < ne;) {
+        int j = i + 1;
+        while (j < ne && e[j].a == e[i].a && e[j].b == e[i].b) ++j;
+        if (j - i > 2) { free(e); return fail(ORC_INVALID, "an edge shared by more than two cells"); }
+        const edge_rec *L = &e[i];  /* lower cell index first (sorted) */
+        const int32_t *cn = m->cell_nodes + 4 * L->cell;
+        int nn = cn[3] < 0 ? 3 : 4;
+        int i0 = cn[L->side], i1 = cn[(L->side + 1) % nn];
+        double tx = xn[i1] - xn[i0], ty = yn[i1] - yn[i0], S = sqrt(tx * tx + ty * ty);
+        int k = nf++;
+        p->fS[k] = S;
+        p->fnx[k] = ty / S;  /* outward of the counter-clockwise L cell */
+        p->fny[k] = -tx / S;
+        p->fmx[k] = 0.5 * (xn[i0] + xn[i1]);
+        p->fmy[k] = 0.5 * (yn[i0] + yn[i1]);
+        p->fL[k] = L->cell;
+        p->cf[4 * L->cell + L->side] = k;
+        p->sgn[4 * L->cell + L->side] = 1.0;
+        if (j - i == 2) {
+            const edge_rec *R = &e[i + 1];
+            p->fR[k] = R->cell;
+            p->ftype[k] = F_INTERIOR;
+            p->fside[k] = -1;
+            p->cf[4 * R->cell + R->side] = k;
+            p->sgn[4 * R->cell + R->side] = -1.0;
+            p->nb[4 * L->cell + L->side] = R->cell;
+            p->nb[4 * R->cell + R->side] = L->cell;
+        } else {
+            int tag = m->side_tag[4 * L->cell + L->side];
+            if (tag < 0 || tag > 3) { free(e); return fail(ORC_INVALID, "boundary edge without a tag 0..3"); }
+            p->fR[k] = -1;
+            p->fside[k] = tag;
+            p->ftype[k] = cfg->bc[tag] == BC_WALL ? F_WALL : F_FAR;
+            if (p->ftype[k] == F_WALL) ++nwall;
+        }
+        i = j;
+    }
+    free(e);
+    /* the shared absent side of the triangles */
+    int kabs = nf++;
+    p->fL[kabs] = p->fR[kabs] = -1;
+    p->ftype[kabs] = F_SELF;
+    p->fside[kabs] = -1;
+    p->fnx[kabs] = p->fny[kabs] = p->fS[kabs] = p->fmx[kabs] = p->fmy[kabs] = 0.0;
+    for (int c = 0; c < nc; ++c)
+        if (m->cell_nodes[4 * c + 3] < 0) p->cf[4 * c + 3] = kabs;
+    p->nf = nf;
+    p->nwall = nwall;
+    for (int c = 0; c < nc; ++c)
+        for (int s = 0; s < 4; ++s) {
+            int m4 = 4 * c + s, k = p->cf[m4];
+            if (p->ftype[k] == F_SELF) continue;  /* absent side: zero geometry */
+            double sg = p->sgn[m4];
+            p->onx[m4] = sg * p->fnx[k];
+            p->ony[m4] = sg * p->fny[k];
+            p->sS[m4] = p->fS[k];
+            p->fdx[m4] = p->fmx[k] - p->xc[c];
+            p->fdy[m4] = p->fmy[k] - p->yc[c];
+            int o = p->nb[m4];
+            if (o >= 0) {
+                p->nbdx[m4] = p->xc[o] - p->xc[c];
+                p->nbdy[m4] = p->yc[o] - p->yc[c];
+            }
+        }
+    for (int c = 0; c < nc; ++c) {
+        double a11 = 0, a12 = 0, a22 = 0;
+        for (int s = 0; s < 4; ++s) {
+            int m4 = 4 * c + s;
+            if (p->nb[m4] < 0) continue;
+            a11 += p->nbdx[m4] * p->nbdx[m4];
+            a12 += p->nbdx[m4] * p->nbdy[m4];
+            a22 += p->nbdy[m4] * p->nbdy[m4];
+        }
+        double det = a11 * a22 - a12 * a12;
+        if (!(det > 0)) return fail(ORC_INVALID, "degenerate least-squares stencil");
+        for (int s = 0; s < 4; ++s) {
+            int m4 = 4 * c + s;
+            if (p->nb[m4] < 0) continue;
+            p->ax[m4] = (a22 * p->nbdx[m4] - a12 * p->nbdy[m4]) / det;
+            p->ay[m4] = (-a12 * p->nbdx[m4] + a11 * p->nbdy[m4]) / det;
+        }
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Creation                                                                   */
 /* ------------------------------------------------------------------------- */
-static int validate(const orc_config *c)
+static int validate(const orc_config *c, const orc_mesh *mesh)
 {
     if (!c) return fail(ORC_INVALID, "null config");
-    if (c->ni < 1 || c->nj < 1) return fail(ORC_INVALID, "mesh needs ni, nj >= 1");
-    if (!c->xn || !c->yn) return fail(ORC_INVALID, "missing node coordinates");
+    if (mesh) {
+        if (mesh->nnodes < 3 || mesh->ncells < 1 || !mesh->xn || !mesh->yn || !mesh->cell_nodes ||
+            !mesh->side_tag)
+            return fail(ORC_INVALID, "incomplete unstructured mesh");
+        for (int s = 0; s < 4; ++s)
+            if (c->bc[s] == BC_PERIODIC) return fail(ORC_INVALID, "no periodic sides on unstructured meshes");
+    } else {
+        if (c->ni < 1 || c->nj < 1) return fail(ORC_INVALID, "mesh needs ni, nj >= 1");
+        if (!c->xn || !c->yn) return fail(ORC_INVALID, "missing node coordinates");
+    }
     if (c->predictor < 0 || c->predictor > 1) return fail(ORC_INVALID, "unknown predictor");
     if (c->relax_sweeps < 0 || c->relax_sweeps > 64) return fail(ORC_INVALID, "relax_sweeps must be 0..64");
     if (c->nvx < 2 || c->nvy < 2) return fail(ORC_INVALID, "need nv >= 2");
@@ -615,7 +798,7 @@ static void free_problem(orc_problem *p)
 {
     if (!p) return;
     void *ptrs[] = {p->xi, p->eta, p->w, p->area, p->xc, p->yc, p->cf, p->nb, p->nbdx, p->nbdy,
-                    p->fdx, p->fdy, p->onx, p->ony, p->sS, p->ax, p->ay, p->fL, p->fR, p->ftype,
+                    p->fdx, p->fdy, p->onx, p->ony, p->sS, p->ax, p->ay, p->sgn, p->fL, p->fR, p->ftype,
                     p->fside, p->fnx, p->fny, p->fS, p->fmx, p->fmy, p->fshx, p->fshy, p->gw,
                     p->ginf, p->hinf, p->wden, p->f, p->drho_g, p->W, p->RT, p->tau, p->q,
                     p->feq, p->bp, p->sx, p->sy, p->F, p->Wf, p->rhow, p->M, p->MW, p->dW,
@@ -646,11 +829,11 @@ static double total_mass(const orc_problem *p, const double *f)
     return m;
 }
 
-int orc_create(const orc_config *cfg, orc_problem **out)
+static int create(const orc_config *cfg, const orc_mesh *mesh, orc_problem **out)
 {
     if (!out) return fail(ORC_INVALID, "null output pointer");
     *out = NULL;
-    int rc = validate(cfg);
+    int rc = validate(cfg, mesh);
     if (rc) return rc;
     orc_problem *p = calloc(1, sizeof *p);
     if (!p) return fail(ORC_NOMEM, "out of memory");
@@ -667,7 +850,7 @@ int orc_create(const orc_config *cfg, orc_problem **out)
     p->cfl_growth = cfg->cfl_growth;
     p->imp_iters = 0;
     p->mu_ref = cfg->Kn / sqrt(M_PI); /* Eq. 37 with rho = L = 2RT = 1 */
-    if ((rc = build_mesh(p, cfg))) {
+    if ((rc = mesh ? build_mesh_unstructured(p, cfg, mesh) : build_mesh(p, cfg))) {
         free_problem(p);
         return rc;
     }
@@ -703,6 +886,7 @@ int orc_create(const orc_config *cfg, orc_problem **out)
         double d = INFINITY;
         for (int s = 0; s < 4; ++s) {
             int m = 4 * c + s;
+            if (p->sS[m] == 0.0) continue; /* absent side of a triangle */
             double e = fabs(p->fdx[m] * p->onx[m] + p->fdy[m] * p->ony[m]);
             if (e < d) d = e;
         }
@@ -793,6 +977,13 @@ int orc_create(const orc_config *cfg, orc_problem **out)
     p->M0 = total_mass(p, p->f);
     *out = p;
     return ORC_OK;
+}
+
+int orc_create(const orc_config *cfg, orc_problem **out) { return create(cfg, NULL, out); }
+
+int orc_create_mesh(const orc_config *cfg, const orc_mesh *mesh, orc_problem **out)
+{
+    return create(cfg, mesh, out);
 }
 
 void orc_sizes(const orc_problem *p, int32_t out[4])
@@ -1038,9 +1229,8 @@ static void flux_sum(orc_problem *p)
             for (int side = 0; side < 4; ++side) {
                 int k = p->cf[4 * c + side];
                 if (p->ftype[k] == F_SELF) continue;
-                int isL = (p->fR[k] < 0) || side == 1 || side == 3;
                 const double *Fk = p->F + (size_t)(s * nf + k) * nv;
-                if (isL)
+                if (p->sgn[4 * c + side] > 0)
                     for (int v = 0; v < nv; ++v) Mc[v] -= Fk[v];
                 else
                     for (int v = 0; v < nv; ++v) Mc[v] += Fk[v];

@@ -46,12 +46,28 @@ typedef struct {
     double cfl_start, cfl_growth;
 } orc_config;
 
+/* Unstructured mesh of quadrilaterals and triangles.  cell_nodes [ncells][4]: node indices
+   counter-clockwise, -1 in the fourth slot of a triangle; side s of a cell is the edge from
+   node s to the next.  side_tag [ncells][4]: for a side on the boundary, which of the four
+   boundary conditions of the configuration (bc, wall_*, far_*) applies, 0..3; ignored
+   elsewhere.  The sweeps take the cells in index order. */
+typedef struct {
+    int32_t nnodes;
+    const double *xn, *yn;
+    int32_t ncells;
+    const int32_t *cell_nodes;
+    const int32_t *side_tag;
+} orc_mesh;
+
 typedef struct orc_problem orc_problem;
 
 /* Return codes. */
 enum { ORC_OK = 0, ORC_INVALID = 1, ORC_NOMEM = 2, ORC_DIVERGED = 4, ORC_NOT_CONVERGED = 5 };
 
 int orc_create(const orc_config *cfg, orc_problem **out);
+/* as orc_create on an unstructured mesh (the structured fields ni, nj, xn, yn are ignored;
+   no periodic sides) */
+int orc_create_mesh(const orc_config *cfg, const orc_mesh *mesh, orc_problem **out);
 void orc_destroy(orc_problem *p);
 const char *orc_last_error(void);
 

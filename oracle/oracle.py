@@ -24,6 +24,14 @@ def build(force=True):
     return _LIB
 
 
+class OrcMesh(C.Structure):
+    _fields_ = [
+        ("nnodes", C.c_int32), ("xn", C.POINTER(C.c_double)), ("yn", C.POINTER(C.c_double)),
+        ("ncells", C.c_int32), ("cell_nodes", C.POINTER(C.c_int32)),
+        ("side_tag", C.POINTER(C.c_int32)),
+    ]
+
+
 class OrcConfig(C.Structure):
     _fields_ = [
         ("ni", C.c_int32), ("nj", C.c_int32),
@@ -55,6 +63,7 @@ def load():
     lib = C.CDLL(_LIB)
     sig = {
         "orc_create": (C.c_int, [C.POINTER(OrcConfig), C.POINTER(_P)]),
+        "orc_create_mesh": (C.c_int, [C.POINTER(OrcConfig), C.POINTER(OrcMesh), C.POINTER(_P)]),
         "orc_destroy": (None, [_P]),
         "orc_last_error": (C.c_char_p, []),
         "orc_sizes": (None, [_P, _I]),
@@ -120,13 +129,28 @@ class Oracle:
     """One problem instance of the CPU reference."""
 
     def __init__(self, cfg):
+        """cfg: a workload dict; with a "mesh" entry (xn, yn, cell_nodes [nc, 4], side_tag
+        [nc, 4]) the problem lives on that unstructured mesh and ni, nj, xn, yn are unused."""
         lib = load()
         self._lib = lib
-        self._xn = np.ascontiguousarray(cfg["xn"], dtype=np.float64)
-        self._yn = np.ascontiguousarray(cfg["yn"], dtype=np.float64)
+        mesh = cfg.get("mesh")
         c = OrcConfig()
-        c.ni, c.nj = cfg["ni"], cfg["nj"]
-        c.xn, c.yn = _dp(self._xn), _dp(self._yn)
+        if mesh is None:
+            self._xn = np.ascontiguousarray(cfg["xn"], dtype=np.float64)
+            self._yn = np.ascontiguousarray(cfg["yn"], dtype=np.float64)
+            c.ni, c.nj = cfg["ni"], cfg["nj"]
+            c.xn, c.yn = _dp(self._xn), _dp(self._yn)
+        else:
+            self._xn = np.ascontiguousarray(mesh["xn"], dtype=np.float64)
+            self._yn = np.ascontiguousarray(mesh["yn"], dtype=np.float64)
+            self._cn = np.ascontiguousarray(mesh["cell_nodes"], dtype=np.int32)
+            self._tag = np.ascontiguousarray(mesh["side_tag"], dtype=np.int32)
+            assert self._cn.shape == self._tag.shape and self._cn.shape[1] == 4
+            m = OrcMesh()
+            m.nnodes, m.ncells = len(self._xn), self._cn.shape[0]
+            m.xn, m.yn = _dp(self._xn), _dp(self._yn)
+            m.cell_nodes = self._cn.ctypes.data_as(_I)
+            m.side_tag = self._tag.ctypes.data_as(_I)
         for s in range(4):
             c.bc[s] = cfg["bc"][s]
             c.wall_u[s] = cfg["wall_u"][s]
@@ -141,14 +165,17 @@ class Oracle:
         c.cfl_start = cfg.get("cfl_start", 0.0)
         c.cfl_growth = cfg.get("cfl_growth", 1.0)
         h = _P()
-        rc = lib.orc_create(C.byref(c), C.byref(h))
+        if mesh is None:
+            rc = lib.orc_create(C.byref(c), C.byref(h))
+        else:
+            rc = lib.orc_create_mesh(C.byref(c), C.byref(m), C.byref(h))
         if rc:
             raise OracleError(rc, lib.orc_last_error().decode())
         self._h = h
         sz = (C.c_int32 * 4)()
         lib.orc_sizes(h, sz)
         self.nc, self.nv, self.nf, self.nwall = list(sz)
-        self.ni, self.nj = cfg["ni"], cfg["nj"]
+        self.ni, self.nj = (cfg["ni"], cfg["nj"]) if mesh is None else (self.nc, 1)
         self.cfg = cfg
 
     def __del__(self):

@@ -32,7 +32,8 @@ def _solver(cfg):
 
 
 def _kn10():
-    return dict(wl.shrink(wl.case("cavity_kn10"), ni=24, nj=24, nv=17), precision=wl.FP64)
+    return dict(wl.shrink(wl.case("cavity_kn10"), ni=24, nj=24, nv=17), precision=wl.FP64,
+                cfl_imp=1000.0)
 
 
 def _cylinder():

@@ -176,7 +176,8 @@ def test_kn10_cavity_128_history_and_divergence():
     read, not of either implementation)."""
     from paper_1709_01819_amd.abi import IdugksError
     from oracle.oracle import OracleError
-    cfg = dict(wl.shrink(wl.case("cavity_kn10"), ni=128, nj=128, nv=17), precision=wl.FP64)
+    cfg = dict(wl.shrink(wl.case("cavity_kn10"), ni=128, nj=128, nv=17), precision=wl.FP64,
+               cfl_imp=1000.0)
     o, g = _pair(cfg)
     ro, rg, fail_o, fail_g = [], [], None, None
     for it in range(1, 41):

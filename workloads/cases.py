@@ -161,8 +161,11 @@ def _c2(precision=FP64):
 
 
 def _c3(precision=FP32_MIXED):
+    # the paper's CFL of 1000 is stable for this case up to a 64^2 mesh (its own has 60^2
+    # cells); on 96^2 and 128^2 the second-order residual against the first-order implicit
+    # operator diverges there, so the 128^2 workload runs at 100
     return cavity(n=128, stretch=None, nv=101, quad=NEWTON_COTES, vmax=4.0, Kn=10.0,
-                  model=SHAKHOV, Pr=2.0 / 3.0, K=1, cfl_imp=1000.0, precision=precision)
+                  model=SHAKHOV, Pr=2.0 / 3.0, K=1, cfl_imp=100.0, precision=precision)
 
 
 def _c4(precision=FP32_MIXED):
@@ -183,7 +186,7 @@ def _c6(precision=FP64):
 _CASES = {
     "couette": _c1,           # Couette flow, 64 cells, GH 16x16, Kn = 0.1
     "cavity_kn0.075": _c2,    # cavity 64^2 tanh, GH 28x28, Kn = 0.075
-    "cavity_kn10": _c3,       # cavity 128^2, NC 101x101 on [-4,4]^2, Shakhov, Kn = 10
+    "cavity_kn10": _c3,       # cavity 128^2, NC 101x101 on [-4,4]^2, Shakhov, Kn = 10, CFL 100
     "cylinder_ma5": _c4,      # O-grid 96x160, NC 100x100 on [-15,15]^2, Shakhov, Ma = 5
     "cavity_kn1": _c5,        # cavity 64^2 tanh, GH 28x28, Kn = 1 (sensitivities)
     "cavity_re1000": _c6,     # cavity 256^2 uniform, NC 17x17 on +-2.5 sqrt(3/2), Re = 1000
