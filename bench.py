@@ -65,6 +65,9 @@ def parse():
                     help="a second, small workload measured in FP64 beside the headline one; it "
                          "also carries the time-to-residual and explicit-vs-implicit runs "
                          "(empty: none)")
+    ap.add_argument("--unstructured", default="cavity_kn10_hybrid",
+                    help="a workload on an unstructured mesh measured like the headline one, in "
+                         "the same precision (empty: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cpu-one-thread", action="store_true",
                     help="skip the single-thread oracle iteration of the CPU baseline")
@@ -290,7 +293,7 @@ def cpu_baseline(cfg, nc, nv, budget_s=15.0, iters=0, one_thread=True):
     except (OSError, StopIteration):
         pass
     out = {"value": nc * nv / dt, "unit": "cell·vel/s", "cores": threads, "kind": "oracle",
-           "sample": f"{how} (after 1 untimed) of the same {cfg['ni']}x{cfg['nj']} x "
+           "sample": f"{how} (after 1 untimed) of the same {mesh_text(cfg)} x "
                      f"{nv}-velocity problem from its uniform initial state, FP64, OpenMP over "
                      f"independent cells/velocities",
            "s_per_iter": dt, "cpu_model": model}
@@ -351,7 +354,7 @@ def measure(cfg, workload, precision, steps, warmup):
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(tag, dom),
                 "algorithmic_bytes_per_launch": per_launch_bytes}
-    if dom == "macro_lusgs":
+    if dom == "macro_lusgs" and cfg.get("mesh") is None and not cfg.get("graph_sweeps"):
         steps_dep = 2 * (cfg["ni"] + cfg["nj"] - 1)
         roofline["note"] = ("one workgroup sweeps 2 x (ni+nj-1) dependent hyperplane steps: "
                             "bound by the step latency, not by bandwidth")
@@ -371,8 +374,16 @@ def measure(cfg, workload, precision, steps, warmup):
             "kernels_ms": {k: round(v["ms_avg"], 5) for k, v in kernels.items()}}
 
 
+def mesh_text(cfg):
+    m = cfg.get("mesh")
+    if m is None:
+        return f"{cfg['ni']}x{cfg['nj']} cells"
+    ntri = int((m["cell_nodes"][:, 3] < 0).sum())
+    return f"{len(m['cell_nodes'])} cells ({ntri} triangles, level-scheduled sweeps)"
+
+
 def describe(workload, cfg, precision):
-    return (f"{workload}: {cfg['ni']}x{cfg['nj']} cells, {cfg['nvx']}x{cfg['nvy']} velocities, "
+    return (f"{workload}: {mesh_text(cfg)}, {cfg['nvx']}x{cfg['nvy']} velocities, "
             f"{'Shakhov' if cfg['model'] == 1 else 'BGK'}, Kn={cfg['Kn']}, CFL={cfg['cfl_imp']}, "
             f"{'FP64' if precision == 'fp64' else 'FP32-mixed'}")
 
@@ -411,6 +422,18 @@ def main():
            "roofline": head["roofline"], "streaming_kernels": head["streaming_kernels"],
            # means of a separate K-iteration pass with events around every kernel
            "kernels_ms": head["kernels_ms"]}
+    # the same physics on a hybrid quadrilateral/triangle mesh (level-scheduled sweeps)
+    if args.unstructured and args.unstructured != args.workload:
+        uc = case_cfg(args.unstructured, prec)
+        um = measure(uc, args.unstructured, args.precision, args.steps, args.warmup)
+        print(f"unstructured {args.unstructured} {args.precision}: {um['ms_per_step']:.3f} ms per "
+              f"iteration", file=sys.stderr, flush=True)
+        out["unstructured"] = {"workload": describe(args.unstructured, uc, args.precision),
+                               "value": um["value"], "unit": "cell·vel/s",
+                               "ms_per_step": um["ms_per_step"], "cells": um["cells"],
+                               "velocities": um["velocities"], "roofline": um["roofline"],
+                               "streaming_kernels": um["streaming_kernels"],
+                               "kernels_ms": um["kernels_ms"]}
     # the small benchmark-style cavity (cache resident and latency bound) beside it
     if args.secondary and args.secondary != args.workload:
         sec_prec = wl.FP64

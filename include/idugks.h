@@ -91,6 +91,23 @@ typedef struct {
                                     min(cfl_imp, cfl_start * cfl_growth^n); 0 = no ramp.
                                     The adjoint iteration keeps cfl_imp. */
     double cfl_growth;           /* ramp factor per implicit iteration, 1 <= g < 1000 */
+    /* Unstructured mesh of quadrilaterals and triangles (the finite-volume form of
+       Section 2.1 sums over the faces of any cell; Section 3 runs hybrid meshes).  With
+       cell_nodes != NULL the mesh is this one, ni and nj are ignored and xn, yn hold nnodes
+       node coordinates.  cell_nodes [ncells][4] (host, read during init): the nodes of each
+       cell counter-clockwise, -1 in the fourth slot of a triangle; side s of a cell is the
+       edge from its node s to the next.  side_tag [ncells][4] (host): on a side that lies on
+       the boundary, which of the four boundary conditions (bc[t], wall_*[t], far_*) applies,
+       t = 0..3 (periodic ones are refused); ignored elsewhere.  An edge belongs to at most
+       two cells.  The implicit sweeps take the cells in index order (Eq. 24-26, Eq. 29-31),
+       level by level of that order's dependency graph.  Sensitivities (idugks_vjp,
+       idugks_objective, idugks_adjoint) are not available on such meshes. */
+    int32_t nnodes, ncells;
+    const int32_t *cell_nodes, *side_tag;
+    int32_t graph_sweeps;        /* structured meshes: 1 runs the level-scheduled sweeps of
+                                    unstructured meshes instead of the i+j hyperplane sweeps
+                                    (the same cell order, hence the same result); unstructured
+                                    meshes always use them */
 } idugks_config;
 
 typedef struct {

@@ -37,6 +37,9 @@ class Config(C.Structure):
         ("init_rho", C.c_double), ("init_u", C.c_double), ("init_v", C.c_double),
         ("init_T", C.c_double), ("predictor", C.c_int32), ("relax_sweeps", C.c_int32),
         ("cfl_start", C.c_double), ("cfl_growth", C.c_double),
+        ("nnodes", C.c_int32), ("ncells", C.c_int32),
+        ("cell_nodes", C.POINTER(C.c_int32)), ("side_tag", C.POINTER(C.c_int32)),
+        ("graph_sweeps", C.c_int32),
     ]
 
 
@@ -110,13 +113,31 @@ def load_library():
 
 
 def make_config(cfg):
-    """Build the C struct from a config dict; returns (struct, keep-alive arrays)."""
+    """Build the C struct from a config dict; returns (struct, keep-alive arrays).
+
+    A "mesh" entry (xn, yn, cell_nodes [nc, 4], side_tag [nc, 4]) selects an unstructured
+    mesh; "graph_sweeps" (0/1) the level-scheduled sweeps on a structured one."""
     import numpy as np
-    xn = np.ascontiguousarray(cfg["xn"], dtype=np.float64)
-    yn = np.ascontiguousarray(cfg["yn"], dtype=np.float64)
+    mesh = cfg.get("mesh")
+    src = cfg if mesh is None else mesh
+    xn = np.ascontiguousarray(src["xn"], dtype=np.float64)
+    yn = np.ascontiguousarray(src["yn"], dtype=np.float64)
     c = Config()
     c.struct_size = C.sizeof(Config)
-    c.ni, c.nj = cfg["ni"], cfg["nj"]
+    keep = [xn, yn]
+    if mesh is None:
+        c.ni, c.nj = cfg["ni"], cfg["nj"]
+    else:
+        cn = np.ascontiguousarray(mesh["cell_nodes"], dtype=np.int32)
+        tg = np.ascontiguousarray(mesh["side_tag"], dtype=np.int32)
+        if cn.ndim != 2 or cn.shape[1] != 4 or tg.shape != cn.shape:
+            raise ValueError("cell_nodes and side_tag must both be [ncells, 4]")
+        c.ni, c.nj = 0, 0
+        c.nnodes, c.ncells = len(xn), cn.shape[0]
+        c.cell_nodes = cn.ctypes.data_as(C.POINTER(C.c_int32))
+        c.side_tag = tg.ctypes.data_as(C.POINTER(C.c_int32))
+        keep += [cn, tg]
+    c.graph_sweeps = int(cfg.get("graph_sweeps", 0))
     c.xn, c.yn = xn.ctypes.data_as(_D), yn.ctypes.data_as(_D)
     for s in range(4):
         c.bc[s] = cfg["bc"][s]
@@ -131,7 +152,7 @@ def make_config(cfg):
     c.relax_sweeps = cfg.get("relax_sweeps", 0)
     c.cfl_start = cfg.get("cfl_start", 0.0)
     c.cfl_growth = cfg.get("cfl_growth", 1.0)
-    return c, (xn, yn)
+    return c, tuple(keep)
 
 
 def describe(cfg):
@@ -139,7 +160,8 @@ def describe(cfg):
     import numpy as np
     lib = load_library()
     c, keep = make_config(cfg)
-    nv, nc = cfg["nvx"] * cfg["nvy"], cfg["ni"] * cfg["nj"]
+    nv = cfg["nvx"] * cfg["nvy"]
+    nc = cfg["ni"] * cfg["nj"] if cfg.get("mesh") is None else len(cfg["mesh"]["cell_nodes"])
     out = {k: np.zeros(nv) for k in ("xi", "eta", "w")}
     out["dt"] = np.zeros(1)
     out["area"] = np.zeros(nc)

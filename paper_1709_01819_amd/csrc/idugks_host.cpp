@@ -179,11 +179,23 @@ namespace {
 idugks_status validate(const idugks_config *c) {
     if (!c) return fail(IDUGKS_E_INVALID, "null config");
     if (c->struct_size != sizeof(idugks_config)) return fail(IDUGKS_E_INVALID, "struct_size mismatch");
-    if (c->ni < 1 || c->nj < 1) return fail(IDUGKS_E_INVALID, "mesh needs ni, nj >= 1");
-    const bool per_i = c->bc[0] == IDUGKS_BC_PERIODIC, per_j = c->bc[2] == IDUGKS_BC_PERIODIC;
-    if (std::min(c->ni, c->nj) > 280 || macro_shape(c->ni, c->nj, per_i, per_j).lds > 150 * 1024 ||
-        macro_shape(c->ni, c->nj, per_i, per_j).threads > 1024 || sweep_shape(c->ni, c->nj, 1, 8).vb == 0)
-        return fail(IDUGKS_E_INVALID, "mesh too large for the LDS-resident sweep fronts");
+    const bool um = c->cell_nodes != nullptr;
+    if (c->graph_sweeps != 0 && c->graph_sweeps != 1) return fail(IDUGKS_E_INVALID, "graph_sweeps must be 0 or 1");
+    if (um) {
+        if (c->ncells < 1 || c->nnodes < 3 || !c->side_tag)
+            return fail(IDUGKS_E_INVALID, "unstructured mesh needs ncells >= 1, nnodes >= 3 and side_tag");
+        for (int s = 0; s < 4; ++s)
+            if (c->bc[s] == IDUGKS_BC_PERIODIC)
+                return fail(IDUGKS_E_INVALID, "no periodic boundary conditions on an unstructured mesh");
+    } else {
+        if (c->ni < 1 || c->nj < 1) return fail(IDUGKS_E_INVALID, "mesh needs ni, nj >= 1");
+        if ((int64_t)c->ni * c->nj >= ((int64_t)1 << 31)) return fail(IDUGKS_E_INVALID, "too many cells");
+        const bool per_i = c->bc[0] == IDUGKS_BC_PERIODIC, per_j = c->bc[2] == IDUGKS_BC_PERIODIC;
+        if (!c->graph_sweeps &&
+            (std::min(c->ni, c->nj) > 280 || macro_shape(c->ni, c->nj, per_i, per_j).lds > 150 * 1024 ||
+             macro_shape(c->ni, c->nj, per_i, per_j).threads > 1024 || sweep_shape(c->ni, c->nj, 1, 8).vb == 0))
+            return fail(IDUGKS_E_INVALID, "mesh too large for the LDS-resident sweep fronts (graph_sweeps = 1 has no such limit)");
+    }
     if (!c->xn || !c->yn) return fail(IDUGKS_E_INVALID, "missing node coordinates");
     if (c->predictor != 0 && c->predictor != 1) return fail(IDUGKS_E_INVALID, "unknown predictor");
     if (c->relax_sweeps < 0 || c->relax_sweeps > 64)
@@ -195,7 +207,8 @@ idugks_status validate(const idugks_config *c) {
     {
         // the sweeps index the state [nc][2][nvp] with 32-bit element offsets
         const int64_t nv = (int64_t)c->nvx * c->nvy, nvp = (nv + VPAD - 1) / VPAD * VPAD;
-        if ((int64_t)c->ni * c->nj * 2 * nvp >= ((int64_t)1 << 31))
+        const int64_t nc = um ? (int64_t)c->ncells : (int64_t)c->ni * c->nj;
+        if (nc * 2 * nvp >= ((int64_t)1 << 31))
             return fail(IDUGKS_E_INVALID, "state too large (nc x 2 x padded nv must stay below 2^31)");
     }
     if (!(c->Kn > 0)) return fail(IDUGKS_E_INVALID, "Kn must be positive");
@@ -217,8 +230,8 @@ idugks_status validate(const idugks_config *c) {
     if ((c->bc[0] == IDUGKS_BC_PERIODIC) != (c->bc[1] == IDUGKS_BC_PERIODIC) ||
         (c->bc[2] == IDUGKS_BC_PERIODIC) != (c->bc[3] == IDUGKS_BC_PERIODIC))
         return fail(IDUGKS_E_INVALID, "periodic sides must come in pairs");
-    if (c->bc[0] == IDUGKS_BC_PERIODIC && c->ni == 2) return fail(IDUGKS_E_INVALID, "periodic ni must be 1 or >= 3");
-    if (c->bc[2] == IDUGKS_BC_PERIODIC && c->nj == 2) return fail(IDUGKS_E_INVALID, "periodic nj must be 1 or >= 3");
+    if (!um && c->bc[0] == IDUGKS_BC_PERIODIC && c->ni == 2) return fail(IDUGKS_E_INVALID, "periodic ni must be 1 or >= 3");
+    if (!um && c->bc[2] == IDUGKS_BC_PERIODIC && c->nj == 2) return fail(IDUGKS_E_INVALID, "periodic nj must be 1 or >= 3");
     for (int s = 0; s < 4; ++s) {
         if (c->bc[s] == IDUGKS_BC_WALL && !(c->wall_T[s] > 0)) return fail(IDUGKS_E_INVALID, "wall T must be positive");
         if (c->bc[s] == IDUGKS_BC_FARFIELD && (!(c->far_rho > 0) || !(c->far_T > 0)))
@@ -237,7 +250,9 @@ struct Built {
     std::vector<int16_t> vix, viy;
     std::vector<double> area, xc, yc;
     std::vector<CellSide> cs;
-    std::vector<int> hp_off, hp_pos;
+    std::vector<int> hp_off, hp_pos;  // hyperplanes (structured) or levels (graph sweeps)
+    int nlev;
+    std::vector<int> gcell, gnb;      // per position: cell, neighbour cell of each side
     std::vector<double> sgeo;
     std::vector<Face> faces;
     std::vector<int> wall_faces;
@@ -335,34 +350,9 @@ void raw12(const Built &b, const double *G, const double *H, const std::vector<c
     }
 }
 
-idugks_status build(const idugks_config *c, Built &b) {
+// Structured mesh: cells (i, j) -> i + j ni, faces, cell sides and the i+j hyperplane order.
+idugks_status build_structured(const idugks_config *c, Built &b) {
     const int ni = c->ni, nj = c->nj;
-    b.ni = ni;
-    b.nj = nj;
-    b.nc = ni * nj;
-    b.nvx = c->nvx;
-    b.nvy = c->nvy;
-    b.nv = c->nvx * c->nvy;
-    b.nvp = (b.nv + VPAD - 1) / VPAD * VPAD;
-    // velocity set
-    bool ok = c->quad == IDUGKS_GAUSS_HERMITE
-                  ? gauss_hermite(c->nvx, b.x1, b.wx1) && gauss_hermite(c->nvy, b.y1, b.wy1)
-                  : newton_cotes(c->nvx, c->vmax, b.x1, b.wx1) && newton_cotes(c->nvy, c->vmax, b.y1, b.wy1);
-    if (!ok) return fail(IDUGKS_E_INVALID, "quadrature construction failed");
-    b.xi.assign(b.nvp, 0.0);
-    b.eta.assign(b.nvp, 0.0);
-    b.w.assign(b.nvp, 0.0);
-    b.vix.assign(b.nvp, 0);
-    b.viy.assign(b.nvp, 0);
-    for (int ix = 0; ix < b.nvx; ++ix)
-        for (int iy = 0; iy < b.nvy; ++iy) {
-            const int v = ix * b.nvy + iy;
-            b.xi[v] = b.x1[ix];
-            b.eta[v] = b.y1[iy];
-            b.w[v] = b.wx1[ix] * b.wy1[iy];
-            b.vix[v] = (int16_t)ix;
-            b.viy[v] = (int16_t)iy;
-        }
     // cells: shoelace area and centroid
     auto X = [&](int i, int j) { return c->xn[i + j * (ni + 1)]; };
     auto Y = [&](int i, int j) { return c->yn[i + j * (ni + 1)]; };
@@ -505,7 +495,7 @@ idugks_status build(const idugks_config *c, Built &b) {
                 q.ay = (a11 * q.ndy - a12 * q.ndx) / det;
             }
         }
-    // i+j hyperplane ordering of the cells and the static sweep geometry in that order
+    // i+j hyperplane ordering of the cells (the levels of the sweeps' dependency graph)
     const int nh = ni + nj - 1;
     b.hp_off.assign(nh + 1, 0);
     b.hp_pos.assign(b.nc, 0);
@@ -514,6 +504,223 @@ idugks_status build(const idugks_config *c, Built &b) {
         const int lo = std::max(0, s - nj + 1), hi = std::min(ni - 1, s);
         for (int i = lo; i <= hi; ++i) b.hp_pos[i + (s - i) * ni] = pos++;
         b.hp_off[s + 1] = pos;
+    }
+    b.nlev = nh;
+    return IDUGKS_OK;
+}
+
+// Unstructured mesh of quadrilaterals and triangles: cells from their nodes, faces from
+// the edges two cells share (the lower cell index is L; faces numbered by their sorted
+// node pair) or that lie on the boundary (tagged with a boundary-condition slot), one
+// zero-length face of type FT_SELF at the end for the absent fourth side of every
+// triangle, and the levels of the sweep order (cell index order): a cell's level is one
+// more than the highest level of the lower-indexed neighbours it couples to.
+idugks_status build_unstructured(const idugks_config *c, Built &b) {
+    const int nc = c->ncells, nn = c->nnodes;
+    const int32_t *cn = c->cell_nodes, *tag = c->side_tag;
+    auto corners = [&](int cell) { return cn[4 * cell + 3] < 0 ? 3 : 4; };
+    auto node = [&](int cell, int k) { return cn[4 * cell + k % corners(cell)]; };
+    b.area.resize(nc);
+    b.xc.resize(nc);
+    b.yc.resize(nc);
+    for (int cell = 0; cell < nc; ++cell) {
+        if (cn[4 * cell + 3] < -1) return fail(IDUGKS_E_INVALID, "bad fourth node (use -1 for a triangle)");
+        double a = 0, sx = 0, sy = 0;
+        for (int k = 0; k < corners(cell); ++k) {
+            const int i0 = node(cell, k), i1 = node(cell, k + 1);
+            if (i0 < 0 || i0 >= nn || i1 < 0 || i1 >= nn) return fail(IDUGKS_E_INVALID, "node index out of range");
+            const double cr = c->xn[i0] * c->yn[i1] - c->xn[i1] * c->yn[i0];
+            a += cr;
+            sx += (c->xn[i0] + c->xn[i1]) * cr;
+            sy += (c->yn[i0] + c->yn[i1]) * cr;
+        }
+        a *= 0.5;
+        if (!(a > 0)) return fail(IDUGKS_E_INVALID, "non-positive cell area (cells must be counter-clockwise)");
+        b.area[cell] = a;
+        b.xc[cell] = sx / (6.0 * a);
+        b.yc[cell] = sy / (6.0 * a);
+    }
+    // edges keyed by their sorted node pair, then the cell and side
+    struct Edge { int a, b, cell, side; };
+    std::vector<Edge> e;
+    e.reserve((size_t)4 * nc);
+    for (int cell = 0; cell < nc; ++cell)
+        for (int k = 0; k < corners(cell); ++k) {
+            const int i0 = node(cell, k), i1 = node(cell, k + 1);
+            if (i0 == i1) return fail(IDUGKS_E_INVALID, "degenerate edge");
+            e.push_back(Edge{std::min(i0, i1), std::max(i0, i1), cell, k});
+        }
+    std::sort(e.begin(), e.end(), [](const Edge &u, const Edge &v) {
+        if (u.a != v.a) return u.a < v.a;
+        if (u.b != v.b) return u.b < v.b;
+        if (u.cell != v.cell) return u.cell < v.cell;
+        return u.side < v.side;
+    });
+    b.cs.assign((size_t)4 * nc, CellSide{});
+    b.faces.clear();
+    b.closed = 1;
+    for (int t = 0; t < 4; ++t)
+        if (c->bc[t] == IDUGKS_BC_FARFIELD) b.closed = 0;
+    // the cell's own counter-clockwise edge of side k: outward normal, length, midpoint
+    auto side_geo = [&](int cell, int k, CellSide &q) {
+        const int i0 = node(cell, k), i1 = node(cell, k + 1);
+        const double tx = c->xn[i1] - c->xn[i0], ty = c->yn[i1] - c->yn[i0], S = sqrt(tx * tx + ty * ty);
+        q.nx = ty / S;
+        q.ny = -tx / S;
+        q.S = S;
+        q.dx = 0.5 * (c->xn[i0] + c->xn[i1]) - b.xc[cell];
+        q.dy = 0.5 * (c->yn[i0] + c->yn[i1]) - b.yc[cell];
+    };
+    for (size_t i = 0; i < e.size();) {
+        size_t j = i + 1;
+        while (j < e.size() && e[j].a == e[i].a && e[j].b == e[i].b) ++j;
+        if (j - i > 2) return fail(IDUGKS_E_INVALID, "an edge shared by more than two cells");
+        const int k = (int)b.faces.size();
+        const Edge &L = e[i];
+        CellSide &qL = b.cs[(size_t)4 * L.cell + L.side];
+        side_geo(L.cell, L.side, qL);
+        Face F{};
+        F.L = L.cell;
+        F.sL = L.side;
+        F.nx = qL.nx;
+        F.ny = qL.ny;
+        F.S = qL.S;
+        qL.face = k;
+        if (j - i == 2) {
+            const Edge &R = e[i + 1];
+            if (R.cell == L.cell) return fail(IDUGKS_E_INVALID, "a cell sharing an edge with itself");
+            CellSide &qR = b.cs[(size_t)4 * R.cell + R.side];
+            side_geo(R.cell, R.side, qR);
+            F.R = R.cell;
+            F.sR = R.side;
+            F.type = FT_INTERIOR;
+            F.wside = -1;
+            qR.face = k;
+            qL.type = qR.type = FT_INTERIOR;
+            qL.nb = R.cell;
+            qR.nb = L.cell;
+            qL.ndx = b.xc[R.cell] - b.xc[L.cell];
+            qL.ndy = b.yc[R.cell] - b.yc[L.cell];
+            qR.ndx = -qL.ndx;
+            qR.ndy = -qL.ndy;
+            qL.tie = 0;
+            qR.tie = 1;  // the R end is upwind for xi.n = 0
+            qL.wside = qR.wside = 0;
+        } else {
+            const int t = tag[4 * L.cell + L.side];
+            if (t < 0 || t > 3) return fail(IDUGKS_E_INVALID, "boundary side without a tag 0..3");
+            F.R = -1;
+            F.sR = -1;
+            F.type = c->bc[t] == IDUGKS_BC_WALL ? FT_WALL : FT_FAR;
+            F.wside = t;
+            qL.type = F.type;
+            qL.nb = -1;
+            qL.tie = F.type == FT_FAR ? 1 : 0;
+            qL.wside = t;
+        }
+        b.faces.push_back(F);
+        i = j;
+    }
+    // the absent fourth side of the triangles
+    {
+        const int k = (int)b.faces.size();
+        Face F{};
+        F.L = F.R = 0;
+        F.sL = F.sR = 3;
+        F.type = FT_SELF;
+        F.wside = -1;
+        b.faces.push_back(F);
+        for (int cell = 0; cell < nc; ++cell) {
+            if (corners(cell) == 4) continue;
+            CellSide &q = b.cs[(size_t)4 * cell + 3];
+            q = CellSide{};
+            q.nb = -1;
+            q.face = k;
+            q.type = FT_SELF;
+        }
+    }
+    b.nf = (int)b.faces.size();
+    // least-squares weights (Eq. 15)
+    for (int cell = 0; cell < nc; ++cell) {
+        double a11 = 0, a12 = 0, a22 = 0;
+        for (int sd = 0; sd < 4; ++sd) {
+            const CellSide &q = b.cs[(size_t)4 * cell + sd];
+            if (q.nb < 0) continue;
+            a11 += q.ndx * q.ndx; a12 += q.ndx * q.ndy; a22 += q.ndy * q.ndy;
+        }
+        const double det = a11 * a22 - a12 * a12;
+        if (!(det > 0)) return fail(IDUGKS_E_INVALID, "degenerate least-squares stencil");
+        for (int sd = 0; sd < 4; ++sd) {
+            CellSide &q = b.cs[(size_t)4 * cell + sd];
+            if (q.nb < 0) continue;
+            q.ax = (a22 * q.ndx - a12 * q.ndy) / det;
+            q.ay = (a11 * q.ndy - a12 * q.ndx) / det;
+        }
+    }
+    // levels of the sweep order and the positions (by level, then cell index)
+    std::vector<int> lev(nc, 0);
+    int nlev = 0;
+    for (int cell = 0; cell < nc; ++cell) {
+        int l = 0;
+        for (int sd = 0; sd < 4; ++sd) {
+            const CellSide &q = b.cs[(size_t)4 * cell + sd];
+            if (q.type != FT_SELF && q.nb >= 0 && q.nb < cell) l = std::max(l, lev[q.nb] + 1);
+        }
+        lev[cell] = l;
+        nlev = std::max(nlev, l + 1);
+    }
+    b.nlev = nlev;
+    b.hp_off.assign(nlev + 1, 0);
+    for (int cell = 0; cell < nc; ++cell) ++b.hp_off[lev[cell] + 1];
+    for (int l = 0; l < nlev; ++l) b.hp_off[l + 1] += b.hp_off[l];
+    b.hp_pos.assign(nc, 0);
+    std::vector<int> fill(b.hp_off.begin(), b.hp_off.end() - 1);
+    for (int cell = 0; cell < nc; ++cell) b.hp_pos[cell] = fill[lev[cell]]++;
+    return IDUGKS_OK;
+}
+
+idugks_status build(const idugks_config *c, Built &b) {
+    const bool um = c->cell_nodes != nullptr;
+    b.ni = um ? c->ncells : c->ni;
+    b.nj = um ? 1 : c->nj;
+    b.nc = b.ni * b.nj;
+    b.nvx = c->nvx;
+    b.nvy = c->nvy;
+    b.nv = c->nvx * c->nvy;
+    b.nvp = (b.nv + VPAD - 1) / VPAD * VPAD;
+    // velocity set
+    bool ok = c->quad == IDUGKS_GAUSS_HERMITE
+                  ? gauss_hermite(c->nvx, b.x1, b.wx1) && gauss_hermite(c->nvy, b.y1, b.wy1)
+                  : newton_cotes(c->nvx, c->vmax, b.x1, b.wx1) && newton_cotes(c->nvy, c->vmax, b.y1, b.wy1);
+    if (!ok) return fail(IDUGKS_E_INVALID, "quadrature construction failed");
+    b.xi.assign(b.nvp, 0.0);
+    b.eta.assign(b.nvp, 0.0);
+    b.w.assign(b.nvp, 0.0);
+    b.vix.assign(b.nvp, 0);
+    b.viy.assign(b.nvp, 0);
+    for (int ix = 0; ix < b.nvx; ++ix)
+        for (int iy = 0; iy < b.nvy; ++iy) {
+            const int v = ix * b.nvy + iy;
+            b.xi[v] = b.x1[ix];
+            b.eta[v] = b.y1[iy];
+            b.w[v] = b.wx1[ix] * b.wy1[iy];
+            b.vix[v] = (int16_t)ix;
+            b.viy[v] = (int16_t)iy;
+        }
+    const idugks_status gs = um ? build_unstructured(c, b) : build_structured(c, b);
+    if (gs != IDUGKS_OK) return gs;
+    // per position of the sweep order: the cell, and per side the neighbour cell, or
+    // -1 - t on a boundary side with boundary-condition slot t, or the cell itself (a side
+    // without flux)
+    b.gcell.assign(b.nc, 0);
+    b.gnb.assign((size_t)4 * b.nc, 0);
+    for (int cidx = 0; cidx < b.nc; ++cidx) {
+        const int pos = b.hp_pos[cidx];
+        b.gcell[pos] = cidx;
+        for (int sd = 0; sd < 4; ++sd) {
+            const CellSide &q = b.cs[(size_t)4 * cidx + sd];
+            b.gnb[(size_t)4 * pos + sd] = q.type == FT_SELF ? cidx : q.nb >= 0 ? q.nb : -1 - q.wside;
+        }
     }
     b.sgeo.assign((size_t)b.nc * SG_N, 0.0);
     for (int cidx = 0; cidx < b.nc; ++cidx)
@@ -537,6 +744,7 @@ idugks_status build(const idugks_config *c, Built &b) {
         double d = 1e300;
         for (int s = 0; s < 4; ++s) {
             const CellSide &q = b.cs[(size_t)4 * cidx + s];
+            if (q.S == 0.0) continue;  // the absent side of a triangle
             d = std::min(d, fabs(q.dx * q.nx + q.dy * q.ny));
         }
         hmin = std::min(hmin, 2.0 * d);
@@ -621,12 +829,19 @@ enum Region {
     R_STAGE, R_HPOFF, R_HPPOS, R_SGEO, R_SREC, R_SDRHO, R_MH, R_FV, R_MWC, R_RECT, R_RECFT,
     // sensitivities (empty unless BGK, no limiter, FP64)
     R_LT, R_GJ, R_FBAR, R_YBUF, R_AGR, R_FADJ, R_CADJ, R_DGW, R_DWDEN, R_JACC, R_JACF, R_RED,
-    R_ADJS, R_DWR, R_COUNT
+    R_ADJS, R_DWR, R_GCELL, R_GNB, R_COUNT
 };
 
 // Sensitivities are available for BGK without limiter in the FP64 form.
 bool adjoint_capable(const idugks_config *c) {
-    return c->model == IDUGKS_BGK && c->limiter == 0 && c->precision == IDUGKS_FP64;
+    return c->model == IDUGKS_BGK && c->limiter == 0 && c->precision == IDUGKS_FP64 && !c->cell_nodes &&
+           !c->graph_sweeps;
+}
+
+// Wall faces the layout provides for: all boundary faces of a structured mesh, the built
+// count on an unstructured one (idugks_workspace_size and init use the same bound).
+int wall_bound(const idugks_config *c, const Built &b) {
+    return c->cell_nodes ? b.nwall : 2 * (c->ni + c->nj);
 }
 
 constexpr int ADJS_N = 16;  // device scalars: [0..3] theta-bar, J of the last product;
@@ -637,7 +852,7 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
     const size_t S = c->precision == IDUGKS_FP32_MIXED ? 4 : 8, TW = (size_t)nvx + nvy;
     // rows of the hyperplane-ordered sweep arrays: the staging waves read whole passes past
     // the last cell of a hyperplane, so these arrays carry min(ni, nj) + HP_SPARE spare rows
-    const size_t ncs = (size_t)nc + std::min(c->ni, c->nj) + HP_SPARE;
+    const size_t ncs = (size_t)nc + (c->cell_nodes ? 1 : std::min(c->ni, c->nj)) + HP_SPARE;
     const int nv = c->nvx * c->nvy, nch = (nv + vel_chunk(nv) - 1) / vel_chunk(nv);
     const size_t adj = adjoint_capable(c) ? 1 : 0;
     const size_t sizes[R_COUNT] = {
@@ -657,7 +872,7 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
         adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 6 * (size_t)nc * nvp, adj * 8 * (size_t)FA_N * nf,
         adj * 8 * (size_t)CA_N * nc, adj * 8 * 8 * (size_t)nvp, adj * 8 * 2 * (size_t)nf,
         adj * 8 * 32 * (size_t)nc, adj * 8 * 32 * (size_t)nf, adj * 8 * (size_t)RED_N, adj * 8 * ADJS_N,
-        8 * 4 * (size_t)nc};
+        8 * 4 * (size_t)nc, sizeof(int) * (size_t)nc, sizeof(int) * 4 * (size_t)nc};
     for (int r = 0; r < R_COUNT; ++r) L.add(sizes[r]);
     L.bytes = (L.bytes + 255) & ~size_t(255);
     return L;
@@ -813,6 +1028,13 @@ idugks_status idugks_workspace_size(const idugks_config *cfg, size_t *bytes) {
     if (!bytes) return fail(IDUGKS_E_INVALID, "null output");
     idugks_status s = validate(cfg);
     if (s != IDUGKS_OK) return s;
+    if (cfg->cell_nodes) {  // face and wall counts come from the mesh
+        Built b;
+        s = build(cfg, b);
+        if (s != IDUGKS_OK) return s;
+        *bytes = layout(cfg, b.nc, b.nf, b.nvp, b.nvx, b.nvy, wall_bound(cfg, b)).bytes;
+        return IDUGKS_OK;
+    }
     const int nc = cfg->ni * cfg->nj, nf = (cfg->ni + 1) * cfg->nj + cfg->ni * (cfg->nj + 1);
     const int nv = cfg->nvx * cfg->nvy, nvp = (nv + VPAD - 1) / VPAD * VPAD;
     *bytes = layout(cfg, nc, nf, nvp, cfg->nvx, cfg->nvy, 2 * (cfg->ni + cfg->nj)).bytes;
@@ -856,7 +1078,7 @@ static idugks_status init_ctx(const idugks_config *cfg, void *d_workspace, void 
     Built b;
     s = build(cfg, b);
     if (s != IDUGKS_OK) return s;
-    Layout L = layout(cfg, b.nc, b.nf, b.nvp, b.nvx, b.nvy, 2 * (cfg->ni + cfg->nj));
+    Layout L = layout(cfg, b.nc, b.nf, b.nvp, b.nvx, b.nvy, wall_bound(cfg, b));
     char *base = (char *)d_workspace;
     auto R = [&](int r) { return (void *)(base + L.off[r]); };
 
@@ -864,13 +1086,15 @@ static idugks_status init_ctx(const idugks_config *cfg, void *d_workspace, void 
     x->scratch_dev = -1;  // set by the caller once the context exists
     x->cfg = *cfg;
     x->cfg.xn = x->cfg.yn = nullptr;
+    x->cfg.cell_nodes = x->cfg.side_tag = nullptr;
     x->fp32 = cfg->precision == IDUGKS_FP32_MIXED;
     x->cfl_start = cfg->cfl_start;
     x->cfl_growth = cfg->cfl_growth;
     x->imp_iters = 0;
     x->st = (hipStream_t)hip_stream;
-    x->sweep = sweep_shape(b.ni, b.nj, b.nv, x->fp32 ? 4 : 8);
-    if (x->sweep.vb == 0) {
+    const bool graph = cfg->cell_nodes || cfg->graph_sweeps;
+    x->sweep = graph ? SweepShape{} : sweep_shape(b.ni, b.nj, b.nv, x->fp32 ? 4 : 8);
+    if (!graph && x->sweep.vb == 0) {
         delete x;
         return fail(IDUGKS_E_INVALID, "no sweep launch shape fits this mesh");
     }
@@ -908,6 +1132,7 @@ static idugks_status init_ctx(const idugks_config *cfg, void *d_workspace, void 
     p.dtimp = (double *)R(R_DTIMP); p.rho_old = (double *)R(R_RHOOLD); p.drho = (double *)R(R_DRHO);
     p.scal = (double *)R(R_SCAL);
     p.hp_off = (const int *)R(R_HPOFF); p.hp_pos = (const int *)R(R_HPPOS);
+    p.graph = graph; p.nlev = b.nlev; p.gcell = (const int *)R(R_GCELL); p.gnb = (const int *)R(R_GNB);
     p.sgeo = (const double *)R(R_SGEO); p.srec = (double *)R(R_SREC); p.sdrho = (double *)R(R_SDRHO);
     p.mh = (double *)R(R_MH); p.fv = R(R_FV); p.recT = R(R_RECT); p.recfT = R(R_RECFT);
     p.MWc = (double *)R(R_MWC);
@@ -928,6 +1153,7 @@ static idugks_status init_ctx(const idugks_config *cfg, void *d_workspace, void 
     };
     hipError_t e = hipSuccess;
 #define UP(r, vec) if (e == hipSuccess && !(vec).empty()) e = up(R(r), (vec).data(), (vec).size() * sizeof((vec)[0]))
+    UP(R_GCELL, b.gcell); UP(R_GNB, b.gnb);
     UP(R_CS, b.cs); UP(R_HPOFF, b.hp_off); UP(R_HPPOS, b.hp_pos); UP(R_SGEO, b.sgeo); UP(R_FACES, b.faces); UP(R_WALLF, b.wall_faces); UP(R_AREA, b.area);
     UP(R_XI, b.xi); UP(R_ETA, b.eta); UP(R_W, b.w); UP(R_X1, b.x1); UP(R_WX1, b.wx1);
     UP(R_Y1, b.y1); UP(R_WY1, b.wy1); UP(R_VIX, b.vix); UP(R_VIY, b.viy); UP(R_GW, b.gw);

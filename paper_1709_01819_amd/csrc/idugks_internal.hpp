@@ -24,13 +24,15 @@ constexpr int NM_SHAKHOV = 12; // + xi^2, xi eta, eta^2, xi|xi|^2, eta|xi|^2 (G)
 constexpr int NM_MAX = 12;
 constexpr int VPAD = 64;
 
-// One side (i-, i+, j-, j+) of one cell.
+// One side of one cell (i-, i+, j-, j+ on a structured mesh; the edge from node s to node
+// s+1 on an unstructured one, where the absent fourth side of a triangle has type FT_SELF,
+// no neighbour and zero length).
 struct CellSide {
     int nb;        // neighbour cell, -1 at a boundary (may be the cell itself: self-periodic)
     int face;      // face index
     int type;      // FaceType
     int tie;       // 1 if this cell is upwind for xi.n_out == 0 (R end of interior, far field)
-    int wside;     // boundary side (0..3) of wall / far-field faces
+    int wside;     // boundary-condition slot (0..3) of wall / far-field faces
     int pad0, pad1, pad2;
     double nx, ny; // outward unit normal
     double S;      // face length
@@ -128,8 +130,15 @@ struct Params {
     double *dWr;             // [nc][4] second increment buffer of the point relaxation
     // per-cell data of the sweeps stored in i+j hyperplane order (position hp_pos[c]), so
     // that the cells of one hyperplane are contiguous and can be staged into LDS at once
-    const int *hp_off;       // [nh+1] first position of each hyperplane
+    const int *hp_off;       // [nh+1] first position of each hyperplane (of each level)
     const int *hp_pos;       // [nc] position of each cell
+    // level-scheduled sweeps (unstructured meshes, or on request): the positions hold the
+    // cells level by level of the sweep order's dependency graph (hp_off has nlev + 1
+    // entries); per position the cell and per side its neighbour cell, -1 - t on a
+    // boundary side of boundary-condition slot t, or the cell itself on a side without flux
+    int graph, nlev;
+    const int *gcell;        // [nc]
+    const int *gnb;          // [nc][4]
     const double *sgeo;      // [nc][SG_N] nx S[4], ny S[4], w_lower[4], w_upper[4] (static)
     double *srec;            // [nc][SR_N] U, V, c0, c1, c2c, c3, kqx, kqy, iRT, KRT, cst, base
     double *sdrho;           // [nc][4] wall ghost density increment per cell side

@@ -6,9 +6,10 @@
 //              upwind reconstruction at the faces (Eq. 11, 13), stored per face and velocity
 //   face rec   face moments of the stored values, wall density, face equilibrium (Eq. 18)
 //   flux       interface distribution (Eq. 18), flux (Eq. 19), M_i(v) (Eq. 23), M_W (Eq. 27)
-//   macro      predicted macroscopic LU-SGS (Eq. 28-31) on i+j hyperplanes
+//   macro      predicted macroscopic LU-SGS (Eq. 28-31) on i+j hyperplanes (or levels)
 //   records*   predicted equilibrium
-//   lower      forward micro sweep of Eq. 26 over hyperplanes, all velocities in parallel
+//   lower      forward micro sweep of Eq. 26 over hyperplanes (or the levels of the sweep
+//              order's dependency graph on an unstructured mesh), all velocities in parallel
 //   ghost      wall ghost density increment from the forward sweep (Eq. 34-35)
 //   upper      backward sweep and update (Eq. 32)
 //   raw        raw moments of the new state
@@ -1460,6 +1461,139 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// micro LU-SGS sweeps (Eq. 24-26) level by level: the sweep order is the cell index order
+// and a level holds cells whose lower-indexed neighbours all lie on earlier levels, so the
+// cells of a level are independent in the forward sweep and, taken in reverse, in the
+// backward one.  This serves any mesh (unstructured ones; structured ones on request,
+// where the levels are the i+j hyperplanes).  One block per slice of 64 velocities; a wave
+// takes one cell of the level at a time (its per-cell data are wave-uniform loads, its
+// state a 64-wide row) and reads its neighbours' increments from d1, written by this block
+// on an earlier level (a block barrier separates the levels; the backward sweep also
+// leaves its increments in d1 for that).  Per cell and velocity the arithmetic is the
+// hyperplane kernel's, in the same order.
+// ---------------------------------------------------------------------------------------
+constexpr int GS_THREADS = 512;
+
+template <class S, bool SHAK, bool UPPER>
+__global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p) {
+    using T = S;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    constexpr int NW = GS_THREADS / 64;
+    const int v = xcd_remap(blockIdx.x, gridDim.x) * 64 + lane;  // < nvp (padding reads zeros)
+    const bool vok = v < p.nv;
+    const int nvp = p.nvp, nv2 = 2 * nvp, ntb = p.nvx + p.nvy;
+    const T x = (T)p.xi[v], y = (T)p.eta[v];
+    const int ix = p.vix[v], iy = p.viy[v];
+    const T sc = (T)p.scal[SC_SCALE];
+    S *d1 = (S *)p.d1, *f = (S *)p.f;
+    for (int t = 0; t < p.nlev; ++t) {
+        const int l = UPPER ? p.nlev - 1 - t : t;
+        const int end = p.hp_off[l + 1];
+        for (int pos = p.hp_off[l] + wave; pos < end; pos += NW) {
+            const int c = p.gcell[pos];
+            const double *g = p.sgeo + (size_t)pos * SG_N, *rr = p.srec + (size_t)pos * SR_N;
+            const int *nb = p.gnb + (size_t)pos * 4;
+            const size_t o = (size_t)c * nv2 + v;
+            const T aG = d1[o], aH = d1[o + nvp], bG = f[o], bH = f[o + nvp];
+            T D = (T)rr[11], sG, sH;
+            if (!UPPER) {
+                RecT<T> r;
+                r.U = (T)rr[0]; r.V = (T)rr[1]; r.c0 = (T)rr[2]; r.c1 = (T)rr[3]; r.c2c = (T)rr[4];
+                r.c3 = (T)rr[5]; r.kqx = (T)rr[6]; r.kqy = (T)rr[7]; r.iRT = (T)rr[8]; r.KRT = (T)rr[9];
+                const S *tb = (const S *)p.tabs + (size_t)c * ntb;
+                T eG, eH;
+                eq_eval<T, SHAK>(r, x, y, tb[ix] * tb[p.nvx + iy], eG, eH);
+                sG = aG - (T)rr[10] * (sc * bG - eG);
+                sH = aH - (T)rr[10] * (sc * bH - eH);
+            } else {
+                sG = sH = T(0);
+            }
+#pragma unroll
+            for (int sd = 0; sd < 4; ++sd) {
+                const T unS = x * (T)g[sd] + y * (T)g[4 + sd];  // (xi.n) S
+                const T uo = fmax(unS, T(0)), ui = fmin(unS, T(0));
+                D += uo;
+                const int j = nb[sd];
+                if (g[(UPPER ? 12 : 8) + sd] != 0.0) {  // inflow from a coupled neighbour
+                    const size_t oj = (size_t)j * nv2 + v;
+                    const T nG = d1[oj], nH = d1[oj + nvp];
+                    sG -= ui * nG;
+                    sH -= ui * nH;
+                }
+                if (UPPER && j < 0) {  // inflow through a boundary: the wall ghost's increment
+                    const int tg = -1 - j;
+                    const T gw = -(T)p.gw[(size_t)tg * nvp + v] * (T)p.sdrho[(size_t)pos * 4 + sd] * ui;
+                    sG += gw;
+                    sH += gw * (T)p.wKRT[tg];
+                }
+            }
+            const T iD = rcp_nr(D);
+            const T dG = UPPER ? aG + sG * iD : sG * iD;
+            const T dH = UPPER ? aH + sH * iD : sH * iD;
+            if (vok) {
+                d1[o] = (S)dG;
+                d1[o + nvp] = (S)dH;
+                if (UPPER) {
+                    f[o] = (S)(sc * bG + dG);
+                    f[o + nvp] = (S)(sc * bH + dH);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Macro LU-SGS sweeps (Eq. 29-31) level by level in one block: one thread per cell of a
+// level, the cell's row and its neighbours' W and sound speed from the macro rows, the
+// increments in dW (cell order; the forward sweep leaves dW* there, the backward sweep
+// reads it back and leaves dW).
+constexpr int GM_THREADS = 512;
+
+__global__ __launch_bounds__(GM_THREADS) void k_gmacro(Params p) {
+    const double ik2 = 1.0 / (p.K + 2);
+    for (int dir = 0; dir < 2; ++dir) {
+        const bool upper = dir == 1;
+        const int need = upper ? SG_UPPER : SG_LOWER;
+        for (int t = 0; t < p.nlev; ++t) {
+            const int l = upper ? p.nlev - 1 - t : t;
+            const int end = p.hp_off[l + 1];
+            for (int pos = p.hp_off[l] + (int)threadIdx.x; pos < end; pos += GM_THREADS) {
+                const int c = p.gcell[pos];
+                const double *m = p.mh + (size_t)pos * MH_N;
+                const int codes = (int)m[5];
+                double r[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int sd = 0; sd < 4; ++sd) {
+                    if (!((codes >> (MH_CODE_BITS * sd)) & need)) continue;
+                    const int j = p.gnb[(size_t)pos * 4 + sd];
+                    const double *mj = p.mh + (size_t)p.hp_pos[j] * MH_N, *dWj = p.dW + (size_t)j * 4;
+                    const double nx = m[MH_SIDE + MH_SN * sd], ny = m[MH_SIDE + MH_SN * sd + 1];
+                    const double hS = 0.5 * m[MH_SIDE + MH_SN * sd + 2];
+                    double Wj[4], Wn[4], dw[4], F0[4], F1[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        Wj[a] = mj[6 + a];
+                        dw[a] = dWj[a];
+                        Wn[a] = Wj[a] + dw[a];
+                    }
+                    const double lam = fabs(euler_flux_n(Wj, nx, ny, ik2, F0)) + mj[10];
+                    euler_flux_n(Wn, nx, ny, ik2, F1);
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) r[a] += hS * (F1[a] - F0[a] - lam * dw[a]);
+                }
+                const double iD = m[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    double *q = p.dW + (size_t)c * 4 + a;
+                    *q = upper ? *q - r[a] * iD : (m[a] - r[a]) * iD;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // wall ghost density increment of each wall face from the forward-sweep G increment
 template <class S>
 __global__ __launch_bounds__(256) void k_wall_ghost(Params p) {
@@ -2249,6 +2383,10 @@ hipError_t launch_macro_relax(const Params &p, hipStream_t st) {
 }
 
 hipError_t launch_macro(const Params &p, hipStream_t st) {
+    if (p.graph) {
+        hipLaunchKernelGGL(k_gmacro, dim3(1), dim3(GM_THREADS), 0, st, p);
+        return hipGetLastError();
+    }
     const MacroShape m = macro_shape(p.ni, p.nj, p.per_i, p.per_j);
     return m.lpc == 4 ? launch_macro_l<4>(p, m, st) : launch_macro_l<2>(p, m, st);
 }
@@ -2308,7 +2446,20 @@ static hipError_t sweep_launch_v(const Params &p, const SweepShape &sh, hipStrea
     return sweep_launch<S, SHAK, UPPER, false, 1>(p, sh, st);
 }
 
+template <class S, bool SHAK, bool UPPER>
+static hipError_t gsweep_launch(const Params &p, hipStream_t st) {
+    hipLaunchKernelGGL((k_gsweep<S, SHAK, UPPER>), dim3(p.nvp / 64), dim3(GS_THREADS), 0, st, p);
+    return hipGetLastError();
+}
+
 hipError_t launch_sweep(const Params &p, bool fp32, bool upper, const SweepShape &sh, hipStream_t st) {
+    if (p.graph) {
+        DISPATCH_S(fp32, {
+            if (p.model == 1) return upper ? gsweep_launch<S, true, true>(p, st) : gsweep_launch<S, true, false>(p, st);
+            return upper ? gsweep_launch<S, false, true>(p, st) : gsweep_launch<S, false, false>(p, st);
+        });
+        return hipSuccess;
+    }
     if (!fp32 && sh.vpl != 1) return hipErrorInvalidValue;
     DISPATCH_S(fp32, {
         if (p.model == 1) return upper ? sweep_launch_v<S, true, true>(p, sh, st) : sweep_launch_v<S, true, false>(p, sh, st);

@@ -122,6 +122,11 @@ HOST_CASES = {
     "cylinder_c4_nc": lambda: wl.shrink(wl.case("cylinder_ma5"), ni=12, nj=20, nv=100),
     "box": lambda: wl.periodic_box(n=5, nv=9),
     "gh60": lambda: wl.cavity(n=3, nv=60),
+    "hybrid_jittered": lambda: wl.hybrid_cavity(n=10, nq=2, nv=8, jitter=0.2, seed=5),
+    "hybrid_random_order": lambda: wl.with_mesh(
+        wl.cavity(n=9, stretch=1.5, nv=6), wl.renumbered(wl.hybrid_square(9, 2, jitter=0.1), 2)),
+    "structured_as_mesh": lambda: wl.with_mesh(wl.case("cavity_kn0.075"), wl.mesh_of(wl.case("cavity_kn0.075"))),
+    "hybrid_kn10_full": lambda: wl.case("cavity_kn10_hybrid"),
 }
 
 
@@ -141,3 +146,64 @@ def test_host_description_matches_oracle(name):
         assert np.max(np.abs(d[k] - sd[k])) <= 1e-13 * max(1.0, np.abs(sd[k]).max()), k
     for k in ("ax", "ay"):
         assert np.max(np.abs(d[k] - sd[k])) <= 1e-11 * np.abs(sd[k]).max(), k
+
+
+# ------------------------------------------------------------------ unstructured meshes
+def _mesh_cfg(**mesh_changes):
+    cfg = wl.hybrid_cavity(n=4, nq=1, nv=4)
+    m = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in cfg["mesh"].items()}
+    for k, f in mesh_changes.items():
+        f(m)
+    return wl.with_mesh(cfg, m)
+
+
+def _init_error(cfg):
+    lib = abi.load_library()
+    c, keep = abi.make_config(cfg)
+    h = C.c_void_p()
+    # the mesh is validated on the host; a dummy non-null workspace is never touched
+    rc = lib.idugks_init(C.byref(c), C.c_void_p(1), 1 << 40, None, C.byref(h))
+    return rc, lib.idugks_last_error().decode()
+
+
+def _set(arr, idx, val):
+    def f(m):
+        m[arr][idx] = val
+    return f
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(cell_nodes=_set("cell_nodes", (0, 1), 10 ** 6)), "node index"),
+    (dict(cell_nodes=_set("cell_nodes", (0, 3), -5)), "fourth node"),
+    (dict(side_tag=_set("side_tag", (0, 0), -1)), "tag"),
+    (dict(cell_nodes=lambda m: m.__setitem__("cell_nodes", m["cell_nodes"][:, [0, 3, 2, 1]].copy())), "area"),
+    (dict(cell_nodes=lambda m: m.__setitem__("cell_nodes", np.vstack([m["cell_nodes"], m["cell_nodes"][:1]])),
+          side_tag=lambda m: m.__setitem__("side_tag", np.vstack([m["side_tag"], m["side_tag"][:1]]))),
+     "more than two cells"),
+])
+def test_invalid_unstructured_meshes_rejected(change, msg):
+    rc, err = _init_error(_mesh_cfg(**change))
+    assert rc == 1 and msg in err
+
+
+def test_unstructured_mesh_refuses_periodic_conditions_and_bad_flags():
+    cfg = _mesh_cfg()
+    cfg["bc"] = [wl.BC_PERIODIC, wl.BC_PERIODIC, wl.BC_WALL, wl.BC_WALL]
+    rc, _, err = _size(cfg)
+    assert rc == 1 and "periodic" in err
+    rc, _, err = _size(dict(wl.case("couette"), graph_sweeps=2))
+    assert rc == 1 and "graph_sweeps" in err
+
+
+def test_level_sweeps_lift_the_structured_size_limit():
+    big = wl.cavity(n=300, nj=300, stretch=None, nv=4)
+    rc, _, err = _size(big)
+    assert rc == 1 and "graph_sweeps" in err
+    assert _size(dict(big, graph_sweeps=1))[0] == 0
+
+
+def test_unstructured_workspace_covers_its_arrays():
+    cfg = wl.case("cavity_kn10_hybrid")
+    rc, n, _ = _size(cfg)
+    nc, nvp = len(cfg["mesh"]["cell_nodes"]), 10240
+    assert rc == 0 and n >= 2 * 2 * nc * nvp * 4

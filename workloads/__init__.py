@@ -10,3 +10,4 @@ from .cases import (  # noqa: F401
     couette, cavity, cavity_re, cylinder, periodic_box, shrink, case, CASE_NAMES,
     perturbation,
 )
+from .meshes import mesh_of, with_mesh, hybrid_square, hybrid_cavity, renumbered  # noqa: F401

@@ -183,6 +183,13 @@ def _c6(precision=FP64):
     return cavity_re(Re=1000.0, n=256, nv=17, vmax=VMAX_RE, precision=precision)
 
 
+def _c7(precision=FP32_MIXED):
+    # the Kn 10 cavity on a hybrid mesh of the same 129^2 nodes: quadrilaterals in a band of
+    # 8 cells along the walls, two triangles in every other grid cell (28928 cells)
+    from .meshes import hybrid_square, with_mesh
+    return with_mesh(_c3(precision), hybrid_square(128, 8))
+
+
 _CASES = {
     "couette": _c1,           # Couette flow, 64 cells, GH 16x16, Kn = 0.1
     "cavity_kn0.075": _c2,    # cavity 64^2 tanh, GH 28x28, Kn = 0.075
@@ -190,6 +197,7 @@ _CASES = {
     "cylinder_ma5": _c4,      # O-grid 96x160, NC 100x100 on [-15,15]^2, Shakhov, Ma = 5
     "cavity_kn1": _c5,        # cavity 64^2 tanh, GH 28x28, Kn = 1 (sensitivities)
     "cavity_re1000": _c6,     # cavity 256^2 uniform, NC 17x17 on +-2.5 sqrt(3/2), Re = 1000
+    "cavity_kn10_hybrid": _c7,  # cavity_kn10 on a hybrid quad/triangle mesh, 28928 cells
 }
 CASE_NAMES = tuple(_CASES)
 
