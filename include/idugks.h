@@ -12,6 +12,8 @@
  * Conventions
  *   - structured quadrilateral mesh of ni x nj cells; cell (i, j) has index i + j*ni;
  *     node (i, j) has index i + j*(ni+1); boundary sides are ordered i-, i+, j-, j+;
+ *     or an unstructured mesh of quadrilaterals and triangles (idugks_config.cell_nodes),
+ *     whose boundary sides name one of the same four boundary-condition slots;
  *   - tensor-product discrete velocities, index v = ix*nvy + iy;
  *   - units: gas constant R = 1/2 (so T = 2RT and the reference Maxwellian is
  *     exp(-|xi|^2)/pi), Knudsen number Kn as in Eq. 37 with rho = L = 2RT_ref = 1;
@@ -153,7 +155,9 @@ idugks_status idugks_init(const idugks_config *cfg, void *d_workspace, size_t by
    IDUGKS_E_NOMEM before any device work.  All other calls work on the context as usual. */
 idugks_status idugks_init_noalloc(const idugks_config *cfg, void *hip_stream, idugks_ctx **out);
 
-/* Sizes and scalars of a context.  out: host. */
+/* Sizes and scalars of a context: cell, velocity (Section 2.2, last paragraph) and face
+   counts, the physical time step of Eq. 21 and the reference mass that the closed-domain
+   rescale holds (Section 2.3).  out: host. */
 idugks_status idugks_get_info(idugks_ctx *ctx, idugks_info *out);
 
 /* The discrete velocity set: xi, eta, weights (weight function included).  host, nv each. */
@@ -192,8 +196,10 @@ idugks_status idugks_macro_residual(idugks_ctx *ctx, double *MW, int32_t on_host
 /* Predicted macroscopic state W* [nc][4] and implicit time step [nc] (Eq. 28-31). */
 idugks_status idugks_predict(idugks_ctx *ctx, double *Wstar, double *dt_imp, int32_t on_host);
 
-/* Canonical FP64 state [2][nc][nv].  set_state makes the set state the closed-domain
-   reference mass and restarts the iteration counter. */
+/* Canonical FP64 state [2][nc][nv]: the transformed distributions G~, H~ of Eq. 10 (the
+   solver's unknowns, Eq. 21-22) per cell and discrete velocity, G~ first; f: host if
+   on_host, else device.  set_state makes the set state the closed-domain reference mass
+   and restarts the iteration counter; the FP32-mixed form rounds it to FP32. */
 idugks_status idugks_get_state(idugks_ctx *ctx, double *f, int32_t on_host);
 idugks_status idugks_set_state(idugks_ctx *ctx, const double *f, int32_t on_host);
 

@@ -23,7 +23,9 @@ def config_at(cfg, theta):
 class SteadyObjective(torch.autograd.Function):
     """J(theta) at the steady state; backward gives dJ/dtheta from one adjoint solve.
 
-    apply(theta, cfg, which, tol, max_iter, adj_tol): theta is a float64 tensor of 3."""
+    apply(theta, cfg, which, tol, max_iter, adj_tol): theta is a float64 tensor of 3.  The
+    forward pass converges the scheme and evaluates J only; the converged solver is kept
+    for the backward pass, which runs the adjoint iteration when a gradient is asked for."""
 
     @staticmethod
     def forward(ctx, theta, cfg, which, tol=1e-12, max_iter=20000, adj_tol=1e-11):
@@ -31,11 +33,17 @@ class SteadyObjective(torch.autograd.Function):
         it, res, ok = s.solve(tol, max_iter)
         if not ok:
             raise RuntimeError(f"forward solve did not converge ({it} iterations, residual {res})")
-        J, grad, _, _, _ = s.adjoint(which, adj_tol, 20 * max_iter)
-        ctx.save_for_backward(torch.as_tensor(grad, dtype=theta.dtype))
+        J, _, _ = s.objective(which)
+        ctx.solver, ctx.which, ctx.adj_tol, ctx.adj_iter = s, which, adj_tol, 20 * max_iter
+        ctx.dtype = theta.dtype
         return torch.as_tensor(J, dtype=theta.dtype)
 
     @staticmethod
     def backward(ctx, gout):
-        (grad,) = ctx.saved_tensors
-        return gout * grad, None, None, None, None, None
+        s = ctx.solver
+        ctx.solver = None  # the adjoint runs once per forward
+        grad = None
+        if ctx.needs_input_grad[0]:
+            _, g, _, _, _ = s.adjoint(ctx.which, ctx.adj_tol, ctx.adj_iter)
+            grad = gout * torch.as_tensor(g, dtype=ctx.dtype)
+        return grad, None, None, None, None, None
