@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--unstructured", default="cavity_kn10_hybrid",
                     help="a workload on an unstructured mesh measured like the headline one, in "
                          "the same precision (empty: none)")
+    ap.add_argument("--sweep-order", type=int, choices=[0, 1, 2], default=None,
+                    help="sweep_order of the structured headline workload: 0 the library's "
+                         "choice (default), 1 levels, 2 i+j hyperplanes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cpu-one-thread", action="store_true",
                     help="skip the single-thread oracle iteration of the CPU baseline")
@@ -354,7 +357,7 @@ def measure(cfg, workload, precision, steps, warmup):
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(tag, dom),
                 "algorithmic_bytes_per_launch": per_launch_bytes}
-    if dom == "macro_lusgs" and cfg.get("mesh") is None and not cfg.get("graph_sweeps"):
+    if dom == "macro_lusgs" and cfg.get("mesh") is None and cfg.get("sweep_order", 0) != 1:
         steps_dep = 2 * (cfg["ni"] + cfg["nj"] - 1)
         roofline["note"] = ("one workgroup sweeps 2 x (ni+nj-1) dependent hyperplane steps: "
                             "bound by the step latency, not by bandwidth")
@@ -408,6 +411,8 @@ def main():
 
     prec = wl.FP64 if args.precision == "fp64" else wl.FP32_MIXED
     cfg = case_cfg(args.workload, prec)
+    if args.sweep_order is not None and cfg.get("mesh") is None:
+        cfg["sweep_order"] = args.sweep_order
     head = measure(cfg, args.workload, args.precision, args.steps, args.warmup)
     print(f"headline {args.workload} {args.precision}: {head['ms_per_step']:.3f} ms per iteration",
           file=sys.stderr, flush=True)

@@ -61,6 +61,7 @@ enum { IDUGKS_GAUSS_HERMITE = 0, IDUGKS_NEWTON_COTES = 1 };
 enum { IDUGKS_BGK = 0, IDUGKS_SHAKHOV = 1 };
 enum { IDUGKS_FP64 = 0, IDUGKS_FP32_MIXED = 1 };
 enum { IDUGKS_EXPLICIT = 0, IDUGKS_IMPLICIT = 1 };
+enum { IDUGKS_SWEEPS_AUTO = 0, IDUGKS_SWEEPS_LEVELS = 1, IDUGKS_SWEEPS_HYPERPLANES = 2 };
 
 /* Problem statement (Section 2 and Section 3 of the paper). */
 typedef struct {
@@ -106,10 +107,17 @@ typedef struct {
        idugks_objective, idugks_adjoint) are not available on such meshes. */
     int32_t nnodes, ncells;
     const int32_t *cell_nodes, *side_tag;
-    int32_t graph_sweeps;        /* structured meshes: 1 runs the level-scheduled sweeps of
-                                    unstructured meshes instead of the i+j hyperplane sweeps
-                                    (the same cell order, hence the same result); unstructured
-                                    meshes always use them */
+    int32_t sweep_order;         /* how the implicit sweeps walk the cell order (the same
+                                    order, hence the same result up to rounding):
+                                    IDUGKS_SWEEPS_AUTO (0) the library's choice: on structured
+                                    meshes the micro sweeps by levels for at least 8192
+                                    velocities (or where the hyperplane shape does not fit),
+                                    else by i+j hyperplanes, and the macro sweep by
+                                    hyperplanes where it fits; IDUGKS_SWEEPS_LEVELS (1) both by
+                                    levels of the order's dependency graph;
+                                    IDUGKS_SWEEPS_HYPERPLANES (2) both by i+j hyperplanes
+                                    (structured meshes that fit the LDS-resident fronts).
+                                    Unstructured meshes take AUTO or LEVELS (both by levels). */
 } idugks_config;
 
 typedef struct {

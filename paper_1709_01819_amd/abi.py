@@ -10,6 +10,7 @@ GAUSS_HERMITE, NEWTON_COTES = 0, 1
 BGK, SHAKHOV = 0, 1
 FP64, FP32_MIXED = 0, 1
 EXPLICIT, IMPLICIT = 0, 1
+SWEEPS_AUTO, SWEEPS_LEVELS, SWEEPS_HYPERPLANES = 0, 1, 2
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_DIVERGED",
           5: "E_NOT_CONVERGED", 6: "E_STATE"}
@@ -39,7 +40,7 @@ class Config(C.Structure):
         ("cfl_start", C.c_double), ("cfl_growth", C.c_double),
         ("nnodes", C.c_int32), ("ncells", C.c_int32),
         ("cell_nodes", C.POINTER(C.c_int32)), ("side_tag", C.POINTER(C.c_int32)),
-        ("graph_sweeps", C.c_int32),
+        ("sweep_order", C.c_int32),
     ]
 
 
@@ -116,7 +117,8 @@ def make_config(cfg):
     """Build the C struct from a config dict; returns (struct, keep-alive arrays).
 
     A "mesh" entry (xn, yn, cell_nodes [nc, 4], side_tag [nc, 4]) selects an unstructured
-    mesh; "graph_sweeps" (0/1) the level-scheduled sweeps on a structured one."""
+    mesh; "sweep_order" (SWEEPS_AUTO, SWEEPS_LEVELS, SWEEPS_HYPERPLANES) how the sweeps walk
+    the cell order."""
     import numpy as np
     mesh = cfg.get("mesh")
     src = cfg if mesh is None else mesh
@@ -137,7 +139,7 @@ def make_config(cfg):
         c.cell_nodes = cn.ctypes.data_as(C.POINTER(C.c_int32))
         c.side_tag = tg.ctypes.data_as(C.POINTER(C.c_int32))
         keep += [cn, tg]
-    c.graph_sweeps = int(cfg.get("graph_sweeps", 0))
+    c.sweep_order = int(cfg.get("sweep_order", SWEEPS_AUTO))
     c.xn, c.yn = xn.ctypes.data_as(_D), yn.ctypes.data_as(_D)
     for s in range(4):
         c.bc[s] = cfg["bc"][s]

@@ -176,25 +176,59 @@ struct idugks_ctx {
 
 namespace {
 
+// How the two sweeps walk the cell order (idugks_config.sweep_order): by levels of the
+// order's dependency graph or by i+j hyperplanes.  The level-scheduled micro sweeps take
+// one workgroup per slice of 64 velocities, so they pay off from about 128 slices (8192
+// velocities) on, where the hyperplane kernel's slices of 8 velocities re-read their
+// staged rows; the one-block hyperplane macro sweep keeps its fronts in LDS and stays the
+// faster one on structured meshes.
+struct SweepPlan {
+    bool micro_levels, macro_levels;  // the sweeps of an implicit iteration
+    bool hyper_micro_fits, hyper_macro_fits;
+};
+
+SweepPlan sweep_plan(const idugks_config *c) {
+    SweepPlan sp{};
+    if (c->cell_nodes) {
+        sp.micro_levels = sp.macro_levels = true;
+        return sp;
+    }
+    const bool per_i = c->bc[0] == IDUGKS_BC_PERIODIC, per_j = c->bc[2] == IDUGKS_BC_PERIODIC;
+    const bool small = std::min(c->ni, c->nj) <= 280;
+    const MacroShape m = macro_shape(c->ni, c->nj, per_i, per_j);
+    sp.hyper_macro_fits = small && m.lds <= 150 * 1024 && m.threads <= 1024;
+    sp.hyper_micro_fits = small && sweep_shape(c->ni, c->nj, 1, 8).vb > 0;
+    const int64_t nv = (int64_t)c->nvx * c->nvy, slices = (nv + VPAD - 1) / VPAD;
+    if (c->sweep_order == IDUGKS_SWEEPS_LEVELS) {
+        sp.micro_levels = sp.macro_levels = true;
+    } else if (c->sweep_order == IDUGKS_SWEEPS_AUTO) {
+        sp.micro_levels = slices >= 128 || !sp.hyper_micro_fits;
+        sp.macro_levels = !sp.hyper_macro_fits;
+    }
+    return sp;
+}
+
 idugks_status validate(const idugks_config *c) {
     if (!c) return fail(IDUGKS_E_INVALID, "null config");
     if (c->struct_size != sizeof(idugks_config)) return fail(IDUGKS_E_INVALID, "struct_size mismatch");
     const bool um = c->cell_nodes != nullptr;
-    if (c->graph_sweeps != 0 && c->graph_sweeps != 1) return fail(IDUGKS_E_INVALID, "graph_sweeps must be 0 or 1");
+    if (c->sweep_order < IDUGKS_SWEEPS_AUTO || c->sweep_order > IDUGKS_SWEEPS_HYPERPLANES)
+        return fail(IDUGKS_E_INVALID, "sweep_order must be IDUGKS_SWEEPS_AUTO, _LEVELS or _HYPERPLANES");
     if (um) {
         if (c->ncells < 1 || c->nnodes < 3 || !c->side_tag)
             return fail(IDUGKS_E_INVALID, "unstructured mesh needs ncells >= 1, nnodes >= 3 and side_tag");
         for (int s = 0; s < 4; ++s)
             if (c->bc[s] == IDUGKS_BC_PERIODIC)
                 return fail(IDUGKS_E_INVALID, "no periodic boundary conditions on an unstructured mesh");
+        if (c->sweep_order == IDUGKS_SWEEPS_HYPERPLANES)
+            return fail(IDUGKS_E_INVALID, "i+j hyperplanes need a structured mesh");
     } else {
         if (c->ni < 1 || c->nj < 1) return fail(IDUGKS_E_INVALID, "mesh needs ni, nj >= 1");
         if ((int64_t)c->ni * c->nj >= ((int64_t)1 << 31)) return fail(IDUGKS_E_INVALID, "too many cells");
-        const bool per_i = c->bc[0] == IDUGKS_BC_PERIODIC, per_j = c->bc[2] == IDUGKS_BC_PERIODIC;
-        if (!c->graph_sweeps &&
-            (std::min(c->ni, c->nj) > 280 || macro_shape(c->ni, c->nj, per_i, per_j).lds > 150 * 1024 ||
-             macro_shape(c->ni, c->nj, per_i, per_j).threads > 1024 || sweep_shape(c->ni, c->nj, 1, 8).vb == 0))
-            return fail(IDUGKS_E_INVALID, "mesh too large for the LDS-resident sweep fronts (graph_sweeps = 1 has no such limit)");
+        const SweepPlan sp = sweep_plan(c);
+        if (c->sweep_order == IDUGKS_SWEEPS_HYPERPLANES && !(sp.hyper_micro_fits && sp.hyper_macro_fits))
+            return fail(IDUGKS_E_INVALID, "mesh too large for the LDS-resident sweep fronts of the hyperplane "
+                                          "sweeps (sweep_order AUTO or LEVELS has no such limit)");
     }
     if (!c->xn || !c->yn) return fail(IDUGKS_E_INVALID, "missing node coordinates");
     if (c->predictor != 0 && c->predictor != 1) return fail(IDUGKS_E_INVALID, "unknown predictor");
@@ -252,7 +286,7 @@ struct Built {
     std::vector<CellSide> cs;
     std::vector<int> hp_off, hp_pos;  // hyperplanes (structured) or levels (graph sweeps)
     int nlev;
-    std::vector<int> gcell, gnb;      // per position: cell, neighbour cell of each side
+    std::vector<int> grow;            // per position: [GR_N] row of the level sweeps
     std::vector<double> sgeo;
     std::vector<Face> faces;
     std::vector<int> wall_faces;
@@ -712,15 +746,20 @@ idugks_status build(const idugks_config *c, Built &b) {
     // per position of the sweep order: the cell, and per side the neighbour cell, or
     // -1 - t on a boundary side with boundary-condition slot t, or the cell itself (a side
     // without flux)
-    b.gcell.assign(b.nc, 0);
-    b.gnb.assign((size_t)4 * b.nc, 0);
+    b.grow.assign((size_t)GR_N * b.nc, 0);
     for (int cidx = 0; cidx < b.nc; ++cidx) {
         const int pos = b.hp_pos[cidx];
-        b.gcell[pos] = cidx;
+        int *g = &b.grow[(size_t)GR_N * pos];
+        g[GR_CELL] = cidx;
+        int mask = 0;
         for (int sd = 0; sd < 4; ++sd) {
             const CellSide &q = b.cs[(size_t)4 * cidx + sd];
-            b.gnb[(size_t)4 * pos + sd] = q.type == FT_SELF ? cidx : q.nb >= 0 ? q.nb : -1 - q.wside;
+            g[GR_NB + sd] = q.type == FT_SELF ? cidx : q.nb >= 0 ? q.nb : -1 - q.wside;
+            const bool coupled = q.type != FT_SELF && q.nb >= 0;
+            if (coupled) mask |= q.nb < cidx ? 1 << sd : 1 << (4 + sd);
+            g[GR_NPOS + sd] = coupled ? b.hp_pos[q.nb] : pos;
         }
+        g[GR_MASK] = mask;
     }
     b.sgeo.assign((size_t)b.nc * SG_N, 0.0);
     for (int cidx = 0; cidx < b.nc; ++cidx)
@@ -829,13 +868,14 @@ enum Region {
     R_STAGE, R_HPOFF, R_HPPOS, R_SGEO, R_SREC, R_SDRHO, R_MH, R_FV, R_MWC, R_RECT, R_RECFT,
     // sensitivities (empty unless BGK, no limiter, FP64)
     R_LT, R_GJ, R_FBAR, R_YBUF, R_AGR, R_FADJ, R_CADJ, R_DGW, R_DWDEN, R_JACC, R_JACF, R_RED,
-    R_ADJS, R_DWR, R_GCELL, R_GNB, R_COUNT
+    R_ADJS, R_DWR, R_GROW, R_COUNT
 };
 
 // Sensitivities are available for BGK without limiter in the FP64 form.
+// (the transposed micro iteration runs the hyperplane sweep kernel)
 bool adjoint_capable(const idugks_config *c) {
     return c->model == IDUGKS_BGK && c->limiter == 0 && c->precision == IDUGKS_FP64 && !c->cell_nodes &&
-           !c->graph_sweeps;
+           c->sweep_order != IDUGKS_SWEEPS_LEVELS && sweep_plan(c).hyper_micro_fits;
 }
 
 // Wall faces the layout provides for: all boundary faces of a structured mesh, the built
@@ -872,7 +912,7 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
         adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 6 * (size_t)nc * nvp, adj * 8 * (size_t)FA_N * nf,
         adj * 8 * (size_t)CA_N * nc, adj * 8 * 8 * (size_t)nvp, adj * 8 * 2 * (size_t)nf,
         adj * 8 * 32 * (size_t)nc, adj * 8 * 32 * (size_t)nf, adj * 8 * (size_t)RED_N, adj * 8 * ADJS_N,
-        8 * 4 * (size_t)nc, sizeof(int) * (size_t)nc, sizeof(int) * 4 * (size_t)nc};
+        8 * 4 * (size_t)nc, sizeof(int) * GR_N * (size_t)nc};
     for (int r = 0; r < R_COUNT; ++r) L.add(sizes[r]);
     L.bytes = (L.bytes + 255) & ~size_t(255);
     return L;
@@ -1092,9 +1132,10 @@ static idugks_status init_ctx(const idugks_config *cfg, void *d_workspace, void 
     x->cfl_growth = cfg->cfl_growth;
     x->imp_iters = 0;
     x->st = (hipStream_t)hip_stream;
-    const bool graph = cfg->cell_nodes || cfg->graph_sweeps;
-    x->sweep = graph ? SweepShape{} : sweep_shape(b.ni, b.nj, b.nv, x->fp32 ? 4 : 8);
-    if (!graph && x->sweep.vb == 0) {
+    const SweepPlan plan = sweep_plan(cfg);
+    // the hyperplane shape serves the micro sweeps and the adjoint's transposed sweeps
+    x->sweep = plan.hyper_micro_fits ? sweep_shape(b.ni, b.nj, b.nv, x->fp32 ? 4 : 8) : SweepShape{};
+    if (!plan.micro_levels && x->sweep.vb == 0) {
         delete x;
         return fail(IDUGKS_E_INVALID, "no sweep launch shape fits this mesh");
     }
@@ -1132,7 +1173,7 @@ static idugks_status init_ctx(const idugks_config *cfg, void *d_workspace, void 
     p.dtimp = (double *)R(R_DTIMP); p.rho_old = (double *)R(R_RHOOLD); p.drho = (double *)R(R_DRHO);
     p.scal = (double *)R(R_SCAL);
     p.hp_off = (const int *)R(R_HPOFF); p.hp_pos = (const int *)R(R_HPPOS);
-    p.graph = graph; p.nlev = b.nlev; p.gcell = (const int *)R(R_GCELL); p.gnb = (const int *)R(R_GNB);
+    p.graph = plan.micro_levels; p.gmacro = plan.macro_levels; p.nlev = b.nlev; p.grow = (const int *)R(R_GROW);
     p.sgeo = (const double *)R(R_SGEO); p.srec = (double *)R(R_SREC); p.sdrho = (double *)R(R_SDRHO);
     p.mh = (double *)R(R_MH); p.fv = R(R_FV); p.recT = R(R_RECT); p.recfT = R(R_RECFT);
     p.MWc = (double *)R(R_MWC);
@@ -1153,7 +1194,7 @@ static idugks_status init_ctx(const idugks_config *cfg, void *d_workspace, void 
     };
     hipError_t e = hipSuccess;
 #define UP(r, vec) if (e == hipSuccess && !(vec).empty()) e = up(R(r), (vec).data(), (vec).size() * sizeof((vec)[0]))
-    UP(R_GCELL, b.gcell); UP(R_GNB, b.gnb);
+    UP(R_GROW, b.grow);
     UP(R_CS, b.cs); UP(R_HPOFF, b.hp_off); UP(R_HPPOS, b.hp_pos); UP(R_SGEO, b.sgeo); UP(R_FACES, b.faces); UP(R_WALLF, b.wall_faces); UP(R_AREA, b.area);
     UP(R_XI, b.xi); UP(R_ETA, b.eta); UP(R_W, b.w); UP(R_X1, b.x1); UP(R_WX1, b.wx1);
     UP(R_Y1, b.y1); UP(R_WY1, b.wy1); UP(R_VIX, b.vix); UP(R_VIY, b.viy); UP(R_GW, b.gw);
@@ -1371,7 +1412,7 @@ idugks_status idugks_predict(idugks_ctx *x, double *Wstar, double *dt_imp, int32
 // ---- sensitivities --------------------------------------------------------------------
 static idugks_status adjoint_check(idugks_ctx *x) {
     if (!x) return fail(IDUGKS_E_INVALID, "null context");
-    if (!x->adj) return fail(IDUGKS_E_INVALID, "sensitivities need the BGK model, no limiter and the FP64 form");
+    if (!x->adj) return fail(IDUGKS_E_INVALID, "sensitivities need the BGK model, no limiter, the FP64 form and a structured mesh whose hyperplane sweeps fit (sweep_order AUTO or HYPERPLANES)");
     return IDUGKS_OK;
 }
 

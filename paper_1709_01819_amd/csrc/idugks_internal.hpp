@@ -92,6 +92,11 @@ constexpr int HP_SPARE = 48;
 // the forward sweep to the adjacent hyperplane, i+ and j+ to the copy kept at a periodic
 // seam; the other way round in the backward sweep.
 enum SweepCode : int { SG_DIAG = 1, SG_LOWER = 2, SG_UPPER = 4 };
+// Row of a position in the level-scheduled sweeps: GR_CELL the cell, GR_NB + s the
+// neighbour code of side s, GR_MASK bit s (bit 4 + s) set if side s couples in the forward
+// (backward) sweep, GR_NPOS + s the neighbour's position (the own position where there is
+// none).
+enum GRow : int { GR_CELL = 0, GR_NB = 1, GR_MASK = 5, GR_NPOS = 6, GR_N = 16 };
 // Scalars kept on the device (FP64).
 enum Scalar : int { SC_SCALE = 0, SC_RES = 1, SC_MASS = 2, SC_FLAG = 3, SC_NUM = 8 };
 
@@ -134,11 +139,11 @@ struct Params {
     const int *hp_pos;       // [nc] position of each cell
     // level-scheduled sweeps (unstructured meshes, or on request): the positions hold the
     // cells level by level of the sweep order's dependency graph (hp_off has nlev + 1
-    // entries); per position the cell and per side its neighbour cell, -1 - t on a
-    // boundary side of boundary-condition slot t, or the cell itself on a side without flux
-    int graph, nlev;
-    const int *gcell;        // [nc]
-    const int *gnb;          // [nc][4]
+    // entries); grow holds per position the cell, per side its neighbour cell (-1 - t on a
+    // boundary side of boundary-condition slot t, the cell itself on a side without flux),
+    // the coupling masks and per side the neighbour's position (GR_* below)
+    int graph, gmacro, nlev;  // micro / macro sweeps by levels (else by hyperplanes)
+    const int *grow;         // [nc][GR_N]
     const double *sgeo;      // [nc][SG_N] nx S[4], ny S[4], w_lower[4], w_upper[4] (static)
     double *srec;            // [nc][SR_N] U, V, c0, c1, c2c, c3, kqx, kqy, iRT, KRT, cst, base
     double *sdrho;           // [nc][4] wall ghost density increment per cell side

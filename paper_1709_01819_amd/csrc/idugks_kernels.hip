@@ -1466,130 +1466,277 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
 // and a level holds cells whose lower-indexed neighbours all lie on earlier levels, so the
 // cells of a level are independent in the forward sweep and, taken in reverse, in the
 // backward one.  This serves any mesh (unstructured ones; structured ones on request,
-// where the levels are the i+j hyperplanes).  One block per slice of 64 velocities; a wave
-// takes one cell of the level at a time (its per-cell data are wave-uniform loads, its
-// state a 64-wide row) and reads its neighbours' increments from d1, written by this block
-// on an earlier level (a block barrier separates the levels; the backward sweep also
+// where the levels are the i+j hyperplanes).  One block of GS_NW waves per slice of 64
+// velocities; wave w takes the cells w, w + GS_NW, ... of a level, in batches of up to CB
+// cells: all loads of a batch are issued before any arithmetic (the stores of one cell
+// would otherwise hold back the loads of the next).  A cell's rows (side data, record,
+// ghost increments) are read one value per lane, so that a batch costs a few registers per
+// cell, and broadcast by readlane; the rows of the next level's first batch are loaded
+// during the current level.  The neighbours' increments come from d1, written by this
+// block on an earlier level (a block barrier separates the levels; the backward sweep also
 // leaves its increments in d1 for that).  Per cell and velocity the arithmetic is the
 // hyperplane kernel's, in the same order.
 // ---------------------------------------------------------------------------------------
-constexpr int GS_THREADS = 512;
+constexpr int GS_NW = 16, GS_THREADS = 64 * GS_NW;
 
-template <class S, bool SHAK, bool UPPER>
+// lane e's value, as a wave-uniform value
+DEV float rl(float v, int e) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), e)); }
+DEV double rl(double v, int e) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, e);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), e);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One lane's share of a cell's rows: lane e holds value e & 15 of the cell's index row
+// (cell, side codes, coupling masks), of its side geometry (nx S, ny S) and of its record
+// (forward: the predicted record; backward: the four ghost increments, then the diagonal
+// base at lane 4), the last two converted to the state precision by each lane (one
+// conversion per lane instead of one per value).
+template <class T>
+struct GRows {
+    int ri;
+    T rg, rr;
+};
+
+template <class T, bool UPPER>
+DEV void grows_load(const Params &p, int pos, int lane, GRows<T> &r) {
+    const int e = lane & 15;
+    r.ri = p.grow[(size_t)pos * GR_N + e];
+    r.rg = (T)p.sgeo[(size_t)pos * SG_N + (e & 7)];
+    if (!UPPER) r.rr = (T)p.srec[(size_t)pos * SR_N + (e < SR_N ? e : 0)];
+    else r.rr = (T)(e < 4 ? p.sdrho[(size_t)pos * 4 + e] : p.srec[(size_t)pos * SR_N + 11]);
+}
+
+// element of a row at a 32-bit byte offset: a wave-uniform row base plus a per-lane
+// offset that fits the load's 32-bit offset field
+template <class S>
+DEV S &at(S *row, unsigned byte_off) {
+    return *(S *)((char *)row + byte_off);
+}
+
+// the loads of one cell of a batch
+template <class S>
+struct GItem {
+    S aG, aH, bG, bH, e1, e2;
+    S nG[4], nH[4];
+};
+
+template <class S, bool SHAK, bool UPPER, int CB>
 __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p) {
     using T = S;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-    constexpr int NW = GS_THREADS / 64;
+    // 32-bit byte offsets of the lane's velocity in a row: a load is a wave-uniform row
+    // base plus that offset
     const int v = xcd_remap(blockIdx.x, gridDim.x) * 64 + lane;  // < nvp (padding reads zeros)
     const bool vok = v < p.nv;
-    const int nvp = p.nvp, nv2 = 2 * nvp, ntb = p.nvx + p.nvy;
+    const int nvp = p.nvp, nv2 = 2 * p.nvp, ntb = p.nvx + p.nvy;
+    const unsigned ov = (unsigned)v * sizeof(S), oh = (unsigned)(nvp + v) * sizeof(S);
     const T x = (T)p.xi[v], y = (T)p.eta[v];
-    const int ix = p.vix[v], iy = p.viy[v];
+    const unsigned ox = (unsigned)p.vix[v] * sizeof(S), oy = (unsigned)(p.nvx + p.viy[v]) * sizeof(S);
     const T sc = (T)p.scal[SC_SCALE];
     S *d1 = (S *)p.d1, *f = (S *)p.f;
-    for (int t = 0; t < p.nlev; ++t) {
-        const int l = UPPER ? p.nlev - 1 - t : t;
-        const int end = p.hp_off[l + 1];
-        for (int pos = p.hp_off[l] + wave; pos < end; pos += NW) {
-            const int c = p.gcell[pos];
-            const double *g = p.sgeo + (size_t)pos * SG_N, *rr = p.srec + (size_t)pos * SR_N;
-            const int *nb = p.gnb + (size_t)pos * 4;
-            const size_t o = (size_t)c * nv2 + v;
-            const T aG = d1[o], aH = d1[o + nvp], bG = f[o], bH = f[o + nvp];
-            T D = (T)rr[11], sG, sH;
-            if (!UPPER) {
-                RecT<T> r;
-                r.U = (T)rr[0]; r.V = (T)rr[1]; r.c0 = (T)rr[2]; r.c1 = (T)rr[3]; r.c2c = (T)rr[4];
-                r.c3 = (T)rr[5]; r.kqx = (T)rr[6]; r.kqy = (T)rr[7]; r.iRT = (T)rr[8]; r.KRT = (T)rr[9];
-                const S *tb = (const S *)p.tabs + (size_t)c * ntb;
-                T eG, eH;
-                eq_eval<T, SHAK>(r, x, y, tb[ix] * tb[p.nvx + iy], eG, eH);
-                sG = aG - (T)rr[10] * (sc * bG - eG);
-                sH = aH - (T)rr[10] * (sc * bH - eH);
-            } else {
-                sG = sH = T(0);
-            }
+    const int nlev = p.nlev;
+    auto lev = [&](int t) { return UPPER ? nlev - 1 - t : t; };
+    // rows of the first batch of level t: cell k = wave + GS_NW b (b < CB) if it exists,
+    // else the level's first cell (loaded and never used)
+    auto load_rows = [&](GRows<T> (&r)[CB], int t, int base) {
+        const int l = lev(t), off = p.hp_off[l], n = p.hp_off[l + 1] - off;
 #pragma unroll
-            for (int sd = 0; sd < 4; ++sd) {
-                const T unS = x * (T)g[sd] + y * (T)g[4 + sd];  // (xi.n) S
-                const T uo = fmax(unS, T(0)), ui = fmin(unS, T(0));
-                D += uo;
-                const int j = nb[sd];
-                if (g[(UPPER ? 12 : 8) + sd] != 0.0) {  // inflow from a coupled neighbour
-                    const size_t oj = (size_t)j * nv2 + v;
-                    const T nG = d1[oj], nH = d1[oj + nvp];
-                    sG -= ui * nG;
-                    sH -= ui * nH;
+        for (int b = 0; b < CB; ++b) {
+            const int k = base + wave + GS_NW * b;
+            grows_load<T, UPPER>(p, off + (k < n ? k : 0), lane, r[b]);
+        }
+    };
+    GRows<T> cur[CB], nxt[CB];
+    load_rows(cur, 0, 0);
+    for (int t = 0; t < nlev; ++t) {
+        const int l = lev(t), n = p.hp_off[l + 1] - p.hp_off[l];
+        for (int base = 0; base < n; base += GS_NW * CB) {
+            if (base > 0) load_rows(cur, t, base);
+            GItem<S> it[CB];
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                if (base + wave + GS_NW * b >= n) continue;  // wave-uniform
+                const int c = __builtin_amdgcn_readlane(cur[b].ri, GR_CELL);
+                const int mask = __builtin_amdgcn_readlane(cur[b].ri, GR_MASK);
+                // wave-uniform row bases, the lane's velocity as the offset
+                const S *dr = d1 + (size_t)c * nv2, *fr = f + (size_t)c * nv2;  // wave-uniform
+                it[b].aG = at(dr, ov);
+                it[b].aH = at(dr, oh);
+                it[b].bG = at(fr, ov);
+                it[b].bH = at(fr, oh);
+                if (!UPPER) {
+                    const S *tb = (const S *)p.tabs + (size_t)c * ntb;
+                    it[b].e1 = at(tb, ox);
+                    it[b].e2 = at(tb, oy);
                 }
-                if (UPPER && j < 0) {  // inflow through a boundary: the wall ghost's increment
-                    const int tg = -1 - j;
-                    const T gw = -(T)p.gw[(size_t)tg * nvp + v] * (T)p.sdrho[(size_t)pos * 4 + sd] * ui;
-                    sG += gw;
-                    sH += gw * (T)p.wKRT[tg];
+#pragma unroll
+                for (int sd = 0; sd < 4; ++sd) {
+                    const int j = __builtin_amdgcn_readlane(cur[b].ri, GR_NB + sd);
+                    if ((mask >> (UPPER ? 4 + sd : sd)) & 1) {
+                        const S *nr = d1 + (size_t)j * nv2;
+                        it[b].nG[sd] = at(nr, ov);
+                        it[b].nH[sd] = at(nr, oh);
+                    }
                 }
             }
-            const T iD = rcp_nr(D);
-            const T dG = UPPER ? aG + sG * iD : sG * iD;
-            const T dH = UPPER ? aH + sH * iD : sH * iD;
-            if (vok) {
-                d1[o] = (S)dG;
-                d1[o + nvp] = (S)dH;
-                if (UPPER) {
-                    f[o] = (S)(sc * bG + dG);
-                    f[o + nvp] = (S)(sc * bH + dH);
+            // the next level's first rows fly during this batch's arithmetic and the barrier
+            if (base + GS_NW * CB >= n && t + 1 < nlev) load_rows(nxt, t + 1, 0);
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                if (base + wave + GS_NW * b >= n) continue;
+                const GRows<T> &r = cur[b];
+                const GItem<S> &q = it[b];
+                const int c = __builtin_amdgcn_readlane(r.ri, GR_CELL);
+                const int mask = __builtin_amdgcn_readlane(r.ri, GR_MASK);
+                T D = rl(r.rr, UPPER ? 4 : 11), sG, sH;
+                if (!UPPER) {
+                    RecT<T> rc;
+                    rc.U = rl(r.rr, 0); rc.V = rl(r.rr, 1); rc.c0 = rl(r.rr, 2); rc.c1 = rl(r.rr, 3);
+                    rc.c2c = rl(r.rr, 4); rc.c3 = rl(r.rr, 5); rc.kqx = rl(r.rr, 6); rc.kqy = rl(r.rr, 7);
+                    rc.iRT = rl(r.rr, 8); rc.KRT = rl(r.rr, 9);
+                    T eG, eH;
+                    eq_eval<T, SHAK>(rc, x, y, q.e1 * q.e2, eG, eH);
+                    const T cst = rl(r.rr, 10);
+                    sG = q.aG - cst * (sc * q.bG - eG);
+                    sH = q.aH - cst * (sc * q.bH - eH);
+                } else {
+                    sG = sH = T(0);
+                }
+#pragma unroll
+                for (int sd = 0; sd < 4; ++sd) {
+                    const T unS = x * rl(r.rg, sd) + y * rl(r.rg, 4 + sd);  // (xi.n) S
+                    const T uo = fmax(unS, T(0)), ui = fmin(unS, T(0));
+                    D += uo;
+                    if ((mask >> (UPPER ? 4 + sd : sd)) & 1) {  // inflow from a coupled neighbour
+                        sG -= ui * q.nG[sd];
+                        sH -= ui * q.nH[sd];
+                    }
+                    if (UPPER) {
+                        const int j = __builtin_amdgcn_readlane(r.ri, GR_NB + sd);
+                        if (j < 0) {  // inflow through a boundary: the wall ghost's increment
+                            // (a cache-resident table, read here to keep the batch's registers)
+                            const T gwv = (T)p.gw[(size_t)(-1 - j) * nvp + v];
+                            const T g = -gwv * rl(r.rr, sd) * ui;
+                            sG += g;
+                            sH += g * (T)p.wKRT[-1 - j];
+                        }
+                    }
+                }
+                const T iD = rcp_nr(D);
+                const T dG = UPPER ? q.aG + sG * iD : sG * iD;
+                const T dH = UPPER ? q.aH + sH * iD : sH * iD;
+                if (vok) {
+                    S *dr = d1 + (size_t)c * nv2, *fr = f + (size_t)c * nv2;
+                    at(dr, ov) = (S)dG;
+                    at(dr, oh) = (S)dH;
+                    if (UPPER) {
+                        at(fr, ov) = (S)(sc * q.bG + dG);
+                        at(fr, oh) = (S)(sc * q.bH + dH);
+                    }
                 }
             }
         }
         __syncthreads();
+#pragma unroll
+        for (int b = 0; b < CB; ++b) cur[b] = nxt[b];
     }
 }
 
-// Macro LU-SGS sweeps (Eq. 29-31) level by level in one block: one thread per cell of a
-// level, the cell's row and its neighbours' W and sound speed from the macro rows, the
-// increments in dW (cell order; the forward sweep leaves dW* there, the backward sweep
-// reads it back and leaves dW).
-constexpr int GM_THREADS = 512;
+// Macro LU-SGS sweeps (Eq. 29-31) level by level in one block: one lane per cell of a
+// level, forward then backward.  A cell's own data (M_W, 1/D, side codes, side geometry;
+// its index and its neighbours' cells and positions) do not depend on the sweep, so each
+// lane loads them for its cell of the next level while it works on the current one; a
+// level then waits for one round of loads, its coupled neighbours' W and sound speed
+// (their macro rows) and increments (dW in cell order: dW* after the forward sweep, dW
+// after the backward one).
+constexpr int GM_THREADS = 256;
+
+struct GMOwn {
+    double mw[4], iD, geo[12];
+    int codes, c, nb[4], np[4];
+};
+
+DEV void gm_load(const Params &p, int pos, GMOwn &o) {
+    const double *m = p.mh + (size_t)pos * MH_N;
+    const int *g = p.grow + (size_t)pos * GR_N;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) o.mw[a] = m[a];
+    o.iD = m[4];
+    o.codes = (int)m[5];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) o.geo[e] = m[MH_SIDE + e];
+    o.c = g[GR_CELL];
+#pragma unroll
+    for (int sd = 0; sd < 4; ++sd) {
+        o.nb[sd] = g[GR_NB + sd];
+        o.np[sd] = g[GR_NPOS + sd];
+    }
+}
 
 __global__ __launch_bounds__(GM_THREADS) void k_gmacro(Params p) {
     const double ik2 = 1.0 / (p.K + 2);
+    const int nlev = p.nlev, tid = threadIdx.x;
     for (int dir = 0; dir < 2; ++dir) {
         const bool upper = dir == 1;
         const int need = upper ? SG_UPPER : SG_LOWER;
-        for (int t = 0; t < p.nlev; ++t) {
-            const int l = upper ? p.nlev - 1 - t : t;
-            const int end = p.hp_off[l + 1];
-            for (int pos = p.hp_off[l] + (int)threadIdx.x; pos < end; pos += GM_THREADS) {
-                const int c = p.gcell[pos];
-                const double *m = p.mh + (size_t)pos * MH_N;
-                const int codes = (int)m[5];
-                double r[4] = {0.0, 0.0, 0.0, 0.0};
+        auto lev = [&](int t) { return upper ? nlev - 1 - t : t; };
+        // the lane's cell k of level t's first round (a level's first cell past its end)
+        auto load = [&](GMOwn &o, int t, int k) {
+            const int l = lev(t), off = p.hp_off[l], n = p.hp_off[l + 1] - off;
+            gm_load(p, off + (k < n ? k : 0), o);
+        };
+        GMOwn cur, nxt;
+        load(cur, 0, tid);
+        for (int t = 0; t < nlev; ++t) {
+            const int l = lev(t), n = p.hp_off[l + 1] - p.hp_off[l];
+            for (int k0 = 0; k0 < n; k0 += GM_THREADS) {
+                if (k0 > 0) load(cur, t, k0 + tid);
+                const bool live = k0 + tid < n;
+                // this cell's coupled neighbours: W, sound speed and increment
+                double Wj[4][4], Cj[4], dWj[4][4], dWc[4];
+                bool use[4];
+#pragma unroll
                 for (int sd = 0; sd < 4; ++sd) {
-                    if (!((codes >> (MH_CODE_BITS * sd)) & need)) continue;
-                    const int j = p.gnb[(size_t)pos * 4 + sd];
-                    const double *mj = p.mh + (size_t)p.hp_pos[j] * MH_N, *dWj = p.dW + (size_t)j * 4;
-                    const double nx = m[MH_SIDE + MH_SN * sd], ny = m[MH_SIDE + MH_SN * sd + 1];
-                    const double hS = 0.5 * m[MH_SIDE + MH_SN * sd + 2];
-                    double Wj[4], Wn[4], dw[4], F0[4], F1[4];
+                    use[sd] = live && ((cur.codes >> (MH_CODE_BITS * sd)) & need);
+                    if (!use[sd]) continue;
+                    const double *mj = p.mh + (size_t)cur.np[sd] * MH_N;
+                    const double *dj = p.dW + (size_t)cur.nb[sd] * 4;
 #pragma unroll
                     for (int a = 0; a < 4; ++a) {
-                        Wj[a] = mj[6 + a];
-                        dw[a] = dWj[a];
-                        Wn[a] = Wj[a] + dw[a];
+                        Wj[sd][a] = mj[6 + a];
+                        dWj[sd][a] = dj[a];
                     }
-                    const double lam = fabs(euler_flux_n(Wj, nx, ny, ik2, F0)) + mj[10];
-                    euler_flux_n(Wn, nx, ny, ik2, F1);
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) r[a] += hS * (F1[a] - F0[a] - lam * dw[a]);
+                    Cj[sd] = mj[10];
                 }
-                const double iD = m[4];
+                if (upper && live)
 #pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    double *q = p.dW + (size_t)c * 4 + a;
-                    *q = upper ? *q - r[a] * iD : (m[a] - r[a]) * iD;
+                    for (int a = 0; a < 4; ++a) dWc[a] = p.dW[(size_t)cur.c * 4 + a];
+                if (k0 + GM_THREADS >= n && t + 1 < nlev) load(nxt, t + 1, tid);
+                if (live) {
+                    double r[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int sd = 0; sd < 4; ++sd) {
+                        if (!use[sd]) continue;
+                        const double nx = cur.geo[MH_SN * sd], ny = cur.geo[MH_SN * sd + 1];
+                        const double hS = 0.5 * cur.geo[MH_SN * sd + 2];
+                        double Wn[4], F0[4], F1[4];
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) Wn[a] = Wj[sd][a] + dWj[sd][a];
+                        const double lam = fabs(euler_flux_n(Wj[sd], nx, ny, ik2, F0)) + Cj[sd];
+                        euler_flux_n(Wn, nx, ny, ik2, F1);
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) r[a] += hS * (F1[a] - F0[a] - lam * dWj[sd][a]);
+                    }
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+                        p.dW[(size_t)cur.c * 4 + a] = upper ? dWc[a] - r[a] * cur.iD : (cur.mw[a] - r[a]) * cur.iD;
                 }
             }
             __syncthreads();
+            cur = nxt;
         }
     }
 }
@@ -2383,7 +2530,7 @@ hipError_t launch_macro_relax(const Params &p, hipStream_t st) {
 }
 
 hipError_t launch_macro(const Params &p, hipStream_t st) {
-    if (p.graph) {
+    if (p.gmacro) {
         hipLaunchKernelGGL(k_gmacro, dim3(1), dim3(GM_THREADS), 0, st, p);
         return hipGetLastError();
     }
@@ -2446,9 +2593,11 @@ static hipError_t sweep_launch_v(const Params &p, const SweepShape &sh, hipStrea
     return sweep_launch<S, SHAK, UPPER, false, 1>(p, sh, st);
 }
 
+// cells per wave and batch: the FP32 state leaves registers for four, FP64 for two
 template <class S, bool SHAK, bool UPPER>
 static hipError_t gsweep_launch(const Params &p, hipStream_t st) {
-    hipLaunchKernelGGL((k_gsweep<S, SHAK, UPPER>), dim3(p.nvp / 64), dim3(GS_THREADS), 0, st, p);
+    constexpr int CB = sizeof(S) == 4 ? 4 : 2;
+    hipLaunchKernelGGL((k_gsweep<S, SHAK, UPPER, CB>), dim3(p.nvp / 64), dim3(GS_THREADS), 0, st, p);
     return hipGetLastError();
 }
 

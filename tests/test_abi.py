@@ -191,15 +191,18 @@ def test_unstructured_mesh_refuses_periodic_conditions_and_bad_flags():
     cfg["bc"] = [wl.BC_PERIODIC, wl.BC_PERIODIC, wl.BC_WALL, wl.BC_WALL]
     rc, _, err = _size(cfg)
     assert rc == 1 and "periodic" in err
-    rc, _, err = _size(dict(wl.case("couette"), graph_sweeps=2))
-    assert rc == 1 and "graph_sweeps" in err
+    rc, _, err = _size(dict(wl.case("couette"), sweep_order=3))
+    assert rc == 1 and "sweep_order" in err
+    rc, _, err = _size(dict(_mesh_cfg(), sweep_order=wl.SWEEPS_HYPERPLANES))
+    assert rc == 1 and "hyperplanes" in err
 
 
 def test_level_sweeps_lift_the_structured_size_limit():
     big = wl.cavity(n=300, nj=300, stretch=None, nv=4)
-    rc, _, err = _size(big)
-    assert rc == 1 and "graph_sweeps" in err
-    assert _size(dict(big, graph_sweeps=1))[0] == 0
+    rc, _, err = _size(dict(big, sweep_order=wl.SWEEPS_HYPERPLANES))
+    assert rc == 1 and "sweep_order" in err
+    assert _size(dict(big, sweep_order=wl.SWEEPS_LEVELS))[0] == 0
+    assert _size(big)[0] == 0  # the library's choice falls back to levels
 
 
 def test_unstructured_workspace_covers_its_arrays():

@@ -1,6 +1,6 @@
 """Level-scheduled sweeps and unstructured meshes on the GPU (needs an MI355X).
 
-1. On structured meshes the level-scheduled sweeps (graph_sweeps = 1) take the same cells
+1. On structured meshes the level-scheduled sweeps (sweep_order LEVELS) take the same cells
    in the same order as the i+j hyperplane sweeps: the micro sweeps do the same
    arithmetic per cell, the macro sweep sums its sides in another order, so the two paths
    agree to rounding (FP64 1e-13, FP32-mixed a few units of the last place).
@@ -53,7 +53,8 @@ STRUCT = {
 @pytest.mark.parametrize("name", list(STRUCT))
 def test_level_sweeps_match_hyperplane_sweeps(name, prec):
     cfg = dict(STRUCT[name](), precision=prec)
-    a, b = _solver(cfg), _solver(dict(cfg, graph_sweeps=1))
+    a = _solver(dict(cfg, sweep_order=wl.SWEEPS_HYPERPLANES))
+    b = _solver(dict(cfg, sweep_order=wl.SWEEPS_LEVELS))
     f0 = _seeded(a.get_state(), 21, 0.05)
     a.set_state(f0)
     b.set_state(f0)

@@ -5,7 +5,7 @@ coordinates, physical parameters and seeded random perturbations.
 """
 from .cases import (  # noqa: F401
     BC_WALL, BC_FARFIELD, BC_PERIODIC, GAUSS_HERMITE, NEWTON_COTES, BGK, SHAKHOV,
-    FP64, FP32_MIXED, EXPLICIT, IMPLICIT,
+    FP64, FP32_MIXED, EXPLICIT, IMPLICIT, SWEEPS_AUTO, SWEEPS_LEVELS, SWEEPS_HYPERPLANES,
     uniform_nodes, tanh_nodes, cartesian_mesh, ogrid_mesh,
     couette, cavity, cavity_re, cylinder, periodic_box, shrink, case, CASE_NAMES,
     perturbation,

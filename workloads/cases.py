@@ -22,6 +22,7 @@ GAUSS_HERMITE, NEWTON_COTES = 0, 1
 BGK, SHAKHOV = 0, 1
 FP64, FP32_MIXED = 0, 1
 EXPLICIT, IMPLICIT = 0, 1
+SWEEPS_AUTO, SWEEPS_LEVELS, SWEEPS_HYPERPLANES = 0, 1, 2
 
 OMEGA_VHS = 0.81        # viscosity exponent mu ~ T^omega used by every case
 
