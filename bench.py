@@ -187,25 +187,20 @@ FLOOR32 = 5e-8   # FP32 iterations hand over to FP64 below this relative density
 
 def ttr_suite(names, budget_s):
     """Time to residual 1e-8 of each named workload from its initial state: FP64, FP32-mixed,
-    and FP32-mixed to its rounding floor followed by FP64 iterations from that state
-    (mixed-precision refinement; the handover copies the state through the canonical FP64
-    layout).  Each solve runs in chunks of 50 iterations until converged or out of budget
+    and FP32-mixed down to FLOOR32 (above the FP32 rounding floor) followed by FP64
+    iterations from that state (mixed-precision refinement; the handover copies the state
+    through the canonical FP64 layout).  Each solve runs in chunks of 50 iterations until converged or out of budget
     (then reported unconverged with the iterations done)."""
     import torch
     import workloads as wl
     from paper_1709_01819_amd import Solver
 
-    def run(s, t0, budget, handover=False):
-        """Solve to 1e-8 in chunks of 50; with handover, stop once the relative density
-        change is below FLOOR32 and no longer falls by a tenth over a chunk (the FP32
-        floor).  Returns (res, converged, error)."""
-        res, ok, err, prev = float("inf"), False, None, float("inf")
+    def run(s, t0, budget, tol=1e-8):
+        """Solve to tol in chunks of 50 iterations.  Returns (res, converged, error)."""
+        res, ok, err = float("inf"), False, None
         try:
             while not ok and time.perf_counter() - t0 < budget:
-                _, res, ok = s.solve(1e-8, 50)
-                if handover and not ok and res < FLOOR32 and res > 0.9 * prev:
-                    break
-                prev = res
+                _, res, ok = s.solve(tol, 50)
         except RuntimeError as e:  # a diverged solve is reported, not raised
             err = str(e)
         return res, ok, err
@@ -231,12 +226,13 @@ def ttr_suite(names, budget_s):
             t0 = time.perf_counter()
             entry = {}
             if pname == "fp32_then_fp64":
-                res, ok, err = run(s, t0, budget_s, handover=True)
+                # FP32 iterations down to FLOOR32, FP64 ones from there
+                res, ok32, err = run(s, t0, budget_s, tol=FLOOR32)
                 it32 = int(s.info().iterations)
                 entry["fp32_iterations"] = it32
                 entry["fp32_res"] = res
-                it = it32
-                if err is None and not ok and res < FLOOR32:
+                it, ok = it32, res < 1e-8
+                if err is None and ok32 and not ok:
                     f = s.get_state()
                     del s
                     s = Solver(cfg_of(wl.FP64))

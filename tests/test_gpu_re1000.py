@@ -1,16 +1,16 @@
 """The continuum lid-driven cavity at Re = 1000 (the paper's Section 3.2 and Table 1), on
 the HIP path (needs an MI355X).
 
-- Parity at the full size (256^2 cells, 17^2 velocities): one implicit iteration from a
+- Parity at the full size (256^2 cells, 25^2 velocities): one implicit iteration from a
   seeded perturbation of the initial state, the whole state element by element against
   the oracle (1e-12 of the largest magnitude per species, as the other FP64 parity
   cases).  This exercises the sweeps at 511 hyperplanes and the macro sweep at the
   largest row staging this mesh takes.
-- Accuracy: the steady flow on a 128^2 mesh (same physics and velocity set) against the
-  IDUGKS row of Table 1 (tests/golden/cavity_re1000_table1.txt): the primary vortex
-  within 2 % (stream function), 3 % (vorticity) and 0.01 (centre); the centres of the
-  secondary vortices within 0.02.  The secondary vortices' stream function values are
-  printed, not checked (the coarser mesh resolves them to 9-16 %).
+- Accuracy: the steady flow on the paper's 256^2 mesh, solved to Res < 1e-8 with the
+  point-relaxation predictor (64 sweeps), against the IDUGKS row of Table 1
+  (tests/golden/cavity_re1000_table1.txt): the primary vortex within 2 % (stream function
+  and vorticity) and 0.01 (centre), the secondary vortices within 10 % (stream function)
+  and 0.02 (centres).
 """
 import os
 
@@ -47,17 +47,20 @@ def test_full_size_step_parity():
 
 def test_steady_vortices_match_table1():
     from paper_1709_01819_amd import Solver
-    cfg = wl.cavity_re(n=128)
+    cfg = dict(wl.case("cavity_re1000"), predictor=1, relax_sweeps=64)
+    assert (cfg["ni"], cfg["nvx"]) == (256, 25)
     g = Solver(cfg)
-    iters, res, ok = g.solve(1e-8, 40000)
+    iters, res, ok = g.solve(1e-8, 20000)
     assert ok, (iters, res)
     m = g.moments()
     vm = vortex_metrics(m[:, 1], m[:, 2], cfg["ni"], cfg["nj"], cfg["wall_u"][3])
     gold = load_golden(os.path.join(HERE, "golden", "cavity_re1000_table1.txt"))
     print({k: round(v, 5) for k, v in vm.items()}, iters)
     assert vm["primary_psi"] == pytest.approx(gold["primary_psi"], rel=0.02)
-    assert vm["primary_omega"] == pytest.approx(gold["primary_omega"], rel=0.03)
+    assert vm["primary_omega"] == pytest.approx(gold["primary_omega"], rel=0.02)
     for k in ("primary_x", "primary_y"):
         assert abs(vm[k] - gold[k]) < 0.01
+    for k in ("left_psi_e4", "right_psi_e3"):
+        assert vm[k] == pytest.approx(gold[k], rel=0.10)
     for k in ("left_x", "left_y", "right_x", "right_y"):
         assert abs(vm[k] - gold[k]) < 0.02
