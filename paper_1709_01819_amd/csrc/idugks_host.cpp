@@ -127,15 +127,17 @@ bool newton_cotes(int n, double vmax, std::vector<double> &x, std::vector<double
 // context
 // ---------------------------------------------------------------------------------------
 struct Layout {
-    size_t off[64];
+    size_t off[64], sz[64];
     size_t bytes = 0;
     int n = 0;
     size_t add(size_t b) {
         bytes = (bytes + 255) & ~size_t(255);
         off[n] = bytes;
+        sz[n] = b;
         bytes += b;
         return n++;
     }
+    size_t size(int r) const { return sz[r]; }
 };
 
 enum KernelId {
@@ -757,6 +759,7 @@ idugks_status build(const idugks_config *c, Built &b) {
             g[GR_NB + sd] = q.type == FT_SELF ? cidx : q.nb >= 0 ? q.nb : -1 - q.wside;
             const bool coupled = q.type != FT_SELF && q.nb >= 0;
             if (coupled) mask |= q.nb < cidx ? 1 << sd : 1 << (4 + sd);
+            if (q.type == FT_WALL) mask |= 1 << (8 + sd);
             g[GR_NPOS + sd] = coupled ? b.hp_pos[q.nb] : pos;
         }
         g[GR_MASK] = mask;
@@ -868,7 +871,7 @@ enum Region {
     R_STAGE, R_HPOFF, R_HPPOS, R_SGEO, R_SREC, R_SDRHO, R_MH, R_FV, R_MWC, R_RECT, R_RECFT,
     // sensitivities (empty unless BGK, no limiter, FP64)
     R_LT, R_GJ, R_FBAR, R_YBUF, R_AGR, R_FADJ, R_CADJ, R_DGW, R_DWDEN, R_JACC, R_JACF, R_RED,
-    R_ADJS, R_DWR, R_GROW, R_COUNT
+    R_ADJS, R_DWR, R_GROW, R_GROWT, R_COUNT
 };
 
 // Sensitivities are available for BGK without limiter in the FP64 form.
@@ -912,7 +915,7 @@ Layout layout(const idugks_config *c, int nc, int nf, int nvp, int nvx, int nvy,
         adj * 8 * 2 * (size_t)nc * nvp, adj * 8 * 6 * (size_t)nc * nvp, adj * 8 * (size_t)FA_N * nf,
         adj * 8 * (size_t)CA_N * nc, adj * 8 * 8 * (size_t)nvp, adj * 8 * 2 * (size_t)nf,
         adj * 8 * 32 * (size_t)nc, adj * 8 * 32 * (size_t)nf, adj * 8 * (size_t)RED_N, adj * 8 * ADJS_N,
-        8 * 4 * (size_t)nc, sizeof(int) * GR_N * (size_t)nc};
+        8 * 4 * (size_t)nc, sizeof(int) * GR_N * (size_t)nc, S * GT_N * (size_t)nc};
     for (int r = 0; r < R_COUNT; ++r) L.add(sizes[r]);
     L.bytes = (L.bytes + 255) & ~size_t(255);
     return L;
@@ -1174,6 +1177,7 @@ static idugks_status init_ctx(const idugks_config *cfg, void *d_workspace, void 
     p.scal = (double *)R(R_SCAL);
     p.hp_off = (const int *)R(R_HPOFF); p.hp_pos = (const int *)R(R_HPPOS);
     p.graph = plan.micro_levels; p.gmacro = plan.macro_levels; p.nlev = b.nlev; p.grow = (const int *)R(R_GROW);
+    p.growT = R(R_GROWT);
     p.sgeo = (const double *)R(R_SGEO); p.srec = (double *)R(R_SREC); p.sdrho = (double *)R(R_SDRHO);
     p.mh = (double *)R(R_MH); p.fv = R(R_FV); p.recT = R(R_RECT); p.recfT = R(R_RECFT);
     p.MWc = (double *)R(R_MWC);
@@ -1195,6 +1199,16 @@ static idugks_status init_ctx(const idugks_config *cfg, void *d_workspace, void 
     hipError_t e = hipSuccess;
 #define UP(r, vec) if (e == hipSuccess && !(vec).empty()) e = up(R(r), (vec).data(), (vec).size() * sizeof((vec)[0]))
     UP(R_GROW, b.grow);
+    // the level sweeps' rows in the state precision: the static side geometry, zeros for
+    // the record and ghost increments (written each iteration; off the walls they stay 0)
+    std::vector<unsigned char> growT(L.size(R_GROWT), 0);
+    for (int pos = 0; pos < b.nc; ++pos)
+        for (int e = 0; e < 8; ++e) {
+            const double g = b.sgeo[(size_t)pos * SG_N + e];
+            if (x->fp32) ((float *)growT.data())[(size_t)pos * GT_N + GT_GEO + e] = (float)g;
+            else ((double *)growT.data())[(size_t)pos * GT_N + GT_GEO + e] = g;
+        }
+    UP(R_GROWT, growT);
     UP(R_CS, b.cs); UP(R_HPOFF, b.hp_off); UP(R_HPPOS, b.hp_pos); UP(R_SGEO, b.sgeo); UP(R_FACES, b.faces); UP(R_WALLF, b.wall_faces); UP(R_AREA, b.area);
     UP(R_XI, b.xi); UP(R_ETA, b.eta); UP(R_W, b.w); UP(R_X1, b.x1); UP(R_WX1, b.wx1);
     UP(R_Y1, b.y1); UP(R_WY1, b.wy1); UP(R_VIX, b.vix); UP(R_VIY, b.viy); UP(R_GW, b.gw);

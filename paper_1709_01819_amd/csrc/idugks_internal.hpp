@@ -94,9 +94,13 @@ constexpr int HP_SPARE = 48;
 enum SweepCode : int { SG_DIAG = 1, SG_LOWER = 2, SG_UPPER = 4 };
 // Row of a position in the level-scheduled sweeps: GR_CELL the cell, GR_NB + s the
 // neighbour code of side s, GR_MASK bit s (bit 4 + s) set if side s couples in the forward
-// (backward) sweep, GR_NPOS + s the neighbour's position (the own position where there is
-// none).
+// (backward) sweep and bit 8 + s if side s is a wall, GR_NPOS + s the neighbour's position
+// (the own position where there is none).
 enum GRow : int { GR_CELL = 0, GR_NB = 1, GR_MASK = 5, GR_NPOS = 6, GR_N = 16 };
+// Row of a position in the state precision for the level-scheduled micro sweeps: side
+// geometry nx S (4), ny S (4) (static), the predicted record as in srec (12, written with
+// it) and the wall ghost increment per side (4, written with sdrho).
+enum GRowT : int { GT_GEO = 0, GT_REC = 8, GT_DRHO = 20, GT_N = 24 };
 // Scalars kept on the device (FP64).
 enum Scalar : int { SC_SCALE = 0, SC_RES = 1, SC_MASS = 2, SC_FLAG = 3, SC_NUM = 8 };
 
@@ -144,6 +148,7 @@ struct Params {
     // the coupling masks and per side the neighbour's position (GR_* below)
     int graph, gmacro, nlev;  // micro / macro sweeps by levels (else by hyperplanes)
     const int *grow;         // [nc][GR_N]
+    void *growT;             // [nc][GT_N] S
     const double *sgeo;      // [nc][SG_N] nx S[4], ny S[4], w_lower[4], w_upper[4] (static)
     double *srec;            // [nc][SR_N] U, V, c0, c1, c2c, c3, kqx, kqy, iRT, KRT, cst, base
     double *sdrho;           // [nc][4] wall ghost density increment per cell side

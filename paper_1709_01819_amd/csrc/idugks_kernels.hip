@@ -481,6 +481,10 @@ __global__ __launch_bounds__(256) void k_records(Params p, int which) {
         o[6] = r.kqx; o[7] = r.kqy; o[8] = r.iRT; o[9] = r.KRT;
         o[10] = 2.0 * p.area[c] / (2.0 * tau + p.dt);    // collision coefficient (Eq. 26)
         o[11] = p.area[c] / p.dtimp[c] + o[10];           // cell part of the diagonal
+        if (p.graph) {  // the level sweeps read it in the state precision
+            S *g = (S *)p.growT + (size_t)p.hp_pos[c] * GT_N + GT_REC;
+            for (int a = 0; a < SR_N; ++a) g[a] = (S)o[a];
+        }
     }
 }
 
@@ -1469,50 +1473,41 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
 // where the levels are the i+j hyperplanes).  One block of GS_NW waves per slice of 64
 // velocities; wave w takes the cells w, w + GS_NW, ... of a level, in batches of up to CB
 // cells: all loads of a batch are issued before any arithmetic (the stores of one cell
-// would otherwise hold back the loads of the next).  A cell's rows (side data, record,
-// ghost increments) are read one value per lane, so that a batch costs a few registers per
-// cell, and broadcast by readlane; the rows of the next level's first batch are loaded
-// during the current level.  The neighbours' increments come from d1, written by this
+// would otherwise hold back the loads of the next).  A cell's rows (index row; side
+// geometry, record and ghost increments in the state precision) are scalar loads.  The
+// neighbours' increments come from d1, written by this
 // block on an earlier level (a block barrier separates the levels; the backward sweep also
 // leaves its increments in d1 for that).  Per cell and velocity the arithmetic is the
 // hyperplane kernel's, in the same order.
 // ---------------------------------------------------------------------------------------
 constexpr int GS_NW = 16, GS_THREADS = 64 * GS_NW;
 
-// lane e's value, as a wave-uniform value
-DEV float rl(float v, int e) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), e)); }
-DEV double rl(double v, int e) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, e);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), e);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// One lane's share of a cell's rows: lane e holds value e & 15 of the cell's index row
-// (cell, side codes, coupling masks), of its side geometry (nx S, ny S) and of its record
-// (forward: the predicted record; backward: the four ghost increments, then the diagonal
-// base at lane 4), the last two converted to the state precision by each lane (one
-// conversion per lane instead of one per value).
-template <class T>
-struct GRows {
-    int ri;
-    T rg, rr;
-};
-
-template <class T, bool UPPER>
-DEV void grows_load(const Params &p, int pos, int lane, GRows<T> &r) {
-    const int e = lane & 15;
-    r.ri = p.grow[(size_t)pos * GR_N + e];
-    r.rg = (T)p.sgeo[(size_t)pos * SG_N + (e & 7)];
-    if (!UPPER) r.rr = (T)p.srec[(size_t)pos * SR_N + (e < SR_N ? e : 0)];
-    else r.rr = (T)(e < 4 ? p.sdrho[(size_t)pos * 4 + e] : p.srec[(size_t)pos * SR_N + 11]);
-}
-
 // element of a row at a 32-bit byte offset: a wave-uniform row base plus a per-lane
 // offset that fits the load's 32-bit offset field
 template <class S>
 DEV S &at(S *row, unsigned byte_off) {
     return *(S *)((char *)row + byte_off);
+}
+
+// a position's rows as wave-uniform vector loads (16-byte rows, so they become wide
+// scalar loads): the first eight values of the index row, and the value row
+DEV void grow8(const int *gr, int (&g)[8]) {
+    const int4 a = ((const int4 *)gr)[0], b = ((const int4 *)gr)[1];
+    g[0] = a.x; g[1] = a.y; g[2] = a.z; g[3] = a.w; g[4] = b.x; g[5] = b.y; g[6] = b.z; g[7] = b.w;
+}
+DEV void growt(const float *gt, float (&r)[GT_N]) {
+#pragma unroll
+    for (int e = 0; e < GT_N; e += 4) {
+        const float4 a = ((const float4 *)gt)[e / 4];
+        r[e] = a.x; r[e + 1] = a.y; r[e + 2] = a.z; r[e + 3] = a.w;
+    }
+}
+DEV void growt(const double *gt, double (&r)[GT_N]) {
+#pragma unroll
+    for (int e = 0; e < GT_N; e += 2) {
+        const double2 a = ((const double2 *)gt)[e / 2];
+        r[e] = a.x; r[e + 1] = a.y;
+    }
 }
 
 // the loads of one cell of a batch
@@ -1522,8 +1517,12 @@ struct GItem {
     S nG[4], nH[4];
 };
 
+// The per-position rows come in as separate read-only, unaliased kernel arguments: their
+// wave-uniform reads then become scalar loads, and the record, geometry and ghost values
+// (in the state precision, growT) are used as scalar operands of the arithmetic.
 template <class S, bool SHAK, bool UPPER, int CB>
-__global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p) {
+__global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p, const int *__restrict__ grow,
+                                                       const S *__restrict__ growT) {
     using T = S;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
@@ -1538,30 +1537,18 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p) {
     const T sc = (T)p.scal[SC_SCALE];
     S *d1 = (S *)p.d1, *f = (S *)p.f;
     const int nlev = p.nlev;
-    auto lev = [&](int t) { return UPPER ? nlev - 1 - t : t; };
-    // rows of the first batch of level t: cell k = wave + GS_NW b (b < CB) if it exists,
-    // else the level's first cell (loaded and never used)
-    auto load_rows = [&](GRows<T> (&r)[CB], int t, int base) {
-        const int l = lev(t), off = p.hp_off[l], n = p.hp_off[l + 1] - off;
-#pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const int k = base + wave + GS_NW * b;
-            grows_load<T, UPPER>(p, off + (k < n ? k : 0), lane, r[b]);
-        }
-    };
-    GRows<T> cur[CB], nxt[CB];
-    load_rows(cur, 0, 0);
     for (int t = 0; t < nlev; ++t) {
-        const int l = lev(t), n = p.hp_off[l + 1] - p.hp_off[l];
+        const int l = UPPER ? nlev - 1 - t : t;
+        const int off = p.hp_off[l], n = p.hp_off[l + 1] - off;
         for (int base = 0; base < n; base += GS_NW * CB) {
-            if (base > 0) load_rows(cur, t, base);
             GItem<S> it[CB];
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
-                if (base + wave + GS_NW * b >= n) continue;  // wave-uniform
-                const int c = __builtin_amdgcn_readlane(cur[b].ri, GR_CELL);
-                const int mask = __builtin_amdgcn_readlane(cur[b].ri, GR_MASK);
-                // wave-uniform row bases, the lane's velocity as the offset
+                const int k = base + wave + GS_NW * b;
+                if (k >= n) continue;  // wave-uniform
+                int g[8];
+                grow8(grow + (size_t)(off + k) * GR_N, g);
+                const int c = g[GR_CELL], mask = g[GR_MASK];
                 const S *dr = d1 + (size_t)c * nv2, *fr = f + (size_t)c * nv2;  // wave-uniform
                 it[b].aG = at(dr, ov);
                 it[b].aH = at(dr, oh);
@@ -1574,32 +1561,32 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p) {
                 }
 #pragma unroll
                 for (int sd = 0; sd < 4; ++sd) {
-                    const int j = __builtin_amdgcn_readlane(cur[b].ri, GR_NB + sd);
                     if ((mask >> (UPPER ? 4 + sd : sd)) & 1) {
-                        const S *nr = d1 + (size_t)j * nv2;
+                        const S *nr = d1 + (size_t)g[GR_NB + sd] * nv2;
                         it[b].nG[sd] = at(nr, ov);
                         it[b].nH[sd] = at(nr, oh);
                     }
                 }
             }
-            // the next level's first rows fly during this batch's arithmetic and the barrier
-            if (base + GS_NW * CB >= n && t + 1 < nlev) load_rows(nxt, t + 1, 0);
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
-                if (base + wave + GS_NW * b >= n) continue;
-                const GRows<T> &r = cur[b];
+                const int k = base + wave + GS_NW * b;
+                if (k >= n) continue;
+                int g[8];
+                grow8(grow + (size_t)(off + k) * GR_N, g);
+                T gt[GT_N];
+                growt(growT + (size_t)(off + k) * GT_N, gt);
                 const GItem<S> &q = it[b];
-                const int c = __builtin_amdgcn_readlane(r.ri, GR_CELL);
-                const int mask = __builtin_amdgcn_readlane(r.ri, GR_MASK);
-                T D = rl(r.rr, UPPER ? 4 : 11), sG, sH;
+                const int c = g[GR_CELL], mask = g[GR_MASK];
+                T D = gt[GT_REC + 11], sG, sH;
                 if (!UPPER) {
                     RecT<T> rc;
-                    rc.U = rl(r.rr, 0); rc.V = rl(r.rr, 1); rc.c0 = rl(r.rr, 2); rc.c1 = rl(r.rr, 3);
-                    rc.c2c = rl(r.rr, 4); rc.c3 = rl(r.rr, 5); rc.kqx = rl(r.rr, 6); rc.kqy = rl(r.rr, 7);
-                    rc.iRT = rl(r.rr, 8); rc.KRT = rl(r.rr, 9);
+                    rc.U = gt[GT_REC]; rc.V = gt[GT_REC + 1]; rc.c0 = gt[GT_REC + 2]; rc.c1 = gt[GT_REC + 3];
+                    rc.c2c = gt[GT_REC + 4]; rc.c3 = gt[GT_REC + 5]; rc.kqx = gt[GT_REC + 6];
+                    rc.kqy = gt[GT_REC + 7]; rc.iRT = gt[GT_REC + 8]; rc.KRT = gt[GT_REC + 9];
                     T eG, eH;
                     eq_eval<T, SHAK>(rc, x, y, q.e1 * q.e2, eG, eH);
-                    const T cst = rl(r.rr, 10);
+                    const T cst = gt[GT_REC + 10];
                     sG = q.aG - cst * (sc * q.bG - eG);
                     sH = q.aH - cst * (sc * q.bH - eH);
                 } else {
@@ -1607,19 +1594,19 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p) {
                 }
 #pragma unroll
                 for (int sd = 0; sd < 4; ++sd) {
-                    const T unS = x * rl(r.rg, sd) + y * rl(r.rg, 4 + sd);  // (xi.n) S
+                    const T unS = x * gt[GT_GEO + sd] + y * gt[GT_GEO + 4 + sd];  // (xi.n) S
                     const T uo = fmax(unS, T(0)), ui = fmin(unS, T(0));
                     D += uo;
                     if ((mask >> (UPPER ? 4 + sd : sd)) & 1) {  // inflow from a coupled neighbour
                         sG -= ui * q.nG[sd];
                         sH -= ui * q.nH[sd];
                     }
-                    if (UPPER) {
-                        const int j = __builtin_amdgcn_readlane(r.ri, GR_NB + sd);
-                        if (j < 0) {  // inflow through a boundary: the wall ghost's increment
+                    if (UPPER && ((mask >> (8 + sd)) & 1)) {
+                        const int j = g[GR_NB + sd];
+                        {  // inflow through a wall: the ghost's increment
                             // (a cache-resident table, read here to keep the batch's registers)
                             const T gwv = (T)p.gw[(size_t)(-1 - j) * nvp + v];
-                            const T g = -gwv * rl(r.rr, sd) * ui;
+                            const T g = -gwv * gt[GT_DRHO + sd] * ui;
                             sG += g;
                             sH += g * (T)p.wKRT[-1 - j];
                         }
@@ -1640,8 +1627,6 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p) {
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int b = 0; b < CB; ++b) cur[b] = nxt[b];
     }
 }
 
@@ -1770,6 +1755,7 @@ __global__ __launch_bounds__(256) void k_wall_ghost(Params p) {
         const double d = -a[0] / p.wden[k];
         p.drho[k] = d;
         p.sdrho[(size_t)p.hp_pos[F.L] * 4 + F.sL] = d;
+        if (p.graph) ((S *)p.growT)[(size_t)p.hp_pos[F.L] * GT_N + GT_DRHO + F.sL] = (S)d;
     }
 }
 
@@ -2596,8 +2582,9 @@ static hipError_t sweep_launch_v(const Params &p, const SweepShape &sh, hipStrea
 // cells per wave and batch: the FP32 state leaves registers for four, FP64 for two
 template <class S, bool SHAK, bool UPPER>
 static hipError_t gsweep_launch(const Params &p, hipStream_t st) {
-    constexpr int CB = sizeof(S) == 4 ? 4 : 2;
-    hipLaunchKernelGGL((k_gsweep<S, SHAK, UPPER, CB>), dim3(p.nvp / 64), dim3(GS_THREADS), 0, st, p);
+    constexpr int CB = sizeof(S) == 4 ? 6 : 3;
+    hipLaunchKernelGGL((k_gsweep<S, SHAK, UPPER, CB>), dim3(p.nvp / 64), dim3(GS_THREADS), 0, st, p,
+                       p.grow, (const S *)p.growT);
     return hipGetLastError();
 }
 
