@@ -770,8 +770,12 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
             const int type = fs.type[s];
             if (type == FT_SELF) continue;
             const int k = fs.face[s];
-            const double und = normal_speed(xd, yd, fs.nx[s], fs.ny[s]);
-            const bool mine = und > 0.0 || (und == 0.0 && fs.tie[s]);
+            // an interior face's value is the stored reconstruction whichever cell is
+            // upwind, so only boundary faces classify the velocity (with the tie rule);
+            // tangent velocities carry no flux either way
+            const double und = type == FT_INTERIOR ? xd * fs.nx[s] + yd * fs.ny[s]
+                                                   : normal_speed(xd, yd, fs.nx[s], fs.ny[s]);
+            const bool mine = type == FT_INTERIOR || und > 0.0 || (und == 0.0 && fs.tie[s]);
             const T un = (T)und;
             const S *r = fs.rec[s];
             T fG, fH;
@@ -1568,14 +1572,30 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p, const int *__re
                     }
                 }
             }
+            // the rows of cell b + 1 are loaded (unconditionally, a valid position) before
+            // cell b's arithmetic, so that their scalar loads overlap it
+            int gn[8];
+            T gtn[GT_N];
+            {
+                const int k = base + wave < n ? base + wave : 0;
+                grow8(grow + (size_t)(off + k) * GR_N, gn);
+                growt(growT + (size_t)(off + k) * GT_N, gtn);
+            }
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
                 const int k = base + wave + GS_NW * b;
-                if (k >= n) continue;
                 int g[8];
-                grow8(grow + (size_t)(off + k) * GR_N, g);
                 T gt[GT_N];
-                growt(growT + (size_t)(off + k) * GT_N, gt);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) g[e] = gn[e];
+#pragma unroll
+                for (int e = 0; e < GT_N; ++e) gt[e] = gtn[e];
+                if (b + 1 < CB) {
+                    const int kn = k + GS_NW < n ? k + GS_NW : 0;
+                    grow8(grow + (size_t)(off + kn) * GR_N, gn);
+                    growt(growT + (size_t)(off + kn) * GT_N, gtn);
+                }
+                if (k >= n) continue;
                 const GItem<S> &q = it[b];
                 const int c = g[GR_CELL], mask = g[GR_MASK];
                 T D = gt[GT_REC + 11], sG, sH;
