@@ -127,7 +127,8 @@ bool newton_cotes(int n, double vmax, std::vector<double> &x, std::vector<double
 // context
 // ---------------------------------------------------------------------------------------
 struct Layout {
-    size_t off[64], sz[64];
+    static constexpr int N = 80;
+    size_t off[N], sz[N];
     size_t bytes = 0;
     int n = 0;
     size_t add(size_t b) {
@@ -873,6 +874,7 @@ enum Region {
     R_LT, R_GJ, R_FBAR, R_YBUF, R_AGR, R_FADJ, R_CADJ, R_DGW, R_DWDEN, R_JACC, R_JACF, R_RED,
     R_ADJS, R_DWR, R_GROW, R_GROWT, R_COUNT
 };
+static_assert(R_COUNT <= Layout::N, "more workspace regions than the layout holds");
 
 // Sensitivities are available for BGK without limiter in the FP64 form.
 // (the transposed micro iteration runs the hyperplane sweep kernel)
