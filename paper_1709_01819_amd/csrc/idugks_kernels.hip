@@ -1576,6 +1576,8 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p, const int *__re
             // cell b's arithmetic, so that their scalar loads overlap it
             int gn[8];
             T gtn[GT_N];
+            T rG[CB], rH[CB];
+            int rc[CB];
             {
                 const int k = base + wave < n ? base + wave : 0;
                 grow8(grow + (size_t)(off + k) * GR_N, gn);
@@ -1635,14 +1637,30 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p, const int *__re
                 const T iD = rcp_nr(D);
                 const T dG = UPPER ? q.aG + sG * iD : sG * iD;
                 const T dH = UPPER ? q.aH + sH * iD : sH * iD;
-                if (vok) {
-                    S *dr = d1 + (size_t)c * nv2, *fr = f + (size_t)c * nv2;
-                    at(dr, ov) = (S)dG;
-                    at(dr, oh) = (S)dH;
-                    if (UPPER) {
+                if (UPPER) {
+                    if (vok) {
+                        S *dr = d1 + (size_t)c * nv2, *fr = f + (size_t)c * nv2;
+                        at(dr, ov) = dG;
+                        at(dr, oh) = dH;
                         at(fr, ov) = (S)(sc * q.bG + dG);
                         at(fr, oh) = (S)(sc * q.bH + dH);
                     }
+                } else {
+                    rG[b] = dG;
+                    rH[b] = dH;
+                    rc[b] = c;
+                }
+            }
+            // the forward sweep stores its batch after all of the batch's arithmetic: a store
+            // between two cells makes the next cell wait for it as well as for its loads (the
+            // backward sweep, with four stores per cell, is faster storing as it goes)
+            if (!UPPER && vok) {
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    if (base + wave + GS_NW * b >= n) continue;
+                    S *dr = d1 + (size_t)rc[b] * nv2;
+                    at(dr, ov) = (S)rG[b];
+                    at(dr, oh) = (S)rH[b];
                 }
             }
         }
