@@ -30,6 +30,13 @@ namespace idugks {
 // helpers
 // ---------------------------------------------------------------------------------------
 
+// element of a row at a 32-bit byte offset: a wave-uniform row base plus a per-lane
+// offset that fits the load's 32-bit offset field
+template <class S>
+DEV S &at(S *row, unsigned byte_off) {
+    return *(S *)((char *)row + byte_off);
+}
+
 // Block b of n is dispatched to XCD b % 8; give each XCD a contiguous range of cells so
 // that neighbouring cells share an L2.
 DEV int xcd_remap(int b, int n) {
@@ -498,22 +505,24 @@ __global__ __launch_bounds__(256) void k_records(Params p, int which) {
 template <class S>
 struct PartStage {
     S rec[5][RT_N];
-    double ax[4], ay[4], dx[4], dy[4], nx[4], ny[4];
+    S ax[4], ay[4], dx[4], dy[4];
+    double nx[4], ny[4];
     int nb[4], face[4], type[4], tie[4];
 };
 
 // phi-bar-plus = ab phi~ + bb phi_eq of one cell at one velocity (Eq. 10, 12), from its
-// record r, factored Maxwellian tb and state row f (G, then H at f + nvp)
+// record r, factored Maxwellian tb and state row f (a block-uniform base; G at byte
+// offset ov, H at oh)
 template <class S, class T, bool SHAK>
-DEV void barplus(const S *r, const S *tb, int nvx, const S *f, int nvp, int v, int ix, int iy, T x,
-                 T y, T sc, T &bG, T &bH) {
+DEV void barplus(const S *r, const S *tb, int nvx, const S *f, unsigned ov, unsigned oh, int ix, int iy,
+                 T x, T y, T sc, T &bG, T &bH) {
     RecT<T> q;
     q.U = r[0]; q.V = r[1]; q.c0 = r[2]; q.c1 = r[3]; q.c2c = r[4]; q.c3 = r[5];
     q.kqx = r[6]; q.kqy = r[7]; q.iRT = r[8]; q.KRT = r[9]; q.ab = r[10]; q.bb = r[11];
     const T E = (T)tb[ix] * (T)tb[nvx + iy];
     T eG, eH;
     eq_eval<T, SHAK>(q, x, y, E, eG, eH);
-    const T XG = sc * (T)f[v], XH = sc * (T)f[nvp + v];
+    const T XG = sc * (T)at(f, ov), XH = sc * (T)at(f, oh);
     bG = q.ab * XG + q.bb * eG;
     bH = q.ab * XH + q.bb * eH;
 }
@@ -522,11 +531,11 @@ template <class T>
 DEV T venkat(T x) { return (x * x + T(2) * x) / (x * x + x + T(2)); }
 
 template <class T>
-DEV T limiter_phi(const double *dx, const double *dy, T b0, T bmax, T bmin, T gx, T gy) {
+DEV T limiter_phi(const T *dx, const T *dy, T b0, T bmax, T bmin, T gx, T gy) {
     T phi = T(1);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const T d = gx * (T)dx[s] + gy * (T)dy[s];
+        const T d = gx * dx[s] + gy * dy[s];
         T th = T(1);
         if (d > T(0)) th = venkat<T>((bmax - b0) / d);
         else if (d < T(0)) th = venkat<T>((bmin - b0) / d);
@@ -553,7 +562,7 @@ __global__ __launch_bounds__(256) void k_partials(Params p) {
     if (tid < 4) {
         const CellSide &q = cs[tid];
         ps.nb[tid] = q.nb; ps.face[tid] = q.face; ps.type[tid] = q.type; ps.tie[tid] = q.tie;
-        ps.ax[tid] = q.ax; ps.ay[tid] = q.ay; ps.dx[tid] = q.dx; ps.dy[tid] = q.dy;
+        ps.ax[tid] = (S)q.ax; ps.ay[tid] = (S)q.ay; ps.dx[tid] = (S)q.dx; ps.dy[tid] = (S)q.dy;
         ps.nx[tid] = q.nx; ps.ny[tid] = q.ny;
     }
     if (tid < 5 * RT_N) {
@@ -571,6 +580,20 @@ __global__ __launch_bounds__(256) void k_partials(Params p) {
         return TL ? (const S *)lt + q * TW : (const S *)p.tab + (size_t)j * TW;
     };
     const T sc = (T)p.scal[SC_SCALE], h = (T)p.h;
+    // the block-uniform side data in scalar registers: neighbours, face types, tie flags
+    // and the rows of the neighbours' states and of the faces' values
+    int nbs[4], tys[4], tis[4];
+    const S *frow[4];
+    S *fvrow[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        nbs[s] = __builtin_amdgcn_readfirstlane(ps.nb[s]);
+        tys[s] = __builtin_amdgcn_readfirstlane(ps.type[s]);
+        tis[s] = __builtin_amdgcn_readfirstlane(ps.tie[s]);
+        frow[s] = (const S *)p.f + (size_t)(nbs[s] < 0 ? c : nbs[s]) * 2 * nvp;
+        fvrow[s] = (S *)p.fv + (size_t)__builtin_amdgcn_readfirstlane(ps.face[s]) * 2 * nvp;
+    }
+    const S *frow0 = (const S *)p.f + (size_t)c * 2 * nvp;
     for (int v = v0 + tid; v < v1; v += blockDim.x) {
         // keep the staged records in LDS, read per iteration (hoisted, the five records
         // would hold about 120 registers and halve the occupancy); emits no code
@@ -578,19 +601,19 @@ __global__ __launch_bounds__(256) void k_partials(Params p) {
         const int ix = p.vix[v], iy = p.viy[v];
         const double xd = p.xi[v], yd = p.eta[v];
         const T x = (T)xd, y = (T)yd;
+        // rows are a block-uniform base plus the lane's 32-bit byte offset
+        const unsigned ov = (unsigned)v * sizeof(S), oh = (unsigned)(nvp + v) * sizeof(S);
         T bG, bH;
-        barplus<S, T, SHAK>(ps.rec[0], tab_of(0, c), nvx, (const S *)p.f + (size_t)c * 2 * nvp, nvp, v,
-                            ix, iy, x, y, sc, bG, bH);
+        barplus<S, T, SHAK>(ps.rec[0], tab_of(0, c), nvx, frow0, ov, oh, ix, iy, x, y, sc, bG, bH);
         T gxG = T(0), gyG = T(0), gxH = T(0), gyH = T(0);
         T mxG = bG, mnG = bG, mxH = bH, mnH = bH;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int n = ps.nb[s];
+            const int n = nbs[s];
             if (n < 0) continue;
             T nG, nH;
-            barplus<S, T, SHAK>(ps.rec[1 + s], tab_of(1 + s, n), nvx, (const S *)p.f + (size_t)n * 2 * nvp,
-                                nvp, v, ix, iy, x, y, sc, nG, nH);
-            const T ax = (T)ps.ax[s], ay = (T)ps.ay[s], dG = nG - bG, dH = nH - bH;
+            barplus<S, T, SHAK>(ps.rec[1 + s], tab_of(1 + s, n), nvx, frow[s], ov, oh, ix, iy, x, y, sc, nG, nH);
+            const T ax = ps.ax[s], ay = ps.ay[s], dG = nG - bG, dH = nH - bH;
             gxG += ax * dG; gyG += ay * dG; gxH += ax * dH; gyH += ay * dH;
             if (LIM) {
                 mxG = nG > mxG ? nG : mxG; mnG = nG < mnG ? nG : mnG;
@@ -604,13 +627,12 @@ __global__ __launch_bounds__(256) void k_partials(Params p) {
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            if (ps.type[s] == FT_SELF) continue;
+            if (tys[s] == FT_SELF) continue;
             const double un = normal_speed(xd, yd, ps.nx[s], ps.ny[s]);
-            if (!(un > 0.0 || (un == 0.0 && ps.tie[s]))) continue;
-            const T rx = (T)ps.dx[s] - h * x, ry = (T)ps.dy[s] - h * y;
-            S *fv = (S *)p.fv + (size_t)ps.face[s] * 2 * nvp + v;
-            fv[0] = (S)(bG + gxG * rx + gyG * ry);
-            fv[nvp] = (S)(bH + gxH * rx + gyH * ry);
+            if (!(un > 0.0 || (un == 0.0 && tis[s]))) continue;
+            const T rx = ps.dx[s] - h * x, ry = ps.dy[s] - h * y;
+            at(fvrow[s], ov) = (S)(bG + gxG * rx + gyG * ry);
+            at(fvrow[s], oh) = (S)(bH + gxH * rx + gyH * ry);
         }
     }
 }
@@ -726,7 +748,8 @@ DEV void macro_row(const Params &p, int c, const double mw[4]) {
 template <class S>
 struct FluxStage {
     S rec[4][RT_N];
-    double nx[4], ny[4], S_[4];
+    S nxT[4], nyT[4], ST[4];
+    double nx[4], ny[4];
     int face[4], type[4], tie[4], wside[4];
 };
 
@@ -743,7 +766,8 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
     if (tid < 4) {
         const CellSide &q = cs[tid];
         fs.face[tid] = q.face; fs.type[tid] = q.type; fs.tie[tid] = q.tie; fs.wside[tid] = q.wside;
-        fs.nx[tid] = q.nx; fs.ny[tid] = q.ny; fs.S_[tid] = q.S;
+        fs.nx[tid] = q.nx; fs.ny[tid] = q.ny;
+        fs.nxT[tid] = (S)q.nx; fs.nyT[tid] = (S)q.ny; fs.ST[tid] = (S)q.S;
     }
     if (tid < 4 * RT_N) {
         const int q = tid / RT_N, e = tid - q * RT_N;
@@ -758,49 +782,77 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
     __syncthreads();
     S *MG = (S *)p.d1 + ((size_t)c * 2) * nvp, *MH = MG + nvp;
     double mw[4] = {0.0, 0.0, 0.0, 0.0};
+    // the block-uniform side data in scalar registers: face types, tie flags, the rows of
+    // the faces' values and of the wall Maxwellians, the wall K RT
+    int tys[4], tis[4];
+    const S *fvrow[4];
+    const double *gwrow[4];
+    T wkrt[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        tys[s] = __builtin_amdgcn_readfirstlane(fs.type[s]);
+        tis[s] = __builtin_amdgcn_readfirstlane(fs.tie[s]);
+        fvrow[s] = (const S *)p.fv + (size_t)__builtin_amdgcn_readfirstlane(fs.face[s]) * 2 * nvp;
+        const int ws = tys[s] == FT_WALL ? __builtin_amdgcn_readfirstlane(fs.wside[s]) : 0;
+        gwrow[s] = p.gw + (size_t)ws * nvp;
+        wkrt[s] = (T)p.wKRT[ws];
+    }
     for (int v = v0 + tid; v < v1; v += blockDim.x) {
         // keep the staged records in LDS, read per iteration (emits no code)
         asm volatile("" ::: "memory");
         const int ix = p.vix[v], iy = p.viy[v];
         const double xd = p.xi[v], yd = p.eta[v];
         const T x = (T)xd, y = (T)yd;
+        const unsigned ov = (unsigned)v * sizeof(S), oh = (unsigned)(nvp + v) * sizeof(S);
+        // every side's stored face values first (they depend only on the velocity; a
+        // boundary face's value is read whichever way the velocity points and used only
+        // where this cell is upwind), then the classification and the arithmetic
+        T fG[4], fH[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (tys[s] == FT_SELF) continue;
+            fG[s] = at(fvrow[s], ov);
+            fH[s] = at(fvrow[s], oh);
+        }
+        T un[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int type = tys[s];
+            if (type == FT_SELF) continue;
+            // an interior face's value is the stored reconstruction whichever cell is
+            // upwind, so only boundary faces classify the velocity (with the tie rule,
+            // in FP64); tangent velocities carry no flux either way
+            if (type == FT_INTERIOR) {
+                un[s] = x * fs.nxT[s] + y * fs.nyT[s];
+                continue;
+            }
+            const double und = normal_speed(xd, yd, fs.nx[s], fs.ny[s]);
+            un[s] = (T)und;
+            if (und > 0.0 || (und == 0.0 && tis[s])) continue;  // reconstructed by this cell
+            if (type == FT_WALL) {
+                const T rw = fs.rec[s][13];
+                const T g = (T)gwrow[s][v];
+                fG[s] = rw * g;
+                fH[s] = rw * wkrt[s] * g;
+            } else {
+                fG[s] = (T)p.ginf[v];
+                fH[s] = (T)p.hinf[v];
+            }
+        }
         T accG = T(0), accH = T(0);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int type = fs.type[s];
-            if (type == FT_SELF) continue;
-            const int k = fs.face[s];
-            // an interior face's value is the stored reconstruction whichever cell is
-            // upwind, so only boundary faces classify the velocity (with the tie rule);
-            // tangent velocities carry no flux either way
-            const double und = type == FT_INTERIOR ? xd * fs.nx[s] + yd * fs.ny[s]
-                                                   : normal_speed(xd, yd, fs.nx[s], fs.ny[s]);
-            const bool mine = type == FT_INTERIOR || und > 0.0 || (und == 0.0 && fs.tie[s]);
-            const T un = (T)und;
+            if (tys[s] == FT_SELF) continue;
             const S *r = fs.rec[s];
-            T fG, fH;
-            if (mine || type == FT_INTERIOR) {  // reconstructed by the upwind cell
-                const S *fv = (const S *)p.fv + (size_t)k * 2 * nvp + v;
-                fG = fv[0];
-                fH = fv[nvp];
-            } else if (type == FT_WALL) {
-                const T rw = r[13];
-                const T g = (T)p.gw[(size_t)fs.wside[s] * nvp + v];
-                fG = rw * g;
-                fH = rw * (T)p.wKRT[fs.wside[s]] * g;
-            } else {
-                fG = (T)p.ginf[v];
-                fH = (T)p.hinf[v];
-            }
             RecT<T> rf;
             rf.U = r[0]; rf.V = r[1]; rf.c0 = r[2]; rf.c1 = r[3]; rf.c2c = r[4]; rf.c3 = r[5];
             rf.kqx = r[6]; rf.kqy = r[7]; rf.iRT = r[8]; rf.KRT = r[9]; rf.ab = r[10]; rf.bb = r[11];
-            const S *tf = TL ? (const S *)lt + s * TW : (const S *)p.tabf + (size_t)k * TW;
+            const S *tf = TL ? (const S *)lt + s * TW : (const S *)p.tabf + (size_t)__builtin_amdgcn_readfirstlane(fs.face[s]) * TW;
             T eG, eH;
             eq_eval<T, SHAK>(rf, x, y, (T)tf[ix] * (T)tf[nvx + iy], eG, eH);
             const T al = r[12];
-            const T pG = al * fG + (T(1) - al) * eG, pH = al * fH + (T(1) - al) * eH;
-            const T fl = (T)fs.S_[s] * un;
+            const T pG = al * fG[s] + (T(1) - al) * eG, pH = al * fH[s] + (T(1) - al) * eH;
+            const T fl = fs.ST[s] * un[s];
             accG -= fl * pG;
             accH -= fl * pH;
         }
@@ -1485,13 +1537,6 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
 // hyperplane kernel's, in the same order.
 // ---------------------------------------------------------------------------------------
 constexpr int GS_NW = 16, GS_THREADS = 64 * GS_NW;
-
-// element of a row at a 32-bit byte offset: a wave-uniform row base plus a per-lane
-// offset that fits the load's 32-bit offset field
-template <class S>
-DEV S &at(S *row, unsigned byte_off) {
-    return *(S *)((char *)row + byte_off);
-}
 
 // a position's rows as wave-uniform vector loads (16-byte rows, so they become wide
 // scalar loads): the first eight values of the index row, and the value row
