@@ -351,30 +351,52 @@ DEV RecT<S> load_recT(const void *base, int i) {
 }
 
 // ---------------------------------------------------------------------------------------
-// raw moments of the stored state, one block per cell
-// ---------------------------------------------------------------------------------------
+// raw moments of the stored state, one wave per cell: the block's RW_W cells share the
+// velocity set (xi, eta, w), staged into LDS a chunk at a time, so that the vector memory
+// path carries only the state; a lane takes the velocities lane, lane + 64, ... in order
+constexpr int RW_W = 8, RW_CH = 64 * RW_W;
+
 template <class S, int NM>
-__global__ __launch_bounds__(256) void k_raw(Params p) {
-    __shared__ double sh[4 * NM];
-    const int c = xcd_remap(blockIdx.x, p.nc);
-    const S *G = rowp<S>(p, p.f, c, 0), *H = rowp<S>(p, p.f, c, 1);
+__global__ __launch_bounds__(64 * RW_W) void k_raw(Params p) {
+    constexpr int PER = RW_CH / 64;  // velocities per lane and chunk
+    __shared__ double vx[RW_CH], vy[RW_CH], vw[RW_CH];
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * RW_W + (threadIdx.x >> 6);
+    const bool live = c < p.nc;
+    const S *G = rowp<S>(p, p.f, live ? c : 0, 0), *H = rowp<S>(p, p.f, live ? c : 0, 1);
     double a[NM];
 #pragma unroll
     for (int m = 0; m < NM; ++m) a[m] = 0.0;
-    // four velocities per lane and pass (four passes of loads in flight)
-    for (int v0 = threadIdx.x; v0 < p.nv; v0 += 4 * blockDim.x) {
-        double ws[4], xs[4], ys[4], gs[4], hs[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int v = v0 + u * blockDim.x, vc = v < p.nv ? v : 0;
-            ws[u] = v < p.nv ? p.w[vc] : 0.0;
-            xs[u] = p.xi[vc]; ys[u] = p.eta[vc];
-            gs[u] = (double)G[vc]; hs[u] = (double)H[vc];
+    for (int c0 = 0; c0 < p.nv; c0 += RW_CH) {
+        const int vt = c0 + threadIdx.x;
+        if (vt < p.nv) {
+            vx[threadIdx.x] = p.xi[vt];
+            vy[threadIdx.x] = p.eta[vt];
+            vw[threadIdx.x] = p.w[vt];
         }
+        __syncthreads();
+        if (live) {
+            S gs[PER], hs[PER];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc_moments<NM>(a, ws[u], xs[u], ys[u], gs[u], hs[u]);
+            for (int u = 0; u < PER; ++u) {
+                const int v = c0 + 64 * u + lane, vc = v < p.nv ? v : 0;
+                gs[u] = G[vc];
+                hs[u] = H[vc];
+            }
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int j = 64 * u + lane;
+                if (c0 + j < p.nv) acc_moments<NM>(a, vw[j], vx[j], vy[j], (double)gs[u], (double)hs[u]);
+            }
+        }
+        __syncthreads();
     }
-    block_sum_store<NM, true>(a, sh, p.raw + (size_t)c * NM_MAX);
+    if (!live) return;
+    wave_sum_dpp<NM>(a);
+    if (lane == 0) {
+#pragma unroll
+        for (int m = 0; m < NM; ++m) p.raw[(size_t)c * NM_MAX + m] = a[m];
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -641,42 +663,64 @@ __global__ __launch_bounds__(256) void k_partials(Params p) {
 // face records: moments of phi-bar at every face, wall density (zero normal mass flux),
 // face equilibrium (heat flux 2 tau qbar / (2 tau + h Pr)).  One wave per face.
 // ---------------------------------------------------------------------------------------
+// The velocity set (xi, eta, w) is staged into LDS a chunk at a time and shared by the
+// block's FR_W faces, so that the vector memory path carries only the face values.
+constexpr int FR_W = 8, FR_CH = 64 * FR_W;
+
 template <class S, bool SHAK>
-__global__ __launch_bounds__(256) void k_face_records(Params p) {
+__global__ __launch_bounds__(64 * FR_W) void k_face_records(Params p) {
     constexpr int NM = SHAK ? NM_SHAKHOV : NM_BGK;
+    constexpr int PER = FR_CH / 64;  // velocities per lane and chunk
+    __shared__ double vx[FR_CH], vy[FR_CH], vw[FR_CH];
     const int lane = threadIdx.x & 63;
-    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (k >= p.nf) return;
-    const Face F = p.faces[k];
-    if (F.type == FT_SELF) return;
+    const int k = blockIdx.x * FR_W + (threadIdx.x >> 6);
+    Face F{};
+    CellSide cL{};
+    bool live = false;
+    if (k < p.nf) {
+        F = p.faces[k];
+        live = F.type != FT_SELF;
+        // (a face without flux may have no cell: L = -1 on an unused periodic face)
+        if (live) cL = p.cs[4 * F.L + F.sL];
+    }
     // moments of the stored face values: every velocity at an interior face, the outflow
-    // half (the interior cell upwind) at a boundary face
-    const CellSide cL = p.cs[4 * F.L + F.sL];
-    const S *fvG = (const S *)p.fv + (size_t)k * 2 * p.nvp, *fvH = fvG + p.nvp;
+    // half (the interior cell upwind) at a boundary face; a lane takes the velocities
+    // lane, lane + 64, ... in order
+    const S *fvG = (const S *)p.fv + (size_t)(live ? k : 0) * 2 * p.nvp, *fvH = fvG + p.nvp;
     double m[NM];
     for (int i = 0; i < NM; ++i) m[i] = 0.0;
-    // four velocities per lane and pass, so that a wave keeps four passes of loads in flight
-    for (int v0 = lane; v0 < p.nv; v0 += 256) {
-        double xs[4], ys[4], ws[4], gs[4], hs[4];
-        bool use[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int v = v0 + 64 * u;
-            use[u] = v < p.nv;
-            const int vc = use[u] ? v : 0;
-            xs[u] = p.xi[vc]; ys[u] = p.eta[vc]; ws[u] = p.w[vc];
-            gs[u] = (double)fvG[vc]; hs[u] = (double)fvH[vc];
+    for (int c0 = 0; c0 < p.nv; c0 += FR_CH) {
+        const int vt = c0 + threadIdx.x;
+        if (vt < p.nv) {
+            vx[threadIdx.x] = p.xi[vt];
+            vy[threadIdx.x] = p.eta[vt];
+            vw[threadIdx.x] = p.w[vt];
         }
+        __syncthreads();
+        if (live) {
+            S gs[PER], hs[PER];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (F.type != FT_INTERIOR) {
-                const double un = normal_speed(xs[u], ys[u], cL.nx, cL.ny);
-                use[u] = use[u] && (un > 0.0 || (un == 0.0 && cL.tie));
+            for (int u = 0; u < PER; ++u) {
+                const int v = c0 + 64 * u + lane, vc = v < p.nv ? v : 0;
+                gs[u] = fvG[vc];
+                hs[u] = fvH[vc];
             }
-            // (the inflow half of a boundary face is never written: skip it, do not weight it)
-            if (use[u]) acc_moments<NM>(m, ws[u], xs[u], ys[u], gs[u], hs[u]);
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int j = 64 * u + lane;
+                bool use = c0 + j < p.nv;
+                const double xs = vx[j], ys = vy[j];
+                if (F.type != FT_INTERIOR) {
+                    const double un = normal_speed(xs, ys, cL.nx, cL.ny);
+                    use = use && (un > 0.0 || (un == 0.0 && cL.tie));
+                }
+                // (the inflow half of a boundary face is never written: skip it, do not weight it)
+                if (use) acc_moments<NM>(m, vw[j], xs, ys, (double)gs[u], (double)hs[u]);
+            }
         }
+        __syncthreads();
     }
+    if (!live) return;
     wave_sum_dpp<NM>(m);
     double rw = 0.0;
     if (F.type != FT_INTERIOR) {
@@ -2454,8 +2498,9 @@ __global__ void k_from_dev(Params p, const double *src, double *dst, double scal
 
 hipError_t launch_raw(const Params &p, bool fp32, int nm, hipStream_t st) {
     DISPATCH_S(fp32, {
-        if (nm == 12) hipLaunchKernelGGL((k_raw<S, 12>), dim3(p.nc), dim3(256), 0, st, p);
-        else hipLaunchKernelGGL((k_raw<S, 4>), dim3(p.nc), dim3(256), 0, st, p);
+        const dim3 g((p.nc + RW_W - 1) / RW_W);
+        if (nm == 12) hipLaunchKernelGGL((k_raw<S, 12>), g, dim3(64 * RW_W), 0, st, p);
+        else hipLaunchKernelGGL((k_raw<S, 4>), g, dim3(64 * RW_W), 0, st, p);
     });
     return hipGetLastError();
 }
@@ -2504,10 +2549,10 @@ hipError_t launch_partials(const Params &p, bool fp32, hipStream_t st) {
 }
 
 hipError_t launch_face_records(const Params &p, bool fp32, hipStream_t st) {
-    const dim3 g((p.nf + 3) / 4);
+    const dim3 g((p.nf + FR_W - 1) / FR_W);
     DISPATCH_S(fp32, {
-        if (p.model == 1) hipLaunchKernelGGL((k_face_records<S, true>), g, dim3(256), 0, st, p);
-        else hipLaunchKernelGGL((k_face_records<S, false>), g, dim3(256), 0, st, p);
+        if (p.model == 1) hipLaunchKernelGGL((k_face_records<S, true>), g, dim3(64 * FR_W), 0, st, p);
+        else hipLaunchKernelGGL((k_face_records<S, false>), g, dim3(64 * FR_W), 0, st, p);
     });
     return hipGetLastError();
 }
