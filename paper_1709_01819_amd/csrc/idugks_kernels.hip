@@ -591,7 +591,11 @@ __global__ __launch_bounds__(256) void k_partials(Params p) {
         const int q = tid / RT_N, e = tid - q * RT_N, j = q == 0 ? c : cs[q - 1].nb;
         ps.rec[q][e] = j >= 0 ? ((const S *)p.recT)[(size_t)j * RT_N + e] : S(0);
     }
-    S *lt = (S *)pdyn;
+    // the 1-D velocity abscissae (x then y; xi = x1[ix], eta = y1[iy] exactly) and, when
+    // they fit, the five cells' factored Maxwellians
+    double *xy = pdyn;
+    S *lt = (S *)(xy + TW);
+    for (int e = tid; e < TW; e += blockDim.x) xy[e] = e < nvx ? p.x1[e] : p.y1[e - nvx];
     if (TL)
         for (int e = tid; e < 5 * TW; e += blockDim.x) {
             const int q = e / TW, i = e - q * TW, j = q == 0 ? c : cs[q - 1].nb;
@@ -621,7 +625,7 @@ __global__ __launch_bounds__(256) void k_partials(Params p) {
         // would hold about 120 registers and halve the occupancy); emits no code
         asm volatile("" ::: "memory");
         const int ix = p.vix[v], iy = p.viy[v];
-        const double xd = p.xi[v], yd = p.eta[v];
+        const double xd = xy[ix], yd = xy[nvx + iy];
         const T x = (T)xd, y = (T)yd;
         // rows are a block-uniform base plus the lane's 32-bit byte offset
         const unsigned ov = (unsigned)v * sizeof(S), oh = (unsigned)(nvp + v) * sizeof(S);
@@ -817,7 +821,14 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
         const int q = tid / RT_N, e = tid - q * RT_N;
         fs.rec[q][e] = cs[q].type == FT_SELF ? S(0) : ((const S *)p.recfT)[(size_t)cs[q].face * RT_N + e];
     }
-    S *lt = (S *)fdyn;
+    // the 1-D velocity abscissae and weights (x then y; xi = x1[ix], eta = y1[iy] and
+    // w = wx1[ix] wy1[iy] exactly) and, when they fit, the four faces' factored Maxwellians
+    double *xy = fdyn, *wxy = fdyn + TW;
+    S *lt = (S *)(fdyn + 2 * TW);
+    for (int e = tid; e < TW; e += blockDim.x) {
+        xy[e] = e < nvx ? p.x1[e] : p.y1[e - nvx];
+        wxy[e] = e < nvx ? p.wx1[e] : p.wy1[e - nvx];
+    }
     if (TL)
         for (int e = tid; e < 4 * TW; e += blockDim.x) {
             const int q = e / TW, i = e - q * TW;
@@ -845,7 +856,7 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
         // keep the staged records in LDS, read per iteration (emits no code)
         asm volatile("" ::: "memory");
         const int ix = p.vix[v], iy = p.viy[v];
-        const double xd = p.xi[v], yd = p.eta[v];
+        const double xd = xy[ix], yd = xy[nvx + iy];
         const T x = (T)xd, y = (T)yd;
         const unsigned ov = (unsigned)v * sizeof(S), oh = (unsigned)(nvp + v) * sizeof(S);
         // every side's stored face values first (they depend only on the velocity; a
@@ -902,7 +913,7 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
         }
         MG[v] = (S)accG;
         MH[v] = (S)accH;
-        const double wv = p.w[v], dG = (double)accG;
+        const double wv = wxy[ix] * wxy[nvx + iy], dG = (double)accG;
         mw[0] += wv * dG;
         mw[1] += wv * xd * dG;
         mw[2] += wv * yd * dG;
@@ -2530,9 +2541,9 @@ static hipError_t combine(const double *src, double *dst, const Params &p, int n
 template <class S, bool SHAK, bool LIM>
 static void launch_partials_t(const Params &p, hipStream_t st) {
     const dim3 g = chunk_grid(p, 1);
-    const size_t tl = (size_t)5 * (p.nvx + p.nvy) * sizeof(S);
-    if (tl <= 16384) hipLaunchKernelGGL((k_partials<S, SHAK, LIM, true>), g, dim3(256), tl, st, p);
-    else hipLaunchKernelGGL((k_partials<S, SHAK, LIM, false>), g, dim3(256), 0, st, p);
+    const size_t xy = (size_t)(p.nvx + p.nvy) * sizeof(double), tl = (size_t)5 * (p.nvx + p.nvy) * sizeof(S);
+    if (tl <= 16384) hipLaunchKernelGGL((k_partials<S, SHAK, LIM, true>), g, dim3(256), xy + tl, st, p);
+    else hipLaunchKernelGGL((k_partials<S, SHAK, LIM, false>), g, dim3(256), xy, st, p);
 }
 
 hipError_t launch_partials(const Params &p, bool fp32, hipStream_t st) {
@@ -2561,13 +2572,13 @@ hipError_t launch_face_records(const Params &p, bool fp32, hipStream_t st) {
 template <class S, bool SHAK>
 static void launch_flux_t(const Params &p, hipStream_t st) {
     const dim3 g = chunk_grid(p, p.nch);
-    const size_t tl = (size_t)4 * (p.nvx + p.nvy) * sizeof(S);
+    const size_t xy = (size_t)2 * (p.nvx + p.nvy) * sizeof(double), tl = (size_t)4 * (p.nvx + p.nvy) * sizeof(S);
     if (p.prep_in_flux) {  // one chunk per cell (checked by the caller)
-        if (tl <= 16384) hipLaunchKernelGGL((k_flux<S, SHAK, true, true>), g, dim3(256), tl, st, p);
-        else hipLaunchKernelGGL((k_flux<S, SHAK, false, true>), g, dim3(256), 0, st, p);
+        if (tl <= 16384) hipLaunchKernelGGL((k_flux<S, SHAK, true, true>), g, dim3(256), xy + tl, st, p);
+        else hipLaunchKernelGGL((k_flux<S, SHAK, false, true>), g, dim3(256), xy, st, p);
     } else {
-        if (tl <= 16384) hipLaunchKernelGGL((k_flux<S, SHAK, true, false>), g, dim3(256), tl, st, p);
-        else hipLaunchKernelGGL((k_flux<S, SHAK, false, false>), g, dim3(256), 0, st, p);
+        if (tl <= 16384) hipLaunchKernelGGL((k_flux<S, SHAK, true, false>), g, dim3(256), xy + tl, st, p);
+        else hipLaunchKernelGGL((k_flux<S, SHAK, false, false>), g, dim3(256), xy, st, p);
     }
 }
 
