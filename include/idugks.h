@@ -51,7 +51,9 @@ typedef enum {
     IDUGKS_E_INVALID = 1,        /* bad argument or configuration; nothing was done */
     IDUGKS_E_NOMEM = 2,          /* workspace too small (host allocation failure) */
     IDUGKS_E_DEVICE = 3,         /* a HIP call failed */
-    IDUGKS_E_DIVERGED = 4,       /* non-physical state (rho <= 0, T <= 0 or NaN) */
+    IDUGKS_E_DIVERGED = 4,       /* non-physical state (rho <= 0, T <= 0 or NaN), or in
+                                    idugks_solve a residual that kept growing
+                                    (idugks_config.diverge_iters) */
     IDUGKS_E_NOT_CONVERGED = 5,  /* iteration limit reached; the state stays valid */
     IDUGKS_E_STATE = 6           /* call not allowed in the current state */
 } idugks_status;
@@ -118,6 +120,11 @@ typedef struct {
                                     IDUGKS_SWEEPS_HYPERPLANES (2) both by i+j hyperplanes
                                     (structured meshes that fit the LDS-resident fronts).
                                     Unstructured meshes take AUTO or LEVELS (both by levels). */
+    int32_t diverge_iters;       /* idugks_solve stops with IDUGKS_E_DIVERGED once the
+                                    residual has grown in this many consecutive iterations,
+                                    before the state turns non-physical; 0 = never on growth
+                                    alone (the non-physical-state check always applies).
+                                    The state stays valid and can be read or replaced. */
 } idugks_config;
 
 typedef struct {
@@ -177,7 +184,9 @@ idugks_status idugks_velocities(idugks_ctx *ctx, double *xi, double *eta, double
 idugks_status idugks_step(idugks_ctx *ctx, int32_t mode, int32_t nsteps, double *res_out);
 
 /* Implicit iterations until res < tol or max_iter.  iters, res_out: host (may be NULL).
-   Returns IDUGKS_E_NOT_CONVERGED at the iteration limit. */
+   Returns IDUGKS_E_NOT_CONVERGED at the iteration limit, IDUGKS_E_DIVERGED on a
+   non-physical state or, with diverge_iters > 0, when the residual has grown in that many
+   consecutive iterations (iters and res_out then give the iteration it stopped at). */
 idugks_status idugks_solve(idugks_ctx *ctx, double tol, int32_t max_iter, int32_t *iters,
                            double *res_out);
 

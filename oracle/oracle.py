@@ -14,6 +14,17 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+def build_sanitized(out_path):
+    """The oracle compiled with AddressSanitizer and UndefinedBehaviorSanitizer (host code,
+    serial: no OpenMP; the first error aborts), for a test that loads it in a child process
+    through IDUGKS_ORACLE_LIB with the ASan runtime preloaded."""
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-o", out_path, _SRC, "-lm"]
+    subprocess.run(cmd, check=True, cwd=_HERE)
+    return out_path
+
+
 def build(force=True):
     """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP over independent loops)."""
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
@@ -58,9 +69,12 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build(force=True)
-    lib = C.CDLL(_LIB)
+    path = os.environ.get("IDUGKS_ORACLE_LIB")  # another build of the same source
+    if path is None:
+        path = _LIB
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+    lib = C.CDLL(path)
     sig = {
         "orc_create": (C.c_int, [C.POINTER(OrcConfig), C.POINTER(_P)]),
         "orc_create_mesh": (C.c_int, [C.POINTER(OrcConfig), C.POINTER(OrcMesh), C.POINTER(_P)]),

@@ -40,7 +40,7 @@ class Config(C.Structure):
         ("cfl_start", C.c_double), ("cfl_growth", C.c_double),
         ("nnodes", C.c_int32), ("ncells", C.c_int32),
         ("cell_nodes", C.POINTER(C.c_int32)), ("side_tag", C.POINTER(C.c_int32)),
-        ("sweep_order", C.c_int32),
+        ("sweep_order", C.c_int32), ("diverge_iters", C.c_int32),
     ]
 
 
@@ -118,7 +118,8 @@ def make_config(cfg):
 
     A "mesh" entry (xn, yn, cell_nodes [nc, 4], side_tag [nc, 4]) selects an unstructured
     mesh; "sweep_order" (SWEEPS_AUTO, SWEEPS_LEVELS, SWEEPS_HYPERPLANES) how the sweeps walk
-    the cell order."""
+    the cell order; "diverge_iters" the consecutive residual growths after which a solve
+    stops as diverged (0: off)."""
     import numpy as np
     mesh = cfg.get("mesh")
     src = cfg if mesh is None else mesh
@@ -140,6 +141,7 @@ def make_config(cfg):
         c.side_tag = tg.ctypes.data_as(C.POINTER(C.c_int32))
         keep += [cn, tg]
     c.sweep_order = int(cfg.get("sweep_order", SWEEPS_AUTO))
+    c.diverge_iters = int(cfg.get("diverge_iters", 0))
     c.xn, c.yn = xn.ctypes.data_as(_D), yn.ctypes.data_as(_D)
     for s in range(4):
         c.bc[s] = cfg["bc"][s]

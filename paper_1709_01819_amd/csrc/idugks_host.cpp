@@ -217,6 +217,7 @@ idugks_status validate(const idugks_config *c) {
     const bool um = c->cell_nodes != nullptr;
     if (c->sweep_order < IDUGKS_SWEEPS_AUTO || c->sweep_order > IDUGKS_SWEEPS_HYPERPLANES)
         return fail(IDUGKS_E_INVALID, "sweep_order must be IDUGKS_SWEEPS_AUTO, _LEVELS or _HYPERPLANES");
+    if (c->diverge_iters < 0) return fail(IDUGKS_E_INVALID, "diverge_iters must be >= 0");
     if (um) {
         if (c->ncells < 1 || c->nnodes < 3 || !c->side_tag)
             return fail(IDUGKS_E_INVALID, "unstructured mesh needs ncells >= 1, nnodes >= 3 and side_tag");
@@ -1327,13 +1328,20 @@ idugks_status idugks_step(idugks_ctx *x, int32_t mode, int32_t nsteps, double *r
 idugks_status idugks_solve(idugks_ctx *x, double tol, int32_t max_iter, int32_t *iters, double *res_out) {
     if (!x) return fail(IDUGKS_E_INVALID, "null context");
     if (!(tol > 0) || max_iter < 0) return fail(IDUGKS_E_INVALID, "bad tolerance or iteration limit");
-    double r = INFINITY;
-    int n = 0;
+    double r = INFINITY, prev = INFINITY;
+    int n = 0, grown = 0;
     idugks_status s = IDUGKS_OK;
     while (n < max_iter) {
         s = idugks_step(x, IDUGKS_IMPLICIT, 1, &r);
         ++n;
         if (s != IDUGKS_OK || r < tol) break;
+        // a residual that keeps growing: stop while the state is still physical
+        grown = r > prev ? grown + 1 : 0;
+        prev = r;
+        if (x->cfg.diverge_iters > 0 && grown >= x->cfg.diverge_iters) {
+            s = fail(IDUGKS_E_DIVERGED, "residual grew in " + std::to_string(grown) + " consecutive iterations");
+            break;
+        }
     }
     if (iters) *iters = n;
     if (res_out) *res_out = r;

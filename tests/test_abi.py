@@ -67,6 +67,7 @@ def test_workspace_size_scales_with_precision():
     ("nvx", 1, "nv >= 2"), ("model", 7, "model"), ("precision", 3, "precision"),
     ("cfl_imp", 0.0, "CFL"), ("limiter", 5, "limiter"), ("predictor", 2, "predictor"),
     ("relax_sweeps", -1, "relax_sweeps"), ("relax_sweeps", 65, "relax_sweeps"),
+    ("diverge_iters", -1, "diverge_iters"),
 ])
 def test_invalid_configs_rejected(field, value, msg):
     cfg = wl.case("couette")

@@ -197,6 +197,22 @@ def test_kn10_cavity_128_history_and_divergence():
             break
     assert fail_o is not None and fail_o == fail_g
     np.testing.assert_allclose(rg[:20], ro[:20], rtol=1e-6)
+    # with diverge_iters the solve stops on the residual's growth, at the first iteration
+    # where it has grown that many times in a row (found in the oracle's history), while
+    # the state is still physical
+    n_div = 3
+    grown, stop = 0, None
+    for k in range(1, len(ro)):
+        grown = grown + 1 if ro[k] > ro[k - 1] else 0
+        if grown >= n_div:
+            stop = k + 1
+            break
+    assert stop is not None and stop < fail_o
+    s = _solver(dict(cfg, diverge_iters=n_div))  # from the same initial state
+    with pytest.raises(IdugksError, match="residual grew"):
+        s.solve(1e-12, 40)
+    assert s.info().iterations == stop
+    assert np.all(np.isfinite(s.get_state()))
 
 
 @pytest.mark.parametrize("name", ["cavity_kn10", "cylinder_ma5"])
