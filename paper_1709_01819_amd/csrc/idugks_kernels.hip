@@ -30,6 +30,17 @@ namespace idugks {
 // helpers
 // ---------------------------------------------------------------------------------------
 
+// The velocity index v = ix nvy + iy split into its 1-D indices without a table: the FP32
+// quotient v (1/nvy) is within 1 of v / nvy for every velocity set the library accepts
+// (v < 2^24: a relative error of a few 2^-24 on a quotient below 4096), and one step on the
+// integer remainder makes it exact.
+DEV void split_velocity(int v, int nvy, float rnvy, int &ix, int &iy) {
+    ix = (int)((float)v * rnvy);
+    iy = v - ix * nvy;
+    if (iy < 0) { --ix; iy += nvy; }
+    else if (iy >= nvy) { ++ix; iy -= nvy; }
+}
+
 // element of a row at a 32-bit byte offset: a wave-uniform row base plus a per-lane
 // offset that fits the load's 32-bit offset field
 template <class S>
@@ -620,11 +631,14 @@ __global__ __launch_bounds__(256) void k_partials(Params p) {
         fvrow[s] = (S *)p.fv + (size_t)__builtin_amdgcn_readfirstlane(ps.face[s]) * 2 * nvp;
     }
     const S *frow0 = (const S *)p.f + (size_t)c * 2 * nvp;
+    const int nvy = p.nvy;
+    const float rnvy = 1.0f / (float)nvy;
     for (int v = v0 + tid; v < v1; v += blockDim.x) {
         // keep the staged records in LDS, read per iteration (hoisted, the five records
         // would hold about 120 registers and halve the occupancy); emits no code
         asm volatile("" ::: "memory");
-        const int ix = p.vix[v], iy = p.viy[v];
+        int ix, iy;
+        split_velocity(v, nvy, rnvy, ix, iy);
         const double xd = xy[ix], yd = xy[nvx + iy];
         const T x = (T)xd, y = (T)yd;
         // rows are a block-uniform base plus the lane's 32-bit byte offset
@@ -852,10 +866,13 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
         gwrow[s] = p.gw + (size_t)ws * nvp;
         wkrt[s] = (T)p.wKRT[ws];
     }
+    const int nvy = p.nvy;
+    const float rnvy = 1.0f / (float)nvy;
     for (int v = v0 + tid; v < v1; v += blockDim.x) {
         // keep the staged records in LDS, read per iteration (emits no code)
         asm volatile("" ::: "memory");
-        const int ix = p.vix[v], iy = p.viy[v];
+        int ix, iy;
+        split_velocity(v, nvy, rnvy, ix, iy);
         const double xd = xy[ix], yd = xy[nvx + iy];
         const T x = (T)xd, y = (T)yd;
         const unsigned ov = (unsigned)v * sizeof(S), oh = (unsigned)(nvp + v) * sizeof(S);
