@@ -868,50 +868,74 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
     }
     const int nvy = p.nvy;
     const float rnvy = 1.0f / (float)nvy;
-    for (int v = v0 + tid; v < v1; v += blockDim.x) {
+    // two velocities per lane and iteration (v and v + blockDim), which share each side's
+    // record read from LDS
+    constexpr int VU = 2;
+    const int B = blockDim.x;
+    for (int v00 = v0 + tid; v00 < v1; v00 += VU * B) {
         // keep the staged records in LDS, read per iteration (emits no code)
         asm volatile("" ::: "memory");
-        int ix, iy;
-        split_velocity(v, nvy, rnvy, ix, iy);
-        const double xd = xy[ix], yd = xy[nvx + iy];
-        const T x = (T)xd, y = (T)yd;
-        const unsigned ov = (unsigned)v * sizeof(S), oh = (unsigned)(nvp + v) * sizeof(S);
+        int vv[VU], ix[VU], iy[VU];
+        bool ok[VU];
+        double xd[VU], yd[VU];
+        T x[VU], y[VU];
+        unsigned ov[VU], oh[VU];
+#pragma unroll
+        for (int u = 0; u < VU; ++u) {
+            ok[u] = v00 + u * B < v1;
+            vv[u] = ok[u] ? v00 + u * B : v00;
+            split_velocity(vv[u], nvy, rnvy, ix[u], iy[u]);
+            xd[u] = xy[ix[u]];
+            yd[u] = xy[nvx + iy[u]];
+            x[u] = (T)xd[u];
+            y[u] = (T)yd[u];
+            ov[u] = (unsigned)vv[u] * sizeof(S);
+            oh[u] = (unsigned)(nvp + vv[u]) * sizeof(S);
+        }
         // every side's stored face values first (they depend only on the velocity; a
         // boundary face's value is read whichever way the velocity points and used only
         // where this cell is upwind), then the classification and the arithmetic
-        T fG[4], fH[4];
+        T fG[VU][4], fH[VU][4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             if (tys[s] == FT_SELF) continue;
-            fG[s] = at(fvrow[s], ov);
-            fH[s] = at(fvrow[s], oh);
+#pragma unroll
+            for (int u = 0; u < VU; ++u) {
+                fG[u][s] = at(fvrow[s], ov[u]);
+                fH[u][s] = at(fvrow[s], oh[u]);
+            }
         }
-        T un[4];
+        T un[VU][4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int type = tys[s];
             if (type == FT_SELF) continue;
-            // an interior face's value is the stored reconstruction whichever cell is
-            // upwind, so only boundary faces classify the velocity (with the tie rule,
-            // in FP64); tangent velocities carry no flux either way
-            if (type == FT_INTERIOR) {
-                un[s] = x * fs.nxT[s] + y * fs.nyT[s];
-                continue;
-            }
-            const double und = normal_speed(xd, yd, fs.nx[s], fs.ny[s]);
-            un[s] = (T)und;
-            if (und > 0.0 || (und == 0.0 && tis[s])) continue;  // reconstructed by this cell
-            if (type == FT_WALL) {
-                const T rw = fs.rec[s][13];
-                const T g = (T)gwrow[s][v];
-                fG[s] = rw * g;
-                fH[s] = rw * wkrt[s] * g;
-            } else {
-                fG[s] = (T)p.ginf[v];
-                fH[s] = (T)p.hinf[v];
+#pragma unroll
+            for (int u = 0; u < VU; ++u) {
+                // an interior face's value is the stored reconstruction whichever cell is
+                // upwind, so only boundary faces classify the velocity (with the tie rule,
+                // in FP64); tangent velocities carry no flux either way
+                if (type == FT_INTERIOR) {
+                    un[u][s] = x[u] * fs.nxT[s] + y[u] * fs.nyT[s];
+                    continue;
+                }
+                const double und = normal_speed(xd[u], yd[u], fs.nx[s], fs.ny[s]);
+                un[u][s] = (T)und;
+                if (und > 0.0 || (und == 0.0 && tis[s])) continue;  // reconstructed by this cell
+                if (type == FT_WALL) {
+                    const T rw = fs.rec[s][13];
+                    const T g = (T)gwrow[s][vv[u]];
+                    fG[u][s] = rw * g;
+                    fH[u][s] = rw * wkrt[s] * g;
+                } else {
+                    fG[u][s] = (T)p.ginf[vv[u]];
+                    fH[u][s] = (T)p.hinf[vv[u]];
+                }
             }
         }
-        T accG = T(0), accH = T(0);
+        T accG[VU], accH[VU];
+#pragma unroll
+        for (int u = 0; u < VU; ++u) accG[u] = accH[u] = T(0);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             if (tys[s] == FT_SELF) continue;
@@ -919,22 +943,29 @@ __global__ __launch_bounds__(256) void k_flux(Params p) {
             RecT<T> rf;
             rf.U = r[0]; rf.V = r[1]; rf.c0 = r[2]; rf.c1 = r[3]; rf.c2c = r[4]; rf.c3 = r[5];
             rf.kqx = r[6]; rf.kqy = r[7]; rf.iRT = r[8]; rf.KRT = r[9]; rf.ab = r[10]; rf.bb = r[11];
+            const T al = r[12], ST = fs.ST[s];
             const S *tf = TL ? (const S *)lt + s * TW : (const S *)p.tabf + (size_t)__builtin_amdgcn_readfirstlane(fs.face[s]) * TW;
-            T eG, eH;
-            eq_eval<T, SHAK>(rf, x, y, (T)tf[ix] * (T)tf[nvx + iy], eG, eH);
-            const T al = r[12];
-            const T pG = al * fG[s] + (T(1) - al) * eG, pH = al * fH[s] + (T(1) - al) * eH;
-            const T fl = fs.ST[s] * un[s];
-            accG -= fl * pG;
-            accH -= fl * pH;
+#pragma unroll
+            for (int u = 0; u < VU; ++u) {
+                T eG, eH;
+                eq_eval<T, SHAK>(rf, x[u], y[u], (T)tf[ix[u]] * (T)tf[nvx + iy[u]], eG, eH);
+                const T pG = al * fG[u][s] + (T(1) - al) * eG, pH = al * fH[u][s] + (T(1) - al) * eH;
+                const T fl = ST * un[u][s];
+                accG[u] -= fl * pG;
+                accH[u] -= fl * pH;
+            }
         }
-        MG[v] = (S)accG;
-        MH[v] = (S)accH;
-        const double wv = wxy[ix] * wxy[nvx + iy], dG = (double)accG;
-        mw[0] += wv * dG;
-        mw[1] += wv * xd * dG;
-        mw[2] += wv * yd * dG;
-        mw[3] += 0.5 * wv * ((xd * xd + yd * yd) * dG + (double)accH);
+#pragma unroll
+        for (int u = 0; u < VU; ++u) {
+            if (!ok[u]) continue;
+            MG[vv[u]] = (S)accG[u];
+            MH[vv[u]] = (S)accH[u];
+            const double wv = wxy[ix[u]] * wxy[nvx + iy[u]], dG = (double)accG[u];
+            mw[0] += wv * dG;
+            mw[1] += wv * xd[u] * dG;
+            mw[2] += wv * yd[u] * dG;
+            mw[3] += 0.5 * wv * ((xd[u] * xd[u] + yd[u] * yd[u]) * dG + (double)accH[u]);
+        }
     }
     if (PREP) {
         block_sum<4, true>(mw, sh);
