@@ -1816,99 +1816,191 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p, const int *__re
     }
 }
 
-// Macro LU-SGS sweeps (Eq. 29-31) level by level in one block: one lane per cell of a
-// level, forward then backward.  A cell's own data (M_W, 1/D, side codes, side geometry;
-// its index and its neighbours' cells and positions) do not depend on the sweep, so each
-// lane loads them for its cell of the next level while it works on the current one; a
-// level then waits for one round of loads, its coupled neighbours' W and sound speed
-// (their macro rows) and increments (dW in cell order: dW* after the forward sweep, dW
-// after the backward one).
-constexpr int GM_THREADS = 256;
+// Macro LU-SGS sweeps (Eq. 29-31) level by level in one block, the work split across
+// waves so that none of them waits for its own stores: the compute waves take a phase of
+// at most G2_PH cells of a level, four lanes per cell (one side each, the parts summed by
+// DPP quad swaps), and touch only LDS; the loader waves stage the next phase's rows (own
+// data, and per position the W and sound speed its neighbours need) into LDS; the writer
+// wave copies the increments of the previous phase from LDS to HBM (dW* into the macro
+// rows, where the backward sweep's loader finds them in position order; dW by cell).  Per
+// position an LDS ring of G2_RS slots (slot = position mod G2_RS) holds W, c, the
+// increment and the cell; a neighbour older than the ring's window is read from HBM (its
+// macro row and dW, flushed long before).  Positions are staged and computed in increasing
+// order in the forward sweep and in decreasing order in the backward one, a phase being at
+// most G2_PH consecutive positions, so a slot holds the position last written to it.
+constexpr int G2_PH = 128;                     // cells per phase
+constexpr int G2_CW = 4 * G2_PH / 64;          // compute waves: four lanes per cell
+constexpr int G2_LW = G2_PH / 64;              // loader waves: one position per lane
+constexpr int G2_THREADS = 64 * (G2_CW + G2_LW + 1);
+constexpr int G2_RS = 1024;
+static_assert(3 * G2_PH <= G2_RS && (G2_RS & (G2_RS - 1)) == 0, "ring too small");
 
-struct GMOwn {
+struct G2Row {  // a cell's own data in its phase
     double mw[4], iD, geo[12];
     int codes, c, nb[4], np[4];
 };
 
-DEV void gm_load(const Params &p, int pos, GMOwn &o) {
-    const double *m = p.mh + (size_t)pos * MH_N;
-    const int *g = p.grow + (size_t)pos * GR_N;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) o.mw[a] = m[a];
-    o.iD = m[4];
-    o.codes = (int)m[5];
-#pragma unroll
-    for (int e = 0; e < 12; ++e) o.geo[e] = m[MH_SIDE + e];
-    o.c = g[GR_CELL];
-#pragma unroll
-    for (int sd = 0; sd < 4; ++sd) {
-        o.nb[sd] = g[GR_NB + sd];
-        o.np[sd] = g[GR_NPOS + sd];
+struct G2Ring {  // per position, for its neighbours
+    double W[4], C, dW[4];
+    int cell;
+};
+
+// the phases of one sweep: round r of level t (levels in sweep order); s, cnt its positions
+struct G2Phase {
+    int t, r, s, cnt;
+};
+
+DEV bool g2_set(const Params &p, bool upper, G2Phase &ph) {
+    if (ph.t >= p.nlev) return false;
+    const int l = upper ? p.nlev - 1 - ph.t : ph.t;
+    const int off = p.hp_off[l], n = p.hp_off[l + 1] - off;
+    if (upper) {  // a level's rounds from its far end
+        const int e = off + n - ph.r * G2_PH;
+        ph.s = e - G2_PH > off ? e - G2_PH : off;
+        ph.cnt = e - ph.s;
+    } else {
+        ph.s = off + ph.r * G2_PH;
+        ph.cnt = n - ph.r * G2_PH < G2_PH ? n - ph.r * G2_PH : G2_PH;
+    }
+    return true;
+}
+
+DEV void g2_next(const Params &p, bool upper, G2Phase &ph) {
+    const int l = upper ? p.nlev - 1 - ph.t : ph.t;
+    const int n = p.hp_off[l + 1] - p.hp_off[l];
+    if ((ph.r + 1) * G2_PH < n) {
+        ++ph.r;
+    } else {
+        ++ph.t;
+        ph.r = 0;
     }
 }
 
-__global__ __launch_bounds__(GM_THREADS) void k_gmacro(Params p) {
+__global__ __launch_bounds__(G2_THREADS) void k_gmacro(Params p) {
+    __shared__ G2Row stage[2][G2_PH];
+    __shared__ G2Ring ring[G2_RS];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int role = wave < G2_CW ? 0 : wave < G2_CW + G2_LW ? 1 : 2;  // compute, loader, writer
     const double ik2 = 1.0 / (p.K + 2);
-    const int nlev = p.nlev, tid = threadIdx.x;
+    // loader: the rows of phase ph into stage buffer b and the ring (the macro row holds
+    // M_W in the forward sweep and, written there by the forward sweep, dW* in the backward one)
+    auto stage_phase = [&](const G2Phase &ph, int b) {
+        const int k = tid - 64 * G2_CW;
+        if (k >= ph.cnt) return;
+        const int pos = ph.s + k;
+        const double *m = p.mh + (size_t)pos * MH_N;
+        const int *g = p.grow + (size_t)pos * GR_N;
+        G2Row &o = stage[b][k];
+        const int c = g[GR_CELL];
+        o.c = c;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) o.mw[a] = m[a];
+        o.iD = m[4];
+        o.codes = (int)m[5];
+#pragma unroll
+        for (int e = 0; e < 12; ++e) o.geo[e] = m[MH_SIDE + e];
+#pragma unroll
+        for (int sd = 0; sd < 4; ++sd) {
+            o.nb[sd] = g[GR_NB + sd];
+            o.np[sd] = g[GR_NPOS + sd];
+        }
+        G2Ring &q = ring[pos & (G2_RS - 1)];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) q.W[a] = m[6 + a];
+        q.C = m[10];
+        q.cell = c;
+    };
+    // writer: the increments of phase ph: dW* into the macro rows (position order) in the
+    // forward sweep, dW (cell order) in the backward one
+    auto flush = [&](const G2Phase &ph, bool upper) {
+        for (int k = lane; k < ph.cnt; k += 64) {
+            const int pos = ph.s + k;
+            const G2Ring &q = ring[pos & (G2_RS - 1)];
+            double *dst = upper ? p.dW + (size_t)q.cell * 4 : p.mh + (size_t)pos * MH_N;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) dst[a] = q.dW[a];
+        }
+    };
     for (int dir = 0; dir < 2; ++dir) {
         const bool upper = dir == 1;
         const int need = upper ? SG_UPPER : SG_LOWER;
-        auto lev = [&](int t) { return upper ? nlev - 1 - t : t; };
-        // the lane's cell k of level t's first round (a level's first cell past its end)
-        auto load = [&](GMOwn &o, int t, int k) {
-            const int l = lev(t), off = p.hp_off[l], n = p.hp_off[l + 1] - off;
-            gm_load(p, off + (k < n ? k : 0), o);
-        };
-        GMOwn cur, nxt;
-        load(cur, 0, tid);
-        for (int t = 0; t < nlev; ++t) {
-            const int l = lev(t), n = p.hp_off[l + 1] - p.hp_off[l];
-            for (int k0 = 0; k0 < n; k0 += GM_THREADS) {
-                if (k0 > 0) load(cur, t, k0 + tid);
-                const bool live = k0 + tid < n;
-                // this cell's coupled neighbours: W, sound speed and increment
-                double Wj[4][4], Cj[4], dWj[4][4], dWc[4];
-                bool use[4];
+        G2Phase cur{0, 0, 0, 0}, prev{0, 0, 0, 0};
+        g2_set(p, upper, cur);
+        if (role == 1) stage_phase(cur, 0);
+        __syncthreads();
+        bool has_prev = false;
+        for (int i = 0;; ++i) {
+            G2Phase nxt = cur;
+            g2_next(p, upper, nxt);
+            const bool has_next = g2_set(p, upper, nxt);
+            if (role == 0) {
+                // lane 4k + sd: side sd of cell k (the quad's lanes stay together for the sums)
+                const int k = tid >> 2, sd = tid & 3;
+                const bool live = k < cur.cnt;
+                const G2Row &o = stage[i & 1][live ? k : 0];
+                double r[4] = {0.0, 0.0, 0.0, 0.0};
+                if (live && ((o.codes >> (MH_CODE_BITS * sd)) & need)) {
+                    const int pj = o.np[sd];
+                    // in the ring unless its slot has been (or is being) reused by a later
+                    // position: the staging of the next phase reaches at most G2_PH
+                    // positions past this one
+                    const bool in = upper ? pj < cur.s - G2_PH + G2_RS : pj >= cur.s + 2 * G2_PH - G2_RS;
+                    double Wj[4], dWj[4], Cj;
+                    const double *mj = p.mh + (size_t)pj * MH_N;
+                    if (in) {
+                        const G2Ring &q = ring[pj & (G2_RS - 1)];
 #pragma unroll
-                for (int sd = 0; sd < 4; ++sd) {
-                    use[sd] = live && ((cur.codes >> (MH_CODE_BITS * sd)) & need);
-                    if (!use[sd]) continue;
-                    const double *mj = p.mh + (size_t)cur.np[sd] * MH_N;
-                    const double *dj = p.dW + (size_t)cur.nb[sd] * 4;
+                        for (int a = 0; a < 4; ++a) {
+                            Wj[a] = q.W[a];
+                            dWj[a] = q.dW[a];
+                        }
+                        Cj = q.C;
+                    } else {  // flushed long before: dW* in the row, dW by cell
+                        const double *dj = upper ? p.dW + (size_t)o.nb[sd] * 4 : mj;
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        Wj[sd][a] = mj[6 + a];
-                        dWj[sd][a] = dj[a];
+                        for (int a = 0; a < 4; ++a) {
+                            Wj[a] = mj[6 + a];
+                            dWj[a] = dj[a];
+                        }
+                        Cj = mj[10];
                     }
-                    Cj[sd] = mj[10];
+                    const double nx = o.geo[MH_SN * sd], ny = o.geo[MH_SN * sd + 1];
+                    const double hS = 0.5 * o.geo[MH_SN * sd + 2];
+                    double Wn[4], F0[4], F1[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) Wn[a] = Wj[a] + dWj[a];
+                    const double lam = fabs(euler_flux_n(Wj, nx, ny, ik2, F0)) + Cj;
+                    euler_flux_n(Wn, nx, ny, ik2, F1);
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) r[a] = hS * (F1[a] - F0[a] - lam * dWj[a]);
                 }
-                if (upper && live)
+                // the four sides' parts: (side 0 + side 1) + (side 2 + side 3) in every lane
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) dWc[a] = p.dW[(size_t)cur.c * 4 + a];
-                if (k0 + GM_THREADS >= n && t + 1 < nlev) load(nxt, t + 1, tid);
-                if (live) {
-                    double r[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int sd = 0; sd < 4; ++sd) {
-                        if (!use[sd]) continue;
-                        const double nx = cur.geo[MH_SN * sd], ny = cur.geo[MH_SN * sd + 1];
-                        const double hS = 0.5 * cur.geo[MH_SN * sd + 2];
-                        double Wn[4], F0[4], F1[4];
-#pragma unroll
-                        for (int a = 0; a < 4; ++a) Wn[a] = Wj[sd][a] + dWj[sd][a];
-                        const double lam = fabs(euler_flux_n(Wj[sd], nx, ny, ik2, F0)) + Cj[sd];
-                        euler_flux_n(Wn, nx, ny, ik2, F1);
-#pragma unroll
-                        for (int a = 0; a < 4; ++a) r[a] += hS * (F1[a] - F0[a] - lam * dWj[sd][a]);
-                    }
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-                        p.dW[(size_t)cur.c * 4 + a] = upper ? dWc[a] - r[a] * cur.iD : (cur.mw[a] - r[a]) * cur.iD;
+                for (int a = 0; a < 4; ++a) {
+                    r[a] += quad_swap<0xB1>(r[a]);
+                    r[a] += quad_swap<0x4E>(r[a]);
                 }
+                if (live) {  // lane sd finishes component sd
+                    const double ra = sd == 0 ? r[0] : sd == 1 ? r[1] : sd == 2 ? r[2] : r[3];
+                    const double ma = sd == 0 ? o.mw[0] : sd == 1 ? o.mw[1] : sd == 2 ? o.mw[2] : o.mw[3];
+                    // forward dW* = (M_W - r)/D, backward dW = dW* - r/D
+                    ring[(cur.s + k) & (G2_RS - 1)].dW[sd] = upper ? ma - ra * o.iD : (ma - ra) * o.iD;
+                }
+            } else if (role == 1) {
+                if (has_next) stage_phase(nxt, (i + 1) & 1);
+            } else if (has_prev) {
+                flush(prev, upper);
             }
             __syncthreads();
+            if (!has_next) break;
+            prev = cur;
+            has_prev = true;
             cur = nxt;
         }
+        // the last phase's increments (the forward sweep's before the backward sweep stages
+        // its rows)
+        if (role == 2) flush(cur, upper);
+        __syncthreads();
     }
 }
 
@@ -2704,7 +2796,7 @@ hipError_t launch_macro_relax(const Params &p, hipStream_t st) {
 
 hipError_t launch_macro(const Params &p, hipStream_t st) {
     if (p.gmacro) {
-        hipLaunchKernelGGL(k_gmacro, dim3(1), dim3(GM_THREADS), 0, st, p);
+        hipLaunchKernelGGL(k_gmacro, dim3(1), dim3(G2_THREADS), 0, st, p);
         return hipGetLastError();
     }
     const MacroShape m = macro_shape(p.ni, p.nj, p.per_i, p.per_j);
