@@ -2858,10 +2858,12 @@ static hipError_t sweep_launch_v(const Params &p, const SweepShape &sh, hipStrea
     return sweep_launch<S, SHAK, UPPER, false, 1>(p, sh, st);
 }
 
-// cells per wave and batch: the FP32 state leaves registers for four, FP64 for two
+// cells per wave and batch within the 128 registers of a 16-wave block: FP32 eight in the
+// backward sweep (a level of up to 128 cells in one batch) and six in the forward one
+// (which also holds the batch's results for its stores), FP64 three
 template <class S, bool SHAK, bool UPPER>
 static hipError_t gsweep_launch(const Params &p, hipStream_t st) {
-    constexpr int CB = sizeof(S) == 4 ? 6 : 3;
+    constexpr int CB = sizeof(S) == 4 ? (UPPER ? 8 : 6) : 3;
     hipLaunchKernelGGL((k_gsweep<S, SHAK, UPPER, CB>), dim3(p.nvp / 64), dim3(GS_THREADS), 0, st, p,
                        p.grow, (const S *)p.growT);
     return hipGetLastError();
