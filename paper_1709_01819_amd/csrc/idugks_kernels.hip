@@ -2004,36 +2004,56 @@ __global__ __launch_bounds__(G2_THREADS) void k_gmacro(Params p) {
     }
 }
 
-// wall ghost density increment of each wall face from the forward-sweep G increment
+// wall ghost density increment of each wall face from the forward-sweep G increment: one
+// wave per wall face, the block's FR_W faces sharing the velocity set staged into LDS a
+// chunk at a time (as in the face records); a lane takes the velocities lane, lane + 64, ...
 template <class S>
-__global__ __launch_bounds__(256) void k_wall_ghost(Params p) {
+__global__ __launch_bounds__(64 * FR_W) void k_wall_ghost(Params p) {
+    constexpr int PER = FR_CH / 64;
+    __shared__ double vx[FR_CH], vy[FR_CH], vw[FR_CH];
     const int lane = threadIdx.x & 63;
-    const int wi = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wi >= p.nwall) return;
-    const int k = p.wall_faces[wi];
-    const Face F = p.faces[k];
-    const S *d = (const S *)p.d1 + ((size_t)F.L * 2) * p.nvp;
-    double a[1] = {0.0};
-    // four velocities per lane and pass (four passes of loads in flight per wave)
-    for (int v0 = lane; v0 < p.nv; v0 += 256) {
-        double un[4], ws[4], ds[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int v = v0 + 64 * u, vc = v < p.nv ? v : 0;
-            un[u] = v < p.nv ? p.xi[vc] * F.nx + p.eta[vc] * F.ny : 0.0;
-            ws[u] = p.w[vc];
-            ds[u] = (double)d[vc];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (un[u] > 0.0) a[0] += ws[u] * un[u] * ds[u];
+    const int wi = blockIdx.x * FR_W + (threadIdx.x >> 6);
+    const bool live = wi < p.nwall;
+    Face F{};
+    int k = 0;
+    if (live) {
+        k = p.wall_faces[wi];
+        F = p.faces[k];
     }
+    const S *d = (const S *)p.d1 + ((size_t)(live ? F.L : 0) * 2) * p.nvp;
+    double a[1] = {0.0};
+    for (int c0 = 0; c0 < p.nv; c0 += FR_CH) {
+        const int vt = c0 + threadIdx.x;
+        if (vt < p.nv) {
+            vx[threadIdx.x] = p.xi[vt];
+            vy[threadIdx.x] = p.eta[vt];
+            vw[threadIdx.x] = p.w[vt];
+        }
+        __syncthreads();
+        if (live) {
+            S ds[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int v = c0 + 64 * u + lane;
+                ds[u] = d[v < p.nv ? v : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int j = 64 * u + lane;
+                if (c0 + j >= p.nv) continue;
+                const double un = vx[j] * F.nx + vy[j] * F.ny;
+                if (un > 0.0) a[0] += vw[j] * un * (double)ds[u];
+            }
+        }
+        __syncthreads();
+    }
+    if (!live) return;
     wave_sum_dpp<1>(a);
     if (lane == 0) {
-        const double d = -a[0] / p.wden[k];
-        p.drho[k] = d;
-        p.sdrho[(size_t)p.hp_pos[F.L] * 4 + F.sL] = d;
-        if (p.graph) ((S *)p.growT)[(size_t)p.hp_pos[F.L] * GT_N + GT_DRHO + F.sL] = (S)d;
+        const double dr = -a[0] / p.wden[k];
+        p.drho[k] = dr;
+        p.sdrho[(size_t)p.hp_pos[F.L] * 4 + F.sL] = dr;
+        if (p.graph) ((S *)p.growT)[(size_t)p.hp_pos[F.L] * GT_N + GT_DRHO + F.sL] = (S)dr;
     }
 }
 
@@ -2887,8 +2907,8 @@ hipError_t launch_sweep(const Params &p, bool fp32, bool upper, const SweepShape
 
 hipError_t launch_wall_ghost(const Params &p, bool fp32, hipStream_t st) {
     if (p.nwall == 0) return hipSuccess;
-    const dim3 g((p.nwall + 3) / 4);
-    DISPATCH_S(fp32, hipLaunchKernelGGL((k_wall_ghost<S>), g, dim3(256), 0, st, p));
+    const dim3 g((p.nwall + FR_W - 1) / FR_W);
+    DISPATCH_S(fp32, hipLaunchKernelGGL((k_wall_ghost<S>), g, dim3(64 * FR_W), 0, st, p));
     return hipGetLastError();
 }
 
