@@ -750,21 +750,54 @@ idugks_status build(const idugks_config *c, Built &b) {
     // per position of the sweep order: the cell, and per side the neighbour cell, or
     // -1 - t on a boundary side with boundary-condition slot t, or the cell itself (a side
     // without flux)
+    // A coupled neighbour is read from the micro sweeps' LDS ring of RN positions when no
+    // level exceeds RN cells, it lies on an earlier level (forward sweep) or a later one
+    // (backward sweep) than the reading cell, and fewer than RN positions separate it from
+    // the far end of the reading cell's level, so that its slot (position mod RN) has been
+    // written in this sweep and not reused since.  (A cell that couples to itself, across
+    // a periodic direction one cell wide, reads its forward-sweep increment from d1.)
     b.grow.assign((size_t)GR_N * b.nc, 0);
+    const int RN = gs_ring_positions(c->precision == IDUGKS_FP32_MIXED);
+    int lev_max = 0;
+    for (int l = 0; l < b.nlev; ++l) lev_max = std::max(lev_max, b.hp_off[l + 1] - b.hp_off[l]);
+    for (int l = 0; l < b.nlev; ++l)
+        for (int pos = b.hp_off[l]; pos < b.hp_off[l + 1]; ++pos) b.grow[(size_t)GR_N * pos] = l;
     for (int cidx = 0; cidx < b.nc; ++cidx) {
         const int pos = b.hp_pos[cidx];
         int *g = &b.grow[(size_t)GR_N * pos];
+        const int l = g[GR_CELL], lo = b.hp_off[l], hi = b.hp_off[l + 1];
         g[GR_CELL] = cidx;
         int mask = 0;
         for (int sd = 0; sd < 4; ++sd) {
             const CellSide &q = b.cs[(size_t)4 * cidx + sd];
             g[GR_NB + sd] = q.type == FT_SELF ? cidx : q.nb >= 0 ? q.nb : -1 - q.wside;
+            g[GR_SRC + sd] = g[GR_NB + sd];
             const bool coupled = q.type != FT_SELF && q.nb >= 0;
             if (coupled) mask |= q.nb < cidx ? 1 << sd : 1 << (4 + sd);
             if (q.type == FT_WALL) mask |= 1 << (8 + sd);
             g[GR_NPOS + sd] = coupled ? b.hp_pos[q.nb] : pos;
+            if (coupled && lev_max <= RN) {
+                const int qp = b.hp_pos[q.nb];
+                if (q.nb < cidx ? qp < lo && qp + RN >= hi : qp >= hi && qp < lo + RN) {
+                    mask |= 1 << (12 + sd);
+                    g[GR_SRC + sd] = qp;
+                }
+            }
         }
         g[GR_MASK] = mask;
+    }
+    // bit 16: every cell that reads this cell's increment in the backward sweep takes it
+    // from the ring, so the backward sweep need not leave it in d1
+    {
+        std::vector<char> from_d1(b.nc, 0);
+        for (int cidx = 0; cidx < b.nc; ++cidx) {
+            const int *g = &b.grow[(size_t)GR_N * b.hp_pos[cidx]];
+            for (int sd = 0; sd < 4; ++sd)
+                if (((g[GR_MASK] >> (4 + sd)) & 1) && !((g[GR_MASK] >> (12 + sd)) & 1))
+                    from_d1[g[GR_NB + sd]] = 1;
+        }
+        for (int cidx = 0; cidx < b.nc; ++cidx)
+            if (!from_d1[cidx]) b.grow[(size_t)GR_N * b.hp_pos[cidx] + GR_MASK] |= 1 << 16;
     }
     b.sgeo.assign((size_t)b.nc * SG_N, 0.0);
     for (int cidx = 0; cidx < b.nc; ++cidx)

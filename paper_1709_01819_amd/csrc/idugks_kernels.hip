@@ -1634,9 +1634,10 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
 // cells: all loads of a batch are issued before any arithmetic (the stores of one cell
 // would otherwise hold back the loads of the next).  A cell's rows (index row; side
 // geometry, record and ghost increments in the state precision) are scalar loads.  The
-// neighbours' increments come from d1, written by this
-// block on an earlier level (a block barrier separates the levels; the backward sweep also
-// leaves its increments in d1 for that).  Per cell and velocity the arithmetic is the
+// neighbours' increments, written by this block on an earlier level (a block barrier
+// separates the levels), come from an LDS ring of the recent positions, or from d1 for a
+// neighbour older than the ring holds (the backward sweep leaves an increment in d1 only
+// where a later cell reads it from there).  Per cell and velocity the arithmetic is the
 // hyperplane kernel's, in the same order.
 // ---------------------------------------------------------------------------------------
 constexpr int GS_NW = 16, GS_THREADS = 64 * GS_NW;
@@ -1661,6 +1662,19 @@ DEV void growt(const double *gt, double (&r)[GT_N]) {
         r[e] = a.x; r[e + 1] = a.y;
     }
 }
+
+// The slice's recent increments in LDS: a ring of N positions (slot = position mod N),
+// per slot and lane the G and H increments side by side.  With every level at most N
+// cells, a neighbour's slot still holds it while fewer than N positions lie between it and
+// the far end of the current level (in the forward sweep q + N >= off + n, in the backward
+// one q < off + N, for the neighbour's position q and the current level's first position
+// off and size n).  The host marks such sides in the index row; the others are read from
+// d1.
+template <class S>
+struct GsRing {
+    static constexpr int N = gs_ring_positions(sizeof(S) == 4);
+    using V = typename std::conditional<sizeof(S) == 4, float2, double2>::type;
+};
 
 // the loads of one cell of a batch
 template <class S>
@@ -1689,6 +1703,9 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p, const int *__re
     const T sc = (T)p.scal[SC_SCALE];
     S *d1 = (S *)p.d1, *f = (S *)p.f;
     const int nlev = p.nlev;
+    constexpr int RN = GsRing<S>::N;
+    using V2 = typename GsRing<S>::V;
+    __shared__ V2 ring[RN * 64];
     for (int t = 0; t < nlev; ++t) {
         const int l = UPPER ? nlev - 1 - t : t;
         const int off = p.hp_off[l], n = p.hp_off[l + 1] - off;
@@ -1714,9 +1731,16 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p, const int *__re
 #pragma unroll
                 for (int sd = 0; sd < 4; ++sd) {
                     if ((mask >> (UPPER ? 4 + sd : sd)) & 1) {
-                        const S *nr = d1 + (size_t)g[GR_NB + sd] * nv2;
-                        it[b].nG[sd] = at(nr, ov);
-                        it[b].nH[sd] = at(nr, oh);
+                        const int q = g[GR_SRC + sd];
+                        if ((mask >> (12 + sd)) & 1) {  // in the ring: q is the position
+                            const V2 e = ring[(q & (RN - 1)) * 64 + lane];
+                            it[b].nG[sd] = e.x;
+                            it[b].nH[sd] = e.y;
+                        } else {
+                            const S *nr = d1 + (size_t)q * nv2;
+                            it[b].nG[sd] = at(nr, ov);
+                            it[b].nH[sd] = at(nr, oh);
+                        }
                     }
                 }
             }
@@ -1772,7 +1796,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p, const int *__re
                         sH -= ui * q.nH[sd];
                     }
                     if (UPPER && ((mask >> (8 + sd)) & 1)) {
-                        const int j = g[GR_NB + sd];
+                        const int j = g[GR_SRC + sd];
                         {  // inflow through a wall: the ghost's increment
                             // (a cache-resident table, read here to keep the batch's registers)
                             const T gwv = (T)p.gw[(size_t)(-1 - j) * nvp + v];
@@ -1786,10 +1810,13 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p, const int *__re
                 const T dG = UPPER ? q.aG + sG * iD : sG * iD;
                 const T dH = UPPER ? q.aH + sH * iD : sH * iD;
                 if (UPPER) {
+                    ring[((off + k) & (RN - 1)) * 64 + lane] = V2{(S)dG, (S)dH};
                     if (vok) {
                         S *dr = d1 + (size_t)c * nv2, *fr = f + (size_t)c * nv2;
-                        at(dr, ov) = dG;
-                        at(dr, oh) = dH;
+                        if (!((mask >> 16) & 1)) {  // a later cell reads it from d1
+                            at(dr, ov) = dG;
+                            at(dr, oh) = dH;
+                        }
                         at(fr, ov) = (S)(sc * q.bG + dG);
                         at(fr, oh) = (S)(sc * q.bH + dH);
                     }
@@ -1805,7 +1832,9 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p, const int *__re
             if (!UPPER && vok) {
 #pragma unroll
                 for (int b = 0; b < CB; ++b) {
-                    if (base + wave + GS_NW * b >= n) continue;
+                    const int k = base + wave + GS_NW * b;
+                    if (k >= n) continue;
+                    ring[((off + k) & (RN - 1)) * 64 + lane] = V2{(S)rG[b], (S)rH[b]};
                     S *dr = d1 + (size_t)rc[b] * nv2;
                     at(dr, ov) = (S)rG[b];
                     at(dr, oh) = (S)rH[b];
