@@ -1632,7 +1632,7 @@ __global__ __launch_bounds__(1024) void k_sweep(Params p, int vb, int nct) {
 // where the levels are the i+j hyperplanes).  One block of GS_NW waves per slice of 64
 // velocities; wave w takes the cells w, w + GS_NW, ... of a level, in batches of up to CB
 // cells: all loads of a batch are issued before any arithmetic (the stores of one cell
-// would otherwise hold back the loads of the next).  A cell's rows (index row; side
+// would otherwise hold back the loads of the next); each cell stores as it finishes.  A cell's rows (index row; side
 // geometry, record and ghost increments in the state precision) are scalar loads.  The
 // neighbours' increments, written by this block on an earlier level (a block barrier
 // separates the levels), come from an LDS ring of the recent positions, or from d1 for a
@@ -1748,8 +1748,6 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p, const int *__re
             // cell b's arithmetic, so that their scalar loads overlap it
             int gn[8];
             T gtn[GT_N];
-            T rG[CB], rH[CB];
-            int rc[CB];
             {
                 const int k = base + wave < n ? base + wave : 0;
                 grow8(grow + (size_t)(off + k) * GR_N, gn);
@@ -1821,23 +1819,12 @@ __global__ __launch_bounds__(GS_THREADS) void k_gsweep(Params p, const int *__re
                         at(fr, oh) = (S)(sc * q.bH + dH);
                     }
                 } else {
-                    rG[b] = dG;
-                    rH[b] = dH;
-                    rc[b] = c;
-                }
-            }
-            // the forward sweep stores its batch after all of the batch's arithmetic: a store
-            // between two cells makes the next cell wait for it as well as for its loads (the
-            // backward sweep, with four stores per cell, is faster storing as it goes)
-            if (!UPPER && vok) {
-#pragma unroll
-                for (int b = 0; b < CB; ++b) {
-                    const int k = base + wave + GS_NW * b;
-                    if (k >= n) continue;
-                    ring[((off + k) & (RN - 1)) * 64 + lane] = V2{(S)rG[b], (S)rH[b]};
-                    S *dr = d1 + (size_t)rc[b] * nv2;
-                    at(dr, ov) = (S)rG[b];
-                    at(dr, oh) = (S)rH[b];
+                    ring[((off + k) & (RN - 1)) * 64 + lane] = V2{(S)dG, (S)dH};
+                    if (vok) {
+                        S *dr = d1 + (size_t)c * nv2;
+                        at(dr, ov) = dG;
+                        at(dr, oh) = dH;
+                    }
                 }
             }
         }
@@ -2909,7 +2896,8 @@ static hipError_t sweep_launch_v(const Params &p, const SweepShape &sh, hipStrea
 
 // cells per wave and batch within the 128 registers of a 16-wave block: FP32 eight in the
 // backward sweep (a level of up to 128 cells in one batch) and six in the forward one
-// (which also holds the batch's results for its stores), FP64 three
+// (whose cells also load the two Maxwellian factors; seven fill the registers, eight are
+// slower), FP64 three
 template <class S, bool SHAK, bool UPPER>
 static hipError_t gsweep_launch(const Params &p, hipStream_t st) {
     constexpr int CB = sizeof(S) == 4 ? (UPPER ? 8 : 6) : 3;
