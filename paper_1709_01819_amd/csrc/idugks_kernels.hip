@@ -1665,11 +1665,11 @@ DEV void growt(const double *gt, double (&r)[GT_N]) {
 
 // The slice's recent increments in LDS: a ring of N positions (slot = position mod N),
 // per slot and lane the G and H increments side by side.  With every level at most N
-// cells, a neighbour's slot still holds it while fewer than N positions lie between it and
-// the far end of the current level (in the forward sweep q + N >= off + n, in the backward
-// one q < off + N, for the neighbour's position q and the current level's first position
-// off and size n).  The host marks such sides in the index row; the others are read from
-// d1.
+// cells, the slot of a neighbour on an earlier level (forward sweep) or a later one
+// (backward sweep) still holds it while fewer than N positions lie between it and the far
+// end of the current level (forward q + N >= off + n, backward q < off + N, for the
+// neighbour's position q and the current level's first position off and size n).  The
+// host marks such sides in the index row; the others are read from d1.
 template <class S>
 struct GsRing {
     static constexpr int N = gs_ring_positions(sizeof(S) == 4);
