@@ -67,6 +67,49 @@ def test_level_sweeps_match_hyperplane_sweeps(name, prec):
         assert abs(ra - rb) <= 1e3 * tol * abs(ra)
 
 
+# The level micro sweeps read a neighbour's increment from an LDS ring of the last 256
+# (FP32) or 128 (FP64) positions when every level fits it and the neighbour is close
+# enough, else from memory.  Levels of 200 (FP32) or 100 (FP64) cells: in the middle of
+# the mesh only part of the previous level is close enough, so one level reads both ways;
+# against the hyperplane sweeps.  Levels of 140 (FP64) or 260 (FP32) cells, larger than
+# the ring: every neighbour comes from memory; against the hyperplane sweeps, and (260^2,
+# too large for the hyperplane macro sweep) against the oracle at the FP32 step bar.
+RING = {"fp32_partial_window": (200, wl.FP32_MIXED), "fp64_partial_window": (100, wl.FP64),
+        "fp64_levels_above_ring": (140, wl.FP64)}
+
+
+def _ring_cfg(n, prec):
+    return dict(wl.cavity(n=n, stretch=None, nv=8, Kn=0.075, precision=prec),
+                sweep_order=wl.SWEEPS_LEVELS)
+
+
+@pytest.mark.parametrize("name", list(RING))
+def test_level_sweeps_ring_window_edges(name):
+    n, prec = RING[name]
+    cfg = _ring_cfg(n, prec)
+    a = _solver(dict(cfg, sweep_order=wl.SWEEPS_HYPERPLANES))
+    b = _solver(cfg)
+    f0 = _seeded(a.get_state(), 23, 0.05)
+    a.set_state(f0)
+    b.set_state(f0)
+    tol = 1e-13 if prec == wl.FP64 else 1e-6
+    for k in range(3):
+        ra, rb = a.step(wl.IMPLICIT, 1), b.step(wl.IMPLICIT, 1)
+        d = _rel_species(b.get_state(), a.get_state())
+        print(f"{name} step {k}: residuals {ra:.6e} {rb:.6e}, state difference {d:.2e}")
+        assert d <= tol
+        assert abs(ra - rb) <= 1e3 * tol * abs(ra)
+
+
+def test_level_sweeps_levels_above_ring_fp32_against_oracle():
+    o, g = _pair(_ring_cfg(260, wl.FP32_MIXED), seed=24, amp=0.05)
+    for k in range(2):
+        ro, rg = o.implicit_step(1), g.step(wl.IMPLICIT, 1)
+        d = _rel_species(g.get_state(), o.get_state())
+        print(f"260^2 FP32 step {k}: res {ro:.6e} / {rg:.6e}, state {d:.2e}")
+        assert d <= 2e-6
+
+
 # ------------------------------------------------------------ 2. hybrid meshes vs the oracle
 def _hyb_bgk():
     return wl.hybrid_cavity(n=16, nq=3, nv=12, jitter=0.15, seed=1, Kn=0.075)
