@@ -63,11 +63,17 @@ struct Rec {
     double rw;               // wall faces: density of the reflected Maxwellian
 };
 
-// Velocities per block of the flux kernel: all of them up to 4096, else chunks of 2048,
-// blocks ordered chunk by chunk, so that a cell's upwind neighbours are read while their
-// slice of the reconstruction is still in L2.  (The face-partial kernel takes all
-// velocities per block: its 4 x NM sums per block would cost more than the reuse saves.)
-inline int vel_chunk(int nv) { return nv <= 4096 ? nv : 2048; }
+// Velocities per block of the flux kernel: all of them up to 8192, else the fewest equal
+// chunks of at most 8192 (rounded up to a multiple of 64), blocks ordered chunk by chunk,
+// so that a cell's upwind neighbours are read while their slice of the reconstruction is
+// still in L2.  Each block first stages its four faces' records and factored Maxwellians,
+// which smaller chunks repeat more often (at 101^2 velocities two chunks beat 2048-wide
+// ones by a fifth).  (The face-partial kernel takes all velocities per block: its 4 x NM
+// sums per block would cost more than the reuse saves.)
+inline int vel_chunk(int nv) {
+    const int n = nv > 8192 ? (nv + 8191) / 8192 : 1;
+    return ((nv + n - 1) / n + 63) & ~63;
+}
 
 // Records in the state precision, per cell (current step) and per face: U, V, c0, c1, c2c,
 // c3, kqx, kqy, iRT, KRT, ab, bb, alpha, rw (two spare), read in the per-velocity loops

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 CASES = {
     "cavity_tanh": lambda: wl.cavity(n=24, nj=20, stretch=1.5, nv=12, Kn=0.075),
-    "cavity_shakhov_chunked": lambda: wl.cavity(n=6, stretch=None, nv=65, quad=wl.NEWTON_COTES,
+    "cavity_shakhov_chunked": lambda: wl.cavity(n=6, stretch=None, nv=91, quad=wl.NEWTON_COTES,
                                                 vmax=4.0, Kn=1.0, model=wl.SHAKHOV, Pr=2 / 3, K=1),
     "cylinder_limiter_fp32": lambda: wl.cylinder(ni=8, nj=12, rmax=6.0, nv=16, vmax=12.0, Kn=0.1,
                                                  precision=wl.FP32_MIXED),

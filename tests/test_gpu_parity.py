@@ -45,11 +45,11 @@ CASES = {
     "cylinder_limiter": lambda: wl.cylinder(ni=8, nj=12, rmax=6.0, nv=16, vmax=12.0, Kn=0.1,
                                             precision=wl.FP64),
     "periodic_box": lambda: wl.periodic_box(n=5, nv=8),
-    # 65^2 = 4225 velocities: the flux kernel splits them into chunks of 2048, 2048 and 129
-    # and combines the per-chunk macroscopic residuals
-    "cavity_shakhov_chunked": lambda: wl.cavity(n=6, stretch=None, nv=65, quad=wl.NEWTON_COTES,
+    # 91^2 = 8281 velocities: the flux kernel splits them into chunks of 4160 and 4121 and
+    # combines the per-chunk macroscopic residuals
+    "cavity_shakhov_chunked": lambda: wl.cavity(n=6, stretch=None, nv=91, quad=wl.NEWTON_COTES,
                                                 vmax=4.0, Kn=1.0, model=wl.SHAKHOV, Pr=2 / 3, K=1),
-    "cylinder_chunked": lambda: wl.cylinder(ni=6, nj=8, rmax=6.0, nv=65, vmax=12.0, Kn=0.1,
+    "cylinder_chunked": lambda: wl.cylinder(ni=6, nj=8, rmax=6.0, nv=91, vmax=12.0, Kn=0.1,
                                             precision=wl.FP64),
 }
 
@@ -231,11 +231,18 @@ def _local_errors(a, b):
 # FP64: the two sides differ in summation order and in the basis of the equilibrium
 # correction (central here, raw in the oracle, whose Gram matrix reaches a condition of
 # about 1e5 at Mach 5: 1e-16 x 1e5 = 1e-11).  Values below 1e-20 of the largest are sums
-# of neighbour terms many orders larger, so only the scaled checks cover them.
+# of neighbour terms many orders larger, so only the scaled checks cover them.  The wide
+# velocity set: 65^2 Newton-Cotes points on [-12, 12]^2 around the ramped cylinder.
+LOCAL_CASES = {
+    "cylinder_wide_ramp": lambda: dict(wl.cylinder(ni=6, nj=8, rmax=6.0, nv=65, vmax=12.0, Kn=0.1,
+                                                   precision=wl.FP64), cfl_start=0.5, cfl_growth=3.0),
+}
+
+
 @pytest.mark.parametrize("name", ["couette", "cavity_tanh", "cavity_shakhov_nc", "cylinder_limiter",
-                                  "cylinder_chunked_ramp"])
+                                  "cylinder_wide_ramp"])
 def test_step_parity_on_local_scales(name):
-    cfg = RAMP_CASES[name]() if name in RAMP_CASES else CASES[name]()
+    cfg = LOCAL_CASES[name]() if name in LOCAL_CASES else CASES[name]()
     o, g = _pair(cfg, seed=14, amp=0.02)
     for _ in range(2):
         o.implicit_step(1)
@@ -253,8 +260,8 @@ def test_full_size_fp32_step(name):
     """The two large workloads in their FP32-mixed benchmark form at full size: the 128^2
     cavity with 101^2 Newton-Cotes velocities (Shakhov, Kn = 10) and the 96 x 160 O-grid
     cylinder with 100^2 velocities (Shakhov, limiter, far field, Ma 5, first step of its
-    CFL ramp); about 1.6e8 cell-velocity pairs each, five velocity chunks of 2048 in the
-    flux, two velocities per sweep lane.  One implicit iteration from a seeded
+    CFL ramp); about 1.6e8 cell-velocity pairs each, two velocity chunks in the flux,
+    level-scheduled sweeps over 160 velocity slices.  One implicit iteration from a seeded
     perturbation against the FP64 oracle, to the FP32 bar of the small cases."""
     cfg = wl.case(name)
     assert cfg["precision"] == wl.FP32_MIXED

@@ -225,7 +225,7 @@ def test_hybrid_free_stream_is_kept():
 # ------------------------------------------------------------ 3. full size
 def test_hybrid_kn10_full_size_fp32_step():
     """The Kn 10 cavity (128^2 nodes, 101^2 Newton-Cotes velocities, Shakhov) on the
-    28928-cell hybrid mesh in its FP32-mixed form: about 3e8 cell-velocity pairs, five
+    28928-cell hybrid mesh in its FP32-mixed form: about 3e8 cell-velocity pairs, two
     velocity chunks in the flux, 160 velocity slices in the sweeps.  One implicit
     iteration from a seeded perturbation against the FP64 oracle."""
     cfg = wl.case("cavity_kn10_hybrid")
