@@ -747,9 +747,9 @@ idugks_status build(const idugks_config *c, Built &b) {
         }
     const idugks_status gs = um ? build_unstructured(c, b) : build_structured(c, b);
     if (gs != IDUGKS_OK) return gs;
-    // per position of the sweep order: the cell, and per side the neighbour cell, or
-    // -1 - t on a boundary side with boundary-condition slot t, or the cell itself (a side
-    // without flux)
+    // Per position of the sweep order the index row (GRow): the cell; per side the
+    // neighbour cell, or -1 - t on a boundary side with boundary-condition slot t, or the
+    // cell itself (a side without flux); the coupling masks; the neighbours' positions.
     // A coupled neighbour is read from the micro sweeps' LDS ring of RN positions when no
     // level exceeds RN cells, it lies on an earlier level (forward sweep) or a later one
     // (backward sweep) than the reading cell, and fewer than RN positions separate it from
@@ -759,13 +759,15 @@ idugks_status build(const idugks_config *c, Built &b) {
     b.grow.assign((size_t)GR_N * b.nc, 0);
     const int RN = gs_ring_positions(c->precision == IDUGKS_FP32_MIXED);
     int lev_max = 0;
-    for (int l = 0; l < b.nlev; ++l) lev_max = std::max(lev_max, b.hp_off[l + 1] - b.hp_off[l]);
-    for (int l = 0; l < b.nlev; ++l)
-        for (int pos = b.hp_off[l]; pos < b.hp_off[l + 1]; ++pos) b.grow[(size_t)GR_N * pos] = l;
+    std::vector<int> lev_of_pos(b.nc);
+    for (int l = 0; l < b.nlev; ++l) {
+        lev_max = std::max(lev_max, b.hp_off[l + 1] - b.hp_off[l]);
+        for (int pos = b.hp_off[l]; pos < b.hp_off[l + 1]; ++pos) lev_of_pos[pos] = l;
+    }
     for (int cidx = 0; cidx < b.nc; ++cidx) {
         const int pos = b.hp_pos[cidx];
         int *g = &b.grow[(size_t)GR_N * pos];
-        const int l = g[GR_CELL], lo = b.hp_off[l], hi = b.hp_off[l + 1];
+        const int l = lev_of_pos[pos], lo = b.hp_off[l], hi = b.hp_off[l + 1];
         g[GR_CELL] = cidx;
         int mask = 0;
         for (int sd = 0; sd < 4; ++sd) {

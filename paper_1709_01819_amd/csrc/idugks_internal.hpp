@@ -98,14 +98,18 @@ constexpr int HP_SPARE = 48;
 // the forward sweep to the adjacent hyperplane, i+ and j+ to the copy kept at a periodic
 // seam; the other way round in the backward sweep.
 enum SweepCode : int { SG_DIAG = 1, SG_LOWER = 2, SG_UPPER = 4 };
-// Row of a position in the level-scheduled sweeps: GR_CELL the cell; GR_MASK bit s (bit
-// 4 + s) set if side s couples in the forward (backward) sweep, bit 8 + s if side s is a
-// wall, bit 12 + s if the coupled neighbour of side s is read from the micro sweeps' LDS
-// ring, bit 16 if no cell reads this cell's backward-sweep increment from d1; GR_SRC + s where the micro sweeps find side s: the neighbour's position if bit
-// 12 + s is set, else its cell (or the code of GR_NB + s); GR_NB + s the neighbour code of
-// side s (its cell, -1 - t on a boundary side of boundary-condition slot t, the cell itself
-// on a side without flux); GR_NPOS + s the neighbour's position (the own position where
-// there is none).  The micro sweeps need only the first eight values.
+// Row of a position in the level-scheduled sweeps:
+//   GR_CELL      the cell;
+//   GR_MASK      bit s (bit 4 + s) set if side s couples in the forward (backward) sweep,
+//                bit 8 + s if side s is a wall, bit 12 + s if the coupled neighbour of
+//                side s is read from the micro sweeps' LDS ring, bit 16 if no cell reads
+//                this cell's backward-sweep increment from d1;
+//   GR_SRC + s   where the micro sweeps find side s: the neighbour's position if bit
+//                12 + s is set, else the value of GR_NB + s;
+//   GR_NB + s    the neighbour code of side s: its cell, -1 - t on a boundary side of
+//                boundary-condition slot t, the cell itself on a side without flux;
+//   GR_NPOS + s  the neighbour's position (the own position where there is none).
+// The micro sweeps need only the first eight values.
 enum GRow : int { GR_CELL = 0, GR_MASK = 1, GR_SRC = 2, GR_NB = 8, GR_NPOS = 12, GR_N = 16 };
 // Positions in the LDS ring of recent increments of the level-scheduled micro sweeps
 // (128 KiB per block in either precision).
